@@ -1,0 +1,512 @@
+/*
+ * FP64 CPU oracle for one IDIC ("implicit drag in cell") time step of
+ * two-fluid SPH (Stoyanovskaya, Glushko, Snytnikov & Snytnikov,
+ * arXiv:1908.01682).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU path is checked against.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no code, header
+ * or constant with the HIP library.
+ *
+ * State of one phase (gas: indices a,b; dust: indices j,k -- Section 2):
+ *   cell[i]            linear drag-cell index  cx + nx (cy + ny cz)
+ *   off[d*n + i]       offset of the particle inside its cell along axis d,
+ *                      0 <= off < Delta_d  (absolute x = lo + cx Delta + off)
+ *   vel[d*n + i]       velocity
+ *   mass[i], id[i], rho[i] (output), energy[i] (gas, adiabatic EOS only)
+ *
+ * Every sum over particles is evaluated serially per particle in a fixed
+ * canonical order: neighbour cells in lexicographic window order (z, then y,
+ * then x offsets), and inside a cell by (cell, id) order.  OpenMP only splits
+ * the outer loop, so results do not depend on the thread count.
+ *
+ * Readings of points the paper leaves open (all restated in the design notes):
+ *  - smoothing kernel: M4 cubic spline with support 2h (the paper's W(h, r),
+ *    Section 2.1, type not named);
+ *  - gas density: summation density over gas particles, self included;
+ *  - the explicit SPH terms of eq. (19) are applied before the cell solve
+ *    (unsplit first-order step, Section 2.3);
+ *  - cell means of eq. (21) are mass weighted, eps* = M_d / M_g (eq. 17 with
+ *    equal masses);
+ *  - a cell holding only one phase gets no drag this step (eq. 17 needs
+ *    N > 0 and L > 0);
+ *  - positions move with the new velocity, x^{n+1} = x^n + tau v^{n+1}.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int32_t dim;
+    int32_t nc[3];
+    double lo[3];
+    double hi[3];
+    double h;
+    int32_t eos;        /* 0: isothermal p = c_s^2 rho; 1: adiabatic p = (gamma-1) rho e */
+    double cs;
+    double gamma;
+    double tstop;
+    double g[3];
+    double dt;
+    double av_alpha;
+    double av_beta;
+} orc_params;
+
+typedef struct {
+    int64_t n;
+    int32_t *cell;
+    double *off;        /* [dim][n] */
+    double *vel;        /* [dim][n] */
+    double *mass;       /* [n] */
+    double *rho;        /* [n], written by the density sums (may be NULL for dust) */
+    double *energy;     /* [n] or NULL */
+    int32_t *id;        /* [n] */
+} orc_phase;
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Smoothing kernel W(h, r): M4 cubic spline, support 2h.                    */
+/* W = sigma_d h^-d f(q), q = r/h,                                           */
+/*   f = 1 - 3/2 q^2 + 3/4 q^3 (q < 1),  1/4 (2 - q)^3 (1 <= q < 2),  0.      */
+/* sigma_1 = 2/3, sigma_2 = 10/(7 pi), sigma_3 = 1/pi.                       */
+/* ------------------------------------------------------------------------ */
+static double orc_sigma(int dim)
+{
+    if (dim == 1) return 2.0 / 3.0;
+    if (dim == 2) return 10.0 / (7.0 * ORC_PI);
+    return 1.0 / ORC_PI;
+}
+
+double orc_kernel_w(int dim, double h, double r)
+{
+    double q = r / h;
+    double f;
+    if (q < 1.0) f = 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+    else if (q < 2.0) { double t = 2.0 - q; f = 0.25 * t * t * t; }
+    else f = 0.0;
+    return orc_sigma(dim) * f / pow(h, dim);
+}
+
+/* dW/dr */
+double orc_kernel_dw(int dim, double h, double r)
+{
+    double q = r / h;
+    double fp;
+    if (q < 1.0) fp = -3.0 * q + 2.25 * q * q;
+    else if (q < 2.0) { double t = 2.0 - q; fp = -0.75 * t * t; }
+    else fp = 0.0;
+    return orc_sigma(dim) * fp / pow(h, dim + 1);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry helpers                                                          */
+/* ------------------------------------------------------------------------ */
+static double orc_delta(const orc_params *p, int d) { return (p->hi[d] - p->lo[d]) / p->nc[d]; }
+
+static int64_t orc_ncells(const orc_params *p)
+{
+    int64_t n = 1;
+    for (int d = 0; d < p->dim; ++d) n *= p->nc[d];
+    return n;
+}
+
+static void orc_split(const orc_params *p, int32_t lin, int c[3])
+{
+    c[0] = c[1] = c[2] = 0;
+    c[0] = lin % p->nc[0];
+    if (p->dim > 1) c[1] = (lin / p->nc[0]) % p->nc[1];
+    if (p->dim > 2) c[2] = lin / (p->nc[0] * p->nc[1]);
+}
+
+static int32_t orc_join(const orc_params *p, const int c[3])
+{
+    int32_t lin = c[0];
+    if (p->dim > 1) lin += p->nc[0] * c[1];
+    if (p->dim > 2) lin += p->nc[0] * p->nc[1] * c[2];
+    return lin;
+}
+
+static int orc_wrapi(int c, int n) { c %= n; return c < 0 ? c + n : c; }
+
+/* neighbour-window half width in cells along axis d: every particle within 2h
+ * of a particle lies in a cell at most W cells away. */
+static int orc_window(const orc_params *p, int d)
+{
+    if (d >= p->dim) return 0;
+    return (int)ceil(2.0 * p->h / orc_delta(p, d) - 1e-12);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Binning (Section 2.3: "at each time instant" the region is split into    */
+/* disjoint volumes).  Volumes = uniform periodic Cartesian cells.  A       */
+/* position exactly on a face belongs to the upper cell.  The carry rule     */
+/* below is floor((x - lo) / Delta) written for the (cell, offset) form.     */
+/* ------------------------------------------------------------------------ */
+void orc_canonicalize(const orc_params *p, orc_phase *ph)
+{
+    const int64_t n = ph->n;
+    for (int64_t i = 0; i < n; ++i) {
+        int c[3];
+        orc_split(p, ph->cell[i], c);
+        for (int d = 0; d < p->dim; ++d) {
+            double D = orc_delta(p, d);
+            double o = ph->off[d * n + i];
+            while (o < 0.0) { o += D; c[d] -= 1; }
+            while (o >= D) { o -= D; c[d] += 1; }
+            c[d] = orc_wrapi(c[d], p->nc[d]);
+            ph->off[d * n + i] = o;
+        }
+        ph->cell[i] = orc_join(p, c);
+    }
+}
+
+/* (cell, id) lexicographic order */
+static const orc_phase *orc_sort_ph;
+static int orc_cmp(const void *A, const void *B)
+{
+    int64_t a = *(const int64_t *)A, b = *(const int64_t *)B;
+    int32_t ca = orc_sort_ph->cell[a], cb = orc_sort_ph->cell[b];
+    if (ca != cb) return ca < cb ? -1 : 1;
+    int32_t ia = orc_sort_ph->id[a], ib = orc_sort_ph->id[b];
+    return (ia > ib) - (ia < ib);
+}
+
+static void orc_permute_d(double *x, const int64_t *perm, int64_t n, double *tmp)
+{
+    for (int64_t i = 0; i < n; ++i) tmp[i] = x[perm[i]];
+    memcpy(x, tmp, sizeof(double) * n);
+}
+
+static void orc_permute_i(int32_t *x, const int64_t *perm, int64_t n, int32_t *tmp)
+{
+    for (int64_t i = 0; i < n; ++i) tmp[i] = x[perm[i]];
+    memcpy(x, tmp, sizeof(int32_t) * n);
+}
+
+/* Reorder all arrays of a phase into (cell, id) order.  Not thread safe
+ * (qsort comparator uses a file-scope pointer); called from serial code. */
+void orc_sort(const orc_params *p, orc_phase *ph)
+{
+    const int64_t n = ph->n;
+    if (n == 0) return;
+    int64_t *perm = (int64_t *)malloc(sizeof(int64_t) * n);
+    double *tmp = (double *)malloc(sizeof(double) * n);
+    int32_t *tmpi = (int32_t *)malloc(sizeof(int32_t) * n);
+    for (int64_t i = 0; i < n; ++i) perm[i] = i;
+    orc_sort_ph = ph;
+    qsort(perm, (size_t)n, sizeof(int64_t), orc_cmp);
+    orc_sort_ph = NULL;
+    for (int d = 0; d < p->dim; ++d) {
+        orc_permute_d(ph->off + d * n, perm, n, tmp);
+        orc_permute_d(ph->vel + d * n, perm, n, tmp);
+    }
+    orc_permute_d(ph->mass, perm, n, tmp);
+    if (ph->rho) orc_permute_d(ph->rho, perm, n, tmp);
+    if (ph->energy) orc_permute_d(ph->energy, perm, n, tmp);
+    orc_permute_i(ph->cell, perm, n, tmpi);
+    orc_permute_i(ph->id, perm, n, tmpi);
+    free(perm); free(tmp); free(tmpi);
+}
+
+/* start[c] = first sorted index of cell c, start[ncells] = n */
+void orc_cell_start(const orc_params *p, const orc_phase *ph, int64_t *start)
+{
+    int64_t nc = orc_ncells(p);
+    for (int64_t c = 0; c <= nc; ++c) start[c] = 0;
+    for (int64_t i = 0; i < ph->n; ++i) start[ph->cell[i] + 1] += 1;
+    for (int64_t c = 0; c < nc; ++c) start[c + 1] += start[c];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbour iteration.  For particle a in cell ca, visit every cell in the  */
+/* window and every particle b in it; r_ab = x_a - x_b with the periodic     */
+/* image of b that lies in the window.                                       */
+/* ------------------------------------------------------------------------ */
+typedef void (*orc_pair_fn)(void *ctx, int64_t a, int64_t b, const double r[3]);
+
+static void orc_for_neighbours(const orc_params *p, const orc_phase *A, int64_t a,
+                               const orc_phase *B, const int64_t *startB,
+                               orc_pair_fn fn, void *ctx)
+{
+    int ca[3];
+    orc_split(p, A->cell[a], ca);
+    int W[3] = {orc_window(p, 0), orc_window(p, 1), orc_window(p, 2)};
+    double D[3] = {orc_delta(p, 0), p->dim > 1 ? orc_delta(p, 1) : 0.0, p->dim > 2 ? orc_delta(p, 2) : 0.0};
+    const int64_t na = A->n, nb = B->n;
+    for (int dz = -W[2]; dz <= W[2]; ++dz)
+        for (int dy = -W[1]; dy <= W[1]; ++dy)
+            for (int dx = -W[0]; dx <= W[0]; ++dx) {
+                int cb[3] = {orc_wrapi(ca[0] + dx, p->nc[0]), orc_wrapi(ca[1] + dy, p->nc[1]),
+                             orc_wrapi(ca[2] + dz, p->nc[2])};
+                int32_t lin = orc_join(p, cb);
+                int dd[3] = {dx, dy, dz};
+                for (int64_t b = startB[lin]; b < startB[lin + 1]; ++b) {
+                    double r[3] = {0.0, 0.0, 0.0};
+                    for (int d = 0; d < p->dim; ++d)
+                        r[d] = A->off[d * na + a] - (B->off[d * nb + b] + dd[d] * D[d]);
+                    fn(ctx, a, b, r);
+                }
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* SPH summation density  rho_a = sum_b m_b W(|r_ab|, h)   (self included).  */
+/* The paper uses rho^n_{a,g} in eqs. (8), (12), (19) without writing it.   */
+/* ------------------------------------------------------------------------ */
+typedef struct { const orc_params *p; const orc_phase *B; double acc; } orc_dens_ctx;
+
+static void orc_dens_pair(void *vctx, int64_t a, int64_t b, const double r[3])
+{
+    (void)a;
+    orc_dens_ctx *c = (orc_dens_ctx *)vctx;
+    double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (rr < 2.0 * c->p->h) c->acc += c->B->mass[b] * orc_kernel_w(c->p->dim, c->p->h, rr);
+}
+
+/* ph must be in (cell, id) order with matching start[] */
+void orc_density(const orc_params *p, const orc_phase *ph, const int64_t *start, double *rho_out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < ph->n; ++a) {
+        orc_dens_ctx c = {p, ph, 0.0};
+        orc_for_neighbours(p, ph, a, ph, start, orc_dens_pair, &c);
+        rho_out[a] = c.acc;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Equation of state.  Isothermal gas (Section 3: "isothermal gas-dust       */
+/* mixture") p = c_s^2 rho; the shock tube uses an ideal gas p=(g-1) rho e.  */
+/* ------------------------------------------------------------------------ */
+static double orc_pressure(const orc_params *p, double rho, double e)
+{
+    return p->eos == 0 ? p->cs * p->cs * rho : (p->gamma - 1.0) * rho * e;
+}
+
+static double orc_sound(const orc_params *p, double rho, double e)
+{
+    if (p->eos == 0) return p->cs;
+    (void)rho;
+    return sqrt(p->gamma * (p->gamma - 1.0) * e);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Explicit gas terms of eq. (19):                                           */
+/*   A_a = - sum_b m_b (p_a/rho_a^2 + p_b/rho_b^2 + Pi_ab) grad_a W_ab + g    */
+/* and, for the adiabatic EOS, the SPH internal-energy equation              */
+/*   de_a/dt = sum_b m_b (p_a/rho_a^2 + Pi_ab/2) v_ab . grad_a W_ab.          */
+/* Pi_ab is the Monaghan-Gingold artificial viscosity (zero when alpha =     */
+/* beta = 0, which is every isothermal case).                                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const orc_params *p; const orc_phase *G; const double *pres; const double *snd;
+    double acc[3]; double dedt;
+} orc_force_ctx;
+
+static void orc_force_pair(void *vctx, int64_t a, int64_t b, const double r[3])
+{
+    orc_force_ctx *c = (orc_force_ctx *)vctx;
+    const orc_params *p = c->p;
+    const orc_phase *G = c->G;
+    if (a == b) return;
+    double rr2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double rr = sqrt(rr2);
+    if (!(rr < 2.0 * p->h) || rr == 0.0) return;
+    const int64_t n = G->n;
+    double dw = orc_kernel_dw(p->dim, p->h, rr);
+    double grad[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < p->dim; ++d) grad[d] = dw * r[d] / rr;
+    double rhoa = G->rho[a], rhob = G->rho[b];
+    double Pa = c->pres[a] / (rhoa * rhoa), Pb = c->pres[b] / (rhob * rhob);
+    double vr = 0.0, vg = 0.0;
+    for (int d = 0; d < p->dim; ++d) {
+        double vab = G->vel[d * n + a] - G->vel[d * n + b];
+        vr += vab * r[d];
+        vg += vab * grad[d];
+    }
+    double Pi = 0.0;
+    if ((p->av_alpha != 0.0 || p->av_beta != 0.0) && vr < 0.0) {
+        double mu = p->h * vr / (rr2 + 0.01 * p->h * p->h);
+        double cbar = 0.5 * (c->snd[a] + c->snd[b]);
+        double rbar = 0.5 * (rhoa + rhob);
+        Pi = (-p->av_alpha * cbar * mu + p->av_beta * mu * mu) / rbar;
+    }
+    double mb = G->mass[b];
+    for (int d = 0; d < p->dim; ++d) c->acc[d] -= mb * (Pa + Pb + Pi) * grad[d];
+    c->dedt += mb * (Pa + 0.5 * Pi) * vg;
+}
+
+void orc_gas_forces(const orc_params *p, const orc_phase *G, const int64_t *start,
+                    double *acc_out /* [dim][n] */, double *dedt_out /* [n] or NULL */)
+{
+    const int64_t n = G->n;
+    double *pres = (double *)malloc(sizeof(double) * (n ? n : 1));
+    double *snd = (double *)malloc(sizeof(double) * (n ? n : 1));
+    for (int64_t a = 0; a < n; ++a) {
+        double e = G->energy ? G->energy[a] : 0.0;
+        pres[a] = orc_pressure(p, G->rho[a], e);
+        snd[a] = orc_sound(p, G->rho[a], e);
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < n; ++a) {
+        orc_force_ctx c = {p, G, pres, snd, {0.0, 0.0, 0.0}, 0.0};
+        orc_for_neighbours(p, G, a, G, start, orc_force_pair, &c);
+        for (int d = 0; d < p->dim; ++d) acc_out[d * n + a] = c.acc[d] + p->g[d];
+        if (dedt_out) dedt_out[a] = c.dedt;
+    }
+    free(pres); free(snd);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One IDIC step n -> n+1 (Section 2.3, eqs. 17-21), both phases sorted on   */
+/* entry and exit.  Returns the number of cells that held one phase only.    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double Mg, Md, Pg[3], Pd[3];
+    double alpha, beta, V[3], U[3];
+    int64_t N, L;
+} orc_cell;
+
+int64_t orc_step(const orc_params *p, orc_phase *G, orc_phase *Dd, int32_t nsteps,
+                 double *cell_diag /* optional [ncells][2+2*dim]: alpha, beta, V*, U* of the last step */)
+{
+    const int dim = p->dim;
+    const int64_t nc = orc_ncells(p);
+    const int64_t ng = G->n, nd = Dd->n;
+    const double tau = p->dt;
+    int64_t *sg = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+    int64_t *sd = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+    double *acc = (double *)malloc(sizeof(double) * (dim * ng + 1));
+    double *dedt = (double *)malloc(sizeof(double) * (ng + 1));
+    orc_cell *cells = (orc_cell *)malloc(sizeof(orc_cell) * nc);
+    int64_t empty_total = 0;
+
+    for (int32_t s = 0; s < nsteps; ++s) {
+        /* volumes at level n */
+        orc_canonicalize(p, G);
+        orc_canonicalize(p, Dd);
+        orc_sort(p, G);
+        orc_sort(p, Dd);
+        orc_cell_start(p, G, sg);
+        orc_cell_start(p, Dd, sd);
+
+        /* explicit SPH terms at level n */
+        orc_density(p, G, sg, G->rho);
+        orc_gas_forces(p, G, sg, acc, G->energy ? dedt : NULL);
+
+        /* predictor: v~ = v + tau A, u~ = u + tau g, e += tau de/dt */
+        for (int d = 0; d < dim; ++d) {
+            for (int64_t a = 0; a < ng; ++a) G->vel[d * ng + a] += tau * acc[d * ng + a];
+            for (int64_t j = 0; j < nd; ++j) Dd->vel[d * nd + j] += tau * p->g[d];
+        }
+        if (G->energy)
+            for (int64_t a = 0; a < ng; ++a) G->energy[a] += tau * dedt[a];
+
+        /* eq. (17), (21): per-volume masses and momenta, canonical order */
+        int64_t empty = 0;
+#pragma omp parallel for schedule(static) reduction(+ : empty)
+        for (int64_t c = 0; c < nc; ++c) {
+            orc_cell *C = &cells[c];
+            memset(C, 0, sizeof(*C));
+            C->N = sg[c + 1] - sg[c];
+            C->L = sd[c + 1] - sd[c];
+            for (int64_t a = sg[c]; a < sg[c + 1]; ++a) {
+                C->Mg += G->mass[a];
+                for (int d = 0; d < dim; ++d) C->Pg[d] += G->mass[a] * G->vel[d * ng + a];
+            }
+            for (int64_t j = sd[c]; j < sd[c + 1]; ++j) {
+                C->Md += Dd->mass[j];
+                for (int d = 0; d < dim; ++d) C->Pd[d] += Dd->mass[j] * Dd->vel[d * nd + j];
+            }
+            if (C->N > 0 && C->L > 0) {
+                /* eq. (17)-(18): eps = M_d / M_g; K over the cell gas density is eps / t_stop,
+                 * K over the cell dust density is 1 / t_stop */
+                double eps = C->Md / C->Mg;
+                C->beta = tau / p->tstop;
+                C->alpha = eps * C->beta;
+                double Dt = 1.0 + C->alpha + C->beta;
+                for (int d = 0; d < dim; ++d) {
+                    double Vt = C->Pg[d] / C->Mg, Ut = C->Pd[d] / C->Md;
+                    /* cell means at n+1 solve (1+alpha)V - alpha U = V~, -beta V + (1+beta) U = U~ */
+                    C->V[d] = ((1.0 + C->beta) * Vt + C->alpha * Ut) / Dt;
+                    C->U[d] = (C->beta * Vt + (1.0 + C->alpha) * Ut) / Dt;
+                }
+            } else {
+                C->alpha = C->beta = 0.0;
+                if (C->N > 0 || C->L > 0) empty += 1;
+            }
+        }
+        empty_total += empty;
+
+        /* eq. (19)-(20) with the other phase's velocity uniform over the volume */
+        for (int64_t c = 0; c < nc; ++c) {
+            const orc_cell *C = &cells[c];
+            for (int64_t a = sg[c]; a < sg[c + 1]; ++a)
+                for (int d = 0; d < dim; ++d)
+                    G->vel[d * ng + a] = (G->vel[d * ng + a] + C->alpha * C->U[d]) / (1.0 + C->alpha);
+            for (int64_t j = sd[c]; j < sd[c + 1]; ++j)
+                for (int d = 0; d < dim; ++d)
+                    Dd->vel[d * nd + j] = (Dd->vel[d * nd + j] + C->beta * C->V[d]) / (1.0 + C->beta);
+        }
+        if (cell_diag && s == nsteps - 1) {
+            int w = 2 + 2 * dim;
+            for (int64_t c = 0; c < nc; ++c) {
+                cell_diag[c * w + 0] = cells[c].alpha;
+                cell_diag[c * w + 1] = cells[c].beta;
+                for (int d = 0; d < dim; ++d) {
+                    cell_diag[c * w + 2 + d] = cells[c].V[d];
+                    cell_diag[c * w + 2 + dim + d] = cells[c].U[d];
+                }
+            }
+        }
+
+        /* positions: x^{n+1} = x^n + tau v^{n+1}, then back into [0, Delta) */
+        for (int d = 0; d < dim; ++d) {
+            for (int64_t a = 0; a < ng; ++a) G->off[d * ng + a] += tau * G->vel[d * ng + a];
+            for (int64_t j = 0; j < nd; ++j) Dd->off[d * nd + j] += tau * Dd->vel[d * nd + j];
+        }
+        orc_canonicalize(p, G);
+        orc_canonicalize(p, Dd);
+    }
+    free(sg); free(sd); free(acc); free(dedt); free(cells);
+    return empty_total;
+}
+
+/* Density sums on the phase's current positions (sorts the phase first). */
+void orc_phase_density(const orc_params *p, orc_phase *ph, double *rho_out)
+{
+    int64_t nc = orc_ncells(p);
+    int64_t *st = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+    orc_canonicalize(p, ph);
+    orc_sort(p, ph);
+    orc_cell_start(p, ph, st);
+    orc_density(p, ph, st, rho_out);
+    free(st);
+}
+
+/* Gas forces on the current positions (sorts the phase, fills rho). */
+void orc_phase_forces(const orc_params *p, orc_phase *G, double *acc_out, double *dedt_out)
+{
+    int64_t nc = orc_ncells(p);
+    int64_t *st = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+    orc_canonicalize(p, G);
+    orc_sort(p, G);
+    orc_cell_start(p, G, st);
+    orc_density(p, G, st, G->rho);
+    orc_gas_forces(p, G, st, acc_out, dedt_out);
+    free(st);
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
