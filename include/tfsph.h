@@ -1,0 +1,198 @@
+/*
+ * tfsph.h -- C ABI of the MI355X (gfx950) two-fluid SPH library with
+ * implicit drag-in-cell (IDIC) coupling.
+ *
+ * Method: Stoyanovskaya, Glushko, Snytnikov & Snytnikov, "Monodisperse
+ * gas-solid mixtures with intense interphase interaction in Two-Fluid
+ * Smoothed Particle Hydrodynamics" (arXiv:1908.01682).  Gas particles carry
+ * the continuity/momentum equations (1) and dust particles (2), coupled by
+ * the drag (3) in the K-form (7).  The drag is evaluated per volume ("cell"):
+ * Section 2.3, eqs. (17)-(21).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every pointer inside tfsph_state / tfsph_phase and every workspace
+ *    pointer is DEVICE memory owned by the caller.  The library never
+ *    allocates device memory on the step paths; it writes only into the
+ *    arrays and the workspace it is given.
+ *  - Real arrays are float (TFSPH_F32) or double (TFSPH_F64), as chosen by
+ *    tfsph_params.precision; void* is used so one ABI serves both.
+ *  - Positions are stored in cell-relative form: a linear cell index
+ *    cell = cx + nx (cy + ny cz) and per-axis offsets 0 <= off < Delta_d
+ *    with Delta_d = (box_hi[d] - box_lo[d]) / n_cells[d].  The absolute
+ *    position is box_lo + (cx, cy, cz) Delta + off.  The box is periodic.
+ *  - Calls are asynchronous on the given HIP stream (hipStream_t passed as
+ *    void*, NULL = default stream).  Host-detectable argument errors are
+ *    returned synchronously before anything is enqueued; numerical trouble
+ *    is recorded in sticky device flags read with tfsph_get_flags().
+ *  - Nothing throws across the ABI.  A failing call returns a negative
+ *    tfsph_status and leaves a message for tfsph_last_error() (thread local).
+ *  - Calls that share a context, a state or a workspace must not overlap in
+ *    time on different streams.
+ */
+#ifndef TFSPH_H
+#define TFSPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TFSPH_OK = 0,
+    TFSPH_E_INVALID_ARG = -1,   /* bad parameter or pointer; nothing enqueued */
+    TFSPH_E_WORKSPACE = -2,     /* workspace missing, too small or misaligned */
+    TFSPH_E_HIP = -3,           /* a HIP runtime call failed (message has the HIP error) */
+    TFSPH_E_UNSUPPORTED = -4,   /* valid request outside what this build implements */
+    TFSPH_E_STATE = -5          /* context/state mismatch (sizes differ from init) */
+} tfsph_status;
+
+/* sticky device flags (bit mask) */
+enum {
+    TFSPH_FLAG_NONFINITE = 1u,         /* a velocity, offset or density became NaN/Inf */
+    TFSPH_FLAG_EMPTY_PHASE_CELL = 2u,  /* some cell held particles of one phase only */
+    TFSPH_FLAG_BAD_CELL = 4u,          /* a state cell index was out of range (treated as cell 0) */
+    TFSPH_FLAG_CELL_OVERFLOW = 8u      /* a cell held more than 4096 particles of one phase: its
+                                          in-cell order fell back to arrival order (not reproducible) */
+};
+
+enum { TFSPH_F32 = 0, TFSPH_F64 = 1 };
+enum { TFSPH_ISOTHERMAL = 0, TFSPH_ADIABATIC = 1 };
+
+/* Run parameters; symbols follow the paper. */
+typedef struct {
+    int32_t dim;            /* 1, 2 or 3 */
+    int32_t n_cells[3];     /* drag volumes per axis (Section 2.3); axes >= dim must be 1 */
+    double box_lo[3];       /* periodic box [box_lo, box_hi) */
+    double box_hi[3];
+    double h;               /* smoothing length of W(h, r) (Section 2.1); kernel support 2h */
+    int32_t eos;            /* TFSPH_ISOTHERMAL: p = c_s^2 rho; TFSPH_ADIABATIC: p = (gamma-1) rho e */
+    double c_s;             /* isothermal sound speed */
+    double gamma;           /* adiabatic index (adiabatic EOS only) */
+    double t_stop;          /* velocity relaxation time of eq. (3); K = rho_d / t_stop (eq. 7) */
+    double g[3];            /* gravity acceleration of eqs. (1)-(2) */
+    double dt;              /* time step tau (eq. 4 bounds it; tau > t_stop is allowed) */
+    double av_alpha;        /* artificial viscosity alpha, beta (0, 0 = off) */
+    double av_beta;
+    int32_t precision;      /* TFSPH_F32 or TFSPH_F64 for every real array */
+} tfsph_params;
+
+/* One particle phase (gas: indices a, b; dust: j, k in the paper's notation).
+ * Every array has n entries; off[d], vel[d] for d < dim. */
+typedef struct {
+    int64_t n;
+    int32_t *cell;          /* linear cell index (in/out) */
+    void *off[3];           /* offsets inside the cell, 0 <= off < Delta (in/out) */
+    void *vel[3];           /* velocity: v for gas, u for dust (in/out) */
+    void *mass;             /* per-particle mass, or NULL to use mass_uniform (in/out: reordered) */
+    double mass_uniform;
+    void *rho;              /* summation density at the start of the last step (out);
+                               required for gas, may be NULL for dust */
+    void *energy;           /* specific internal energy, gas with adiabatic EOS only (in/out) */
+    int32_t *id;            /* particle ids, unique within the phase (in, travel with the particle) */
+} tfsph_phase;
+
+typedef struct {
+    tfsph_phase gas;
+    tfsph_phase dust;
+} tfsph_state;
+
+typedef struct tfsph_ctx tfsph_ctx;   /* opaque; host memory only */
+
+/* Human-readable name of a status code (static string). */
+const char *tfsph_status_string(tfsph_status s);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *tfsph_last_error(void);
+
+/* Host-only check of a parameter set (no device call).  Fails with
+ * TFSPH_E_INVALID_ARG when: dim not in 1..3; a cell count < 1 or, on an
+ * axis >= dim, != 1; box_hi <= box_lo; h <= 0; an axis with fewer than
+ * 2W+1 cells where W = ceil(2h / Delta) is the neighbour window; W > 8;
+ * t_stop <= 0 or dt <= 0 or non-finite; isothermal with c_s <= 0; adiabatic
+ * with gamma <= 1; negative viscosity coefficients; unknown eos/precision;
+ * more than 2^31-1 cells. */
+tfsph_status tfsph_validate(const tfsph_params *p);
+
+/* Host-only: bytes of device workspace tfsph_init() needs for n_gas, n_dust
+ * particles (each 0 .. 2^31-1).  The workspace must be 256-byte aligned. */
+tfsph_status tfsph_workspace_size(const tfsph_params *p, int64_t n_gas, int64_t n_dust, size_t *bytes);
+
+/* Create a context for one simulation and bring the state into canonical
+ * form on the device: every offset is carried into [0, Delta) (the cell
+ * index moves accordingly, periodic wrap), and both phases are reordered in
+ * place into (cell, id) lexicographic order.  The workspace (device,
+ * caller-owned, at least tfsph_workspace_size() bytes) is used by every later
+ * call on this context and must stay allocated until tfsph_destroy().
+ * Errors: TFSPH_E_INVALID_ARG (params, NULL arrays, n mismatch with mass/
+ * energy requirements), TFSPH_E_WORKSPACE, TFSPH_E_HIP. */
+tfsph_status tfsph_init(tfsph_ctx **out, const tfsph_params *p, tfsph_state *s, void *workspace,
+                        size_t ws_bytes, void *hip_stream);
+
+/* Advance the state n_steps IDIC time steps (Section 2.3), in place.  One
+ * step n -> n+1:
+ *   (a) bin both phases into the volumes at level n (counting sort, order
+ *       (cell, id), deterministic);
+ *   (b) gas summation density rho_a = sum_b m_b W(|r_ab|, h) and pressure;
+ *   (c) explicit terms of eq. (19): v~_a = v_a + tau (-sum_b m_b (p_a/rho_a^2
+ *       + p_b/rho_b^2 + Pi_ab) grad_a W_ab + g), e_a += tau de_a/dt for the
+ *       adiabatic EOS; u~_j = u_j + tau g (eq. 20);
+ *   (d) per cell: M_g, M_d and the momenta of v~, u~ (eqs. 17, 21), the
+ *       implicit solve of eqs. (19)-(21) for the new cell means
+ *       (eps = M_d/M_g, alpha = eps tau/t_stop, beta = tau/t_stop),
+ *       then v_a = (v~_a + alpha U*)/(1+alpha), u_j = (u~_j + beta V*)/(1+beta);
+ *       cells with one phase only get no drag;
+ *   (e) x += tau v_new, offsets carried back into [0, Delta).
+ * On return the arrays hold level n+N, ordered by the cells of the last
+ * step's start; rho holds the gas density used by that step.  Sums are
+ * evaluated in a fixed order: results are bitwise reproducible.
+ * Errors: TFSPH_E_INVALID_ARG (n_steps < 0), TFSPH_E_STATE (n differ from
+ * init), TFSPH_E_HIP. */
+tfsph_status tfsph_step(tfsph_ctx *ctx, tfsph_state *s, int32_t n_steps, void *hip_stream);
+
+/* Summation density of one phase over itself at the current positions,
+ * written to that phase's rho array (phase 0 = gas, 1 = dust; dust density
+ * is a diagnostic, the gas density of a step is computed by tfsph_step).
+ * Reorders the phase into canonical (cell, id) order first. */
+tfsph_status tfsph_density(tfsph_ctx *ctx, tfsph_state *s, int32_t phase, void *hip_stream);
+
+/* Read and clear the sticky flags and the count of one-phase cells seen
+ * since the last call.  Synchronises the context's last stream. */
+tfsph_status tfsph_get_flags(tfsph_ctx *ctx, uint32_t *flags, int64_t *one_phase_cells);
+
+/* Kernel timing for measurement.  tfsph_profile(ctx, 1) starts recording a
+ * HIP event pair around every launch of the timed kernels on the stream the
+ * launch uses (it creates the events on the host; nothing is allocated on the
+ * device); tfsph_profile(ctx, 0) stops and keeps what was recorded.
+ * tfsph_profile_read() synchronises, then returns the summed duration in ms
+ * and the number of launches of one kernel:
+ *   TFSPH_KERNEL_UPDATE  (force + predictor + cell solve + particle update),
+ *   TFSPH_KERNEL_DENSITY (gas summation density),
+ *   TFSPH_KERNEL_BIN     (count + scan + scatter + rank/gather, as one span). */
+enum { TFSPH_KERNEL_UPDATE = 0, TFSPH_KERNEL_DENSITY = 1, TFSPH_KERNEL_BIN = 2 };
+tfsph_status tfsph_profile(tfsph_ctx *ctx, int32_t enable);
+tfsph_status tfsph_profile_read(tfsph_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
+
+/* Convert n absolute FP64 positions x (device, layout [dim][n], inside or
+ * outside the box) to the cell-relative form: cell = floor((x - box_lo)/Delta)
+ * evaluated in FP64 (periodic wrap), off = (x - box_lo) - cell Delta rounded
+ * to the state precision and carried into [0, Delta).  cell, off[d] are
+ * device arrays of n entries.  Host-checked arguments; async on the stream. */
+tfsph_status tfsph_positions_to_cells(const tfsph_params *p, int64_t n, const double *x, int32_t *cell, void *off[3],
+                                      void *hip_stream);
+
+/* Inverse conversion: x[d*n + i] = box_lo[d] + c_d Delta_d + off[d][i] in FP64
+ * (device arrays). */
+tfsph_status tfsph_cells_to_positions(const tfsph_params *p, int64_t n, const int32_t *cell, void *const off[3],
+                                      double *x, void *hip_stream);
+
+/* Release the context (host memory only; the workspace stays the caller's). */
+tfsph_status tfsph_destroy(tfsph_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFSPH_H */

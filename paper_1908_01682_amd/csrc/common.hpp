@@ -1,0 +1,185 @@
+// Device-side building blocks shared by every TFSPH kernel (gfx950, wave64).
+//
+// Position representation: linear cell index + per-axis offset inside the
+// cell, 0 <= off < Delta.  Pair separations are formed as
+// (off_a - d Delta) - off_b where d is the window offset of b's cell, so no
+// absolute coordinate (and no periodic wrap of a coordinate) is ever formed;
+// FP32 keeps ~1e-7 of a cell width of resolution anywhere in the box.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tfsph {
+
+constexpr int kBlock = 256;          // threads per block of the streaming kernels
+constexpr int kMaxWindow = 8;        // largest neighbour window half-width (cells)
+
+// --------------------------------------------------------------------------
+// Smoothing kernel W(h, r) of Section 2.1: M4 cubic spline, support 2h.
+// f(q) = 1 - 1.5 q^2 + 0.75 q^3 on [0,1), 0.25 (2-q)^3 on [1,2), 0 beyond;
+// W = sigma_d h^-d f(r/h).  The device code evaluates f and f' branch-free.
+// --------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R spline_f(R q)
+{
+    const R t = R(2) - q;
+    const R inner = R(1) + q * q * (R(0.75) * q - R(1.5));
+    const R outer = R(0.25) * t * t * t;
+    return q < R(1) ? inner : (q < R(2) ? outer : R(0));
+}
+
+template <typename R>
+__device__ __forceinline__ R spline_df(R q)
+{
+    const R t = R(2) - q;
+    const R inner = q * (R(2.25) * q - R(3));
+    const R outer = R(-0.75) * t * t;
+    return q < R(1) ? inner : (q < R(2) ? outer : R(0));
+}
+
+// Grid + kernel geometry of one problem (uniform periodic cells, Section 2.3).
+template <typename R>
+struct Geom {
+    int dim;
+    int nc[3];
+    int ncell;
+    int win[3];          // neighbour window half width per axis
+    R delta[3];          // cell width per axis
+    R h, inv_h;
+    R support2;          // (2h)^2
+    R wnorm;             // sigma_d / h^d
+    R gnorm;             // sigma_d / h^(d+1)
+};
+
+// Physics of the step: EOS, drag, time step, viscosity.
+template <typename R>
+struct Phys {
+    int eos;             // 0 isothermal, 1 adiabatic
+    int av;              // artificial viscosity on
+    R cs;                // isothermal sound speed
+    R cs2;
+    R gm1;               // gamma - 1
+    R ggm1;              // gamma (gamma - 1): c^2 = ggm1 * e
+    R tau;               // time step
+    R beta;              // tau / t_stop
+    R g[3];
+    R av_alpha, av_beta;
+    R eta2;              // 0.01 h^2 in the viscosity denominator
+    R h;
+};
+
+// Caller-owned arrays of one phase.
+template <typename R>
+struct Phase {
+    int n;
+    int *cell;
+    R *off[3];
+    R *vel[3];
+    const R *mass;       // nullable: uniform mass m_uniform
+    R m_uniform;
+    R *rho;              // nullable for dust
+    R *energy;           // nullable
+    int *id;
+};
+
+// Workspace arrays of one phase: the step's canonical (cell, id) ordered copy
+// plus binning scratch.
+template <typename R>
+struct Sorted {
+    int n;
+    int *cell;
+    R *off[3];
+    R *vel[3];
+    R *mass;             // nullable
+    R m_uniform;
+    R *energy;           // nullable
+    int *id;
+    R *rho;              // summation density
+    R *prs;              // p / rho^2 (gas)
+    R *vt[3];            // predictor velocity v~ (gas)
+    int *count;          // [ncell] histogram
+    int *start;          // [ncell + 1] exclusive offsets
+    int *slot;           // [n] slot claimed inside the cell during counting
+    int *tmp_idx;        // [n] unsorted-within-cell scatter of source indices
+    int *tmp_id;         // [n] ids in the same layout
+};
+
+struct Flags {
+    unsigned int *word;                 // sticky TFSPH_FLAG_* bits
+    unsigned long long *one_phase;      // count of one-phase cells
+};
+
+// A cell index read from caller memory; anything out of range is treated as
+// cell 0 (and reported by the kernels that read it) so no access leaves the
+// cell arrays.
+__device__ __forceinline__ int safe_cell(int c, int ncell)
+{
+    return (c >= 0 && c < ncell) ? c : 0;
+}
+
+constexpr int kMaxRankCell = 1 << 12;    // cells above this size are ordered by slot, and flagged
+
+__device__ __forceinline__ int wrap_index(int c, int n)
+{
+    c %= n;
+    return c < 0 ? c + n : c;
+}
+
+template <typename R>
+__device__ __forceinline__ bool finite_r(R x)
+{
+    return x == x && x - x == R(0);
+}
+
+// Carry rule of the binning: bring off into [0, D) moving the cell index by
+// whole cells (a point exactly on a face belongs to the upper cell).  Offsets
+// more than a few cells away are first reduced with floor; non-finite or
+// absurdly large offsets are reset to 0 in the same cell and reported, so the
+// cell index always stays a valid array index.
+template <typename R>
+__device__ __forceinline__ bool carry(R &o, int &c, R D, int n)
+{
+#pragma clang fp contract(off)
+    bool ok = true;
+    if (!(o >= R(-4) * D && o < R(5) * D)) {
+        const R lim = D * R(n) * R(4);
+        if (!(o > -lim && o < lim)) {
+            o = R(0);
+            ok = false;
+        } else {
+            const R k = floor(o / D);
+            o = o - k * D;
+            c += int(k);
+            c = wrap_index(c, n);
+        }
+    }
+    for (int it = 0; it < 8 && o < R(0); ++it) { o += D; c -= 1; }
+    for (int it = 0; it < 8 && o >= D; ++it) { o -= D; c += 1; }
+    if (o < R(0) || o >= D) { o = R(0); ok = false; }
+    c = wrap_index(c, n);
+    return ok;
+}
+
+template <typename R>
+__device__ __forceinline__ void split_cell(const Geom<R> &G, int lin, int &cx, int &cy, int &cz)
+{
+    cx = lin % G.nc[0];
+    const int r = lin / G.nc[0];
+    cy = r % G.nc[1];
+    cz = r / G.nc[1];
+}
+
+template <typename R>
+__device__ __forceinline__ int join_cell(const Geom<R> &G, int cx, int cy, int cz)
+{
+    return cx + G.nc[0] * (cy + G.nc[1] * cz);
+}
+
+template <typename R>
+__device__ __forceinline__ R mass_of(const R *m, R mu, int i)
+{
+    return m ? m[i] : mu;
+}
+
+}  // namespace tfsph

@@ -1,0 +1,320 @@
+// SPH sums and the fused IDIC update (Section 2.3, eqs. 17-21).
+//
+// k_density  : rho_a = sum_b m_b W(|r_ab|, h) over the cell window, self
+//              included; also stores p_a / rho_a^2 for the force pass.
+// k_update   : one block owns a contiguous run of cells (both phases).  It
+//              evaluates the explicit gas terms of eq. (19) for its gas
+//              particles, forms the predictor v~, sums mass and momentum of
+//              each cell serially in (cell, id) order (no float atomics),
+//              solves the 2x2 implicit system of each cell in closed form,
+//              updates every particle of its cells, moves it and carries its
+//              offset back into [0, Delta).
+#pragma once
+
+#include "common.hpp"
+
+namespace tfsph {
+
+// Visit every particle of phase (start, off) in the neighbour window of a
+// point with offsets oa[] in cell (cx, cy, cz).  fn(b, rx, ry, rz) gets
+// r = x_a - x_b.  Order: window z, y, x offsets ascending, then cell order.
+template <typename R, int DIM, typename Fn>
+__device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
+                                           const int *__restrict__ start, R *const off[3], Fn &&fn)
+{
+    const int wz = DIM > 2 ? G.win[2] : 0;
+    const int wy = DIM > 1 ? G.win[1] : 0;
+    const int wx = G.win[0];
+    for (int dz = -wz; dz <= wz; ++dz) {
+        const int z = DIM > 2 ? wrap_index(cz + dz, G.nc[2]) : 0;
+        const R rz0 = DIM > 2 ? oa[2] - R(dz) * G.delta[2] : R(0);
+        for (int dy = -wy; dy <= wy; ++dy) {
+            const int y = DIM > 1 ? wrap_index(cy + dy, G.nc[1]) : 0;
+            const R ry0 = DIM > 1 ? oa[1] - R(dy) * G.delta[1] : R(0);
+            const int row = G.nc[0] * (y + G.nc[1] * z);
+            for (int dx = -wx; dx <= wx; ++dx) {
+                const int x = wrap_index(cx + dx, G.nc[0]);
+                const R rx0 = oa[0] - R(dx) * G.delta[0];
+                const int lin = x + row;
+                const int b0 = start[lin];
+                const int b1 = start[lin + 1];
+                for (int b = b0; b < b1; ++b) {
+                    const R rx = rx0 - off[0][b];
+                    const R ry = DIM > 1 ? ry0 - off[1][b] : R(0);
+                    const R rz = DIM > 2 ? rz0 - off[2][b] : R(0);
+                    fn(b, rx, ry, rz);
+                }
+            }
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ R pressure_of(const Phys<R> &Ph, R rho, R e)
+{
+    return Ph.eos == 0 ? Ph.cs2 * rho : Ph.gm1 * rho * e;
+}
+
+template <typename R>
+__device__ __forceinline__ R sound_of(const Phys<R> &Ph, R e)
+{
+    return Ph.eos == 0 ? Ph.cs : sqrt(Ph.ggm1 * e);
+}
+
+// --------------------------------------------------------------------------
+// Summation density of phase S at its own sorted particle a.
+// --------------------------------------------------------------------------
+template <typename R, int DIM>
+__device__ __forceinline__ R density_at(const Geom<R> &G, const Sorted<R> &S, int a)
+{
+    int cx, cy, cz;
+    split_cell(G, S.cell[a], cx, cy, cz);
+    R oa[3] = {S.off[0][a], DIM > 1 ? S.off[1][a] : R(0), DIM > 2 ? S.off[2][a] : R(0)};
+    R acc = R(0);
+    const R *mass = S.mass;
+    const R mu = S.m_uniform;
+    for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.off, [&](int b, R rx, R ry, R rz) {
+        const R r2 = rx * rx + ry * ry + rz * rz;
+        if (r2 < G.support2) {
+            const R q = sqrt(r2) * G.inv_h;
+            acc += mass_of(mass, mu, b) * spline_f(q);
+        }
+    });
+    return acc * G.wnorm;
+}
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(kBlock) k_density(Geom<R> G, Phys<R> Ph, Sorted<R> S, int want_prs)
+{
+    const int a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= S.n) return;
+    const R rho = density_at<R, DIM>(G, S, a);
+    S.rho[a] = rho;
+    if (want_prs) {
+        const R e = S.energy ? S.energy[a] : R(0);
+        S.prs[a] = pressure_of(Ph, rho, e) / (rho * rho);
+    }
+}
+
+// --------------------------------------------------------------------------
+// Explicit gas terms at sorted gas particle a: acceleration (without g) and
+// de/dt.
+//   A_a   = -sum_b m_b (P_a + P_b + Pi_ab) grad_a W_ab,   P = p / rho^2
+//   de_a  =  sum_b m_b (P_a + Pi_ab / 2) v_ab . grad_a W_ab
+//   Pi_ab = (-alpha cbar mu + beta mu^2) / rhobar  if v_ab . r_ab < 0
+//   mu    = h v_ab . r_ab / (r^2 + 0.01 h^2)
+// --------------------------------------------------------------------------
+template <typename R, int DIM>
+__device__ __forceinline__ void gas_force_at(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &S, int a,
+                                             R acc[3], R &dedt)
+{
+    int cx, cy, cz;
+    split_cell(G, S.cell[a], cx, cy, cz);
+    R oa[3] = {S.off[0][a], DIM > 1 ? S.off[1][a] : R(0), DIM > 2 ? S.off[2][a] : R(0)};
+    const R Pa = S.prs[a];
+    const R *mass = S.mass;
+    const R mu_m = S.m_uniform;
+    R ax = R(0), ay = R(0), az = R(0), de = R(0);
+    if (!Ph.av && Ph.eos == 0) {
+        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.off, [&](int b, R rx, R ry, R rz) {
+            const R r2 = rx * rx + ry * ry + rz * rz;
+            if (r2 < G.support2 && r2 > R(0)) {
+                const R r = sqrt(r2);
+                const R fac = mass_of(mass, mu_m, b) * (Pa + S.prs[b]) * spline_df(r * G.inv_h) / r;
+                ax -= fac * rx;
+                ay -= fac * ry;
+                az -= fac * rz;
+            }
+        });
+    } else {
+        const R va[3] = {S.vel[0][a], DIM > 1 ? S.vel[1][a] : R(0), DIM > 2 ? S.vel[2][a] : R(0)};
+        const R rhoa = S.rho[a];
+        const R ca = sound_of(Ph, S.energy ? S.energy[a] : R(0));
+        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.off, [&](int b, R rx, R ry, R rz) {
+            const R r2 = rx * rx + ry * ry + rz * rz;
+            if (r2 < G.support2 && r2 > R(0)) {
+                const R r = sqrt(r2);
+                const R gfac = spline_df(r * G.inv_h) / r;   // grad_a W = gfac * gnorm * r_vec
+                const R vx = va[0] - S.vel[0][b];
+                const R vy = DIM > 1 ? va[1] - S.vel[1][b] : R(0);
+                const R vz = DIM > 2 ? va[2] - S.vel[2][b] : R(0);
+                const R vr = vx * rx + vy * ry + vz * rz;
+                R Pi = R(0);
+                if (Ph.av && vr < R(0)) {
+                    const R mu = Ph.h * vr / (r2 + Ph.eta2);
+                    const R cb = sound_of(Ph, S.energy ? S.energy[b] : R(0));
+                    const R cbar = R(0.5) * (ca + cb);
+                    const R rbar = R(0.5) * (rhoa + S.rho[b]);
+                    Pi = (-Ph.av_alpha * cbar * mu + Ph.av_beta * mu * mu) / rbar;
+                }
+                const R mb = mass_of(mass, mu_m, b);
+                const R fac = mb * (Pa + S.prs[b] + Pi) * gfac;
+                ax -= fac * rx;
+                ay -= fac * ry;
+                az -= fac * rz;
+                de += mb * (Pa + R(0.5) * Pi) * gfac * vr;
+            }
+        });
+    }
+    acc[0] = ax * G.gnorm;
+    acc[1] = ay * G.gnorm;
+    acc[2] = az * G.gnorm;
+    dedt = de * G.gnorm;
+}
+
+// --------------------------------------------------------------------------
+// Per-cell closed-form implicit solve (eqs. 17-21 with first-order time
+// differences).  With eps = M_d / M_g, alpha = eps tau / t_stop and
+// beta = tau / t_stop the new cell means solve
+//   (1 + alpha) V - alpha U = V~,   -beta V + (1 + beta) U = U~,
+// so with D = 1 + alpha + beta:
+//   V = ((1 + beta) V~ + alpha U~) / D,   U = (beta V~ + (1 + alpha) U~) / D.
+// A cell without gas or without dust gets alpha = beta = 0 (no drag).
+// --------------------------------------------------------------------------
+template <typename R>
+struct CellSolve {
+    R alpha, beta;
+    R V[3], U[3];
+};
+
+template <typename R, int DIM>
+__device__ __forceinline__ bool solve_cell(const Phys<R> &Ph, const Sorted<R> &Sg, const Sorted<R> &Sd, int c,
+                                           CellSolve<R> &out)
+{
+    const int g0 = Sg.start[c], g1 = Sg.start[c + 1];
+    const int d0 = Sd.start[c], d1 = Sd.start[c + 1];
+    R Mg = R(0), Md = R(0);
+    R Pg[3] = {R(0), R(0), R(0)}, Pd[3] = {R(0), R(0), R(0)};
+    for (int a = g0; a < g1; ++a) {
+        const R m = mass_of(Sg.mass, Sg.m_uniform, a);
+        Mg += m;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) Pg[d] += m * Sg.vt[d][a];
+    }
+    for (int j = d0; j < d1; ++j) {
+        const R m = mass_of(Sd.mass, Sd.m_uniform, j);
+        Md += m;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) Pd[d] += m * (Sd.vel[d][j] + Ph.tau * Ph.g[d]);
+    }
+    const bool both = g1 > g0 && d1 > d0;
+    if (both) {
+        const R eps = Md / Mg;
+        out.beta = Ph.beta;
+        out.alpha = eps * Ph.beta;
+        const R D = R(1) + out.alpha + out.beta;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            const R Vt = Pg[d] / Mg, Ut = Pd[d] / Md;
+            out.V[d] = ((R(1) + out.beta) * Vt + out.alpha * Ut) / D;
+            out.U[d] = (out.beta * Vt + (R(1) + out.alpha) * Ut) / D;
+        }
+    } else {
+        out.alpha = out.beta = R(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) out.V[d] = out.U[d] = R(0);
+    }
+    return !both && (g1 > g0 || d1 > d0);
+}
+
+// Block-to-cell-range map.  Consecutive block ids land on different XCDs
+// (round-robin dispatch over 8 XCDs); remap so that each XCD works on one
+// contiguous slab of cell ranges and neighbour halos stay in its own L2.
+__device__ __forceinline__ int xcd_block(int nblocks)
+{
+    const int b = blockIdx.x;
+    const int per = nblocks / 8;
+    if (per == 0 || b >= per * 8) return b;
+    return (b % 8) * per + b / 8;
+}
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(kBlock)
+k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R> Pd, Flags F, int cells_per_block,
+         int nblocks)
+{
+    extern __shared__ unsigned char smem_raw[];
+    CellSolve<R> *cs = reinterpret_cast<CellSolve<R> *>(smem_raw);
+    __shared__ int s_bad, s_one;
+    const int blk = xcd_block(nblocks);
+    const int c0 = blk * cells_per_block;
+    const int c1 = min(c0 + cells_per_block, G.ncell);
+    if (threadIdx.x == 0) { s_bad = 0; s_one = 0; }
+
+    // (1) explicit gas terms and predictor v~ (eq. 19, explicit part)
+    const int ga = Sg.start[c0], gb = Sg.start[c1];
+    for (int a = ga + threadIdx.x; a < gb; a += kBlock) {
+        R acc[3], dedt;
+        gas_force_at<R, DIM>(G, Ph, Sg, a, acc, dedt);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) Sg.vt[d][a] = Sg.vel[d][a] + Ph.tau * (acc[d] + Ph.g[d]);
+        if (Sg.energy) Pg.energy[a] = Sg.energy[a] + Ph.tau * dedt;
+    }
+    __syncthreads();
+
+    // (2) per-cell sums in canonical order and the implicit solve
+    int one = 0;
+    for (int c = c0 + threadIdx.x; c < c1; c += kBlock)
+        one += solve_cell<R, DIM>(Ph, Sg, Sd, c, cs[c - c0]) ? 1 : 0;
+    if (one) atomicAdd(&s_one, one);
+    __syncthreads();
+
+    // (3) implicit particle update (eqs. 19-20), position update, carry
+    int bad = 0;
+    for (int a = ga + threadIdx.x; a < gb; a += kBlock) {
+        const int c = Sg.cell[a];
+        const CellSolve<R> &C = cs[c - c0];
+        const R inv = R(1) / (R(1) + C.alpha);
+        int cc[3];
+        split_cell(G, c, cc[0], cc[1], cc[2]);
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            const R v = (Sg.vt[d][a] + C.alpha * C.U[d]) * inv;
+            R o = Sg.off[d][a] + Ph.tau * v;
+            ok &= finite_r(v);
+            ok &= carry(o, cc[d], G.delta[d], G.nc[d]);
+            Pg.vel[d][a] = v;
+            Pg.off[d][a] = o;
+        }
+        Pg.cell[a] = join_cell(G, cc[0], cc[1], cc[2]);
+        Pg.id[a] = Sg.id[a];
+        if (Sg.mass) const_cast<R *>(Pg.mass)[a] = Sg.mass[a];
+        Pg.rho[a] = Sg.rho[a];
+        bad |= !ok;
+    }
+    const int da = Sd.start[c0], db = Sd.start[c1];
+    for (int j = da + threadIdx.x; j < db; j += kBlock) {
+        const int c = Sd.cell[j];
+        const CellSolve<R> &C = cs[c - c0];
+        const R inv = R(1) / (R(1) + C.beta);
+        int cc[3];
+        split_cell(G, c, cc[0], cc[1], cc[2]);
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            const R ut = Sd.vel[d][j] + Ph.tau * Ph.g[d];
+            const R u = (ut + C.beta * C.V[d]) * inv;
+            R o = Sd.off[d][j] + Ph.tau * u;
+            ok &= finite_r(u);
+            ok &= carry(o, cc[d], G.delta[d], G.nc[d]);
+            Pd.vel[d][j] = u;
+            Pd.off[d][j] = o;
+        }
+        Pd.cell[j] = join_cell(G, cc[0], cc[1], cc[2]);
+        Pd.id[j] = Sd.id[j];
+        if (Sd.mass) const_cast<R *>(Pd.mass)[j] = Sd.mass[j];
+        bad |= !ok;
+    }
+    if (bad) atomicOr(&s_bad, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_bad) atomicOr(F.word, 1u);
+        if (s_one) {
+            atomicOr(F.word, 2u);
+            atomicAdd(F.one_phase, (unsigned long long)s_one);
+        }
+    }
+}
+
+}  // namespace tfsph

@@ -1,0 +1,686 @@
+// Host runtime of the TFSPH library: parameter validation, workspace
+// planning, and the launch sequence of one IDIC step (Section 2.3).
+// Declarations and the contract of every entry point: include/tfsph.h.
+#include "../../include/tfsph.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "binning.hpp"
+#include "common.hpp"
+#include "sph.hpp"
+
+using namespace tfsph;
+
+// ----------------------------------------------------------------------------
+// errors
+// ----------------------------------------------------------------------------
+static thread_local char g_last_error[512] = "";
+
+static tfsph_status fail(tfsph_status s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(TFSPH_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCH_CHECK(name)                                                                          \
+    do {                                                                                            \
+        hipError_t e_ = hipGetLastError();                                                          \
+        if (e_ != hipSuccess) return fail(TFSPH_E_HIP, "launch %s: %s", name, hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char *tfsph_status_string(tfsph_status s)
+{
+    switch (s) {
+    case TFSPH_OK: return "TFSPH_OK";
+    case TFSPH_E_INVALID_ARG: return "TFSPH_E_INVALID_ARG";
+    case TFSPH_E_WORKSPACE: return "TFSPH_E_WORKSPACE";
+    case TFSPH_E_HIP: return "TFSPH_E_HIP";
+    case TFSPH_E_UNSUPPORTED: return "TFSPH_E_UNSUPPORTED";
+    case TFSPH_E_STATE: return "TFSPH_E_STATE";
+    }
+    return "TFSPH_E_UNKNOWN";
+}
+
+extern "C" const char *tfsph_last_error(void) { return g_last_error; }
+
+// ----------------------------------------------------------------------------
+// validation (host only)
+// ----------------------------------------------------------------------------
+static int window_of(const tfsph_params *p, int d)
+{
+    const double D = (p->box_hi[d] - p->box_lo[d]) / p->n_cells[d];
+    return (int)std::ceil(2.0 * p->h / D - 1e-12);
+}
+
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+extern "C" tfsph_status tfsph_validate(const tfsph_params *p)
+{
+    g_last_error[0] = 0;
+    if (!p) return fail(TFSPH_E_INVALID_ARG, "params is NULL");
+    if (p->dim < 1 || p->dim > 3) return fail(TFSPH_E_INVALID_ARG, "dim must be 1, 2 or 3 (got %d)", p->dim);
+    if (p->precision != TFSPH_F32 && p->precision != TFSPH_F64)
+        return fail(TFSPH_E_INVALID_ARG, "unknown precision %d", p->precision);
+    if (p->eos != TFSPH_ISOTHERMAL && p->eos != TFSPH_ADIABATIC) return fail(TFSPH_E_INVALID_ARG, "unknown eos %d", p->eos);
+    if (!finite_pos(p->h)) return fail(TFSPH_E_INVALID_ARG, "h must be positive and finite");
+    long long ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (d >= p->dim) {
+            if (p->n_cells[d] != 1) return fail(TFSPH_E_INVALID_ARG, "n_cells[%d] must be 1 for dim %d", d, p->dim);
+            continue;
+        }
+        if (p->n_cells[d] < 1) return fail(TFSPH_E_INVALID_ARG, "n_cells[%d] must be >= 1", d);
+        if (!(std::isfinite(p->box_lo[d]) && std::isfinite(p->box_hi[d]) && p->box_hi[d] > p->box_lo[d]))
+            return fail(TFSPH_E_INVALID_ARG, "box axis %d must satisfy box_lo < box_hi (finite)", d);
+        const int W = window_of(p, d);
+        if (W > kMaxWindow) return fail(TFSPH_E_INVALID_ARG, "neighbour window %d cells on axis %d exceeds %d", W, d, kMaxWindow);
+        if (p->n_cells[d] < 2 * W + 1)
+            return fail(TFSPH_E_INVALID_ARG, "axis %d has %d cells; the 2h window needs at least %d", d, p->n_cells[d], 2 * W + 1);
+        ncell *= p->n_cells[d];
+        if (ncell > 0x7fffffffLL - 1) return fail(TFSPH_E_INVALID_ARG, "too many cells");
+    }
+    if (!finite_pos(p->t_stop)) return fail(TFSPH_E_INVALID_ARG, "t_stop must be positive");
+    if (!finite_pos(p->dt)) return fail(TFSPH_E_INVALID_ARG, "dt must be positive");
+    if (p->eos == TFSPH_ISOTHERMAL && !finite_pos(p->c_s)) return fail(TFSPH_E_INVALID_ARG, "c_s must be positive");
+    if (p->eos == TFSPH_ADIABATIC && !(std::isfinite(p->gamma) && p->gamma > 1.0))
+        return fail(TFSPH_E_INVALID_ARG, "gamma must be > 1");
+    if (!(p->av_alpha >= 0.0 && p->av_beta >= 0.0 && std::isfinite(p->av_alpha) && std::isfinite(p->av_beta)))
+        return fail(TFSPH_E_INVALID_ARG, "viscosity coefficients must be >= 0");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(p->g[d])) return fail(TFSPH_E_INVALID_ARG, "g must be finite");
+    return TFSPH_OK;
+}
+
+// ----------------------------------------------------------------------------
+// workspace layout
+// ----------------------------------------------------------------------------
+namespace {
+
+struct Carver {
+    size_t off = 0;
+    char *base = nullptr;
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += sizeof(T) * (count ? count : 1);
+        return p;
+    }
+};
+
+struct PhaseFlags {
+    bool mass;      // per-particle mass array present
+    bool energy;    // energy array present
+    bool prs;       // needs p / rho^2 and predictor scratch (gas)
+};
+
+template <typename R>
+Sorted<R> carve_phase(Carver &cv, int n, int dim, int ncell, PhaseFlags f, R m_uniform)
+{
+    Sorted<R> S{};
+    S.n = n;
+    S.cell = cv.take<int>(n);
+    S.id = cv.take<int>(n);
+    for (int d = 0; d < 3; ++d) {
+        S.off[d] = d < dim ? cv.take<R>(n) : nullptr;
+        S.vel[d] = d < dim ? cv.take<R>(n) : nullptr;
+        S.vt[d] = (f.prs && d < dim) ? cv.take<R>(n) : nullptr;
+    }
+    S.mass = f.mass ? cv.take<R>(n) : nullptr;
+    S.m_uniform = m_uniform;
+    S.energy = f.energy ? cv.take<R>(n) : nullptr;
+    S.rho = cv.take<R>(n);
+    S.prs = f.prs ? cv.take<R>(n) : nullptr;
+    S.count = cv.take<int>(ncell);
+    S.start = cv.take<int>(size_t(ncell) + 1);
+    S.slot = cv.take<int>(n);
+    S.tmp_idx = cv.take<int>(n);
+    S.tmp_id = cv.take<int>(n);
+    return S;
+}
+
+int ncell_of(const tfsph_params *p)
+{
+    int n = 1;
+    for (int d = 0; d < p->dim; ++d) n *= p->n_cells[d];
+    return n;
+}
+
+int ntiles_of(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
+
+template <typename R>
+size_t plan_bytes(const tfsph_params *p, int ng, int nd, PhaseFlags fg, PhaseFlags fd)
+{
+    Carver cv;
+    const int ncell = ncell_of(p);
+    carve_phase<R>(cv, ng, p->dim, ncell, fg, R(0));
+    carve_phase<R>(cv, nd, p->dim, ncell, fd, R(0));
+    cv.take<int>(size_t(2) * ntiles_of(ncell));
+    cv.take<unsigned int>(64);
+    cv.take<unsigned long long>(8);
+    return cv.off + 256;
+}
+
+}  // namespace
+
+// event pairs bracketing launches of one kernel kind
+struct KernelTimer {
+    std::vector<hipEvent_t> ev;   // pairs: start, stop
+    size_t used = 0;              // events recorded so far
+};
+
+struct tfsph_ctx {
+    tfsph_params p;
+    bool profiling = false;
+    KernelTimer timers[3];
+    int ng, nd;
+    PhaseFlags fg, fd;
+    double mg_uniform, md_uniform;
+    char *ws;
+    size_t ws_bytes;
+    hipStream_t last_stream;
+    int cells_per_block;
+};
+
+// record one event of a (start, stop) pair for kernel kind k when profiling
+static tfsph_status timer_mark(tfsph_ctx *c, int k, hipStream_t st)
+{
+    if (!c->profiling) return TFSPH_OK;
+    KernelTimer &T = c->timers[k];
+    if (T.used == T.ev.size()) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        T.ev.push_back(e);
+    }
+    HIP_TRY(hipEventRecord(T.ev[T.used++], st));
+    return TFSPH_OK;
+}
+
+#define MARK(k)                                         \
+    do {                                                \
+        tfsph_status m_ = timer_mark(c, (k), st);       \
+        if (m_ != TFSPH_OK) return m_;                  \
+    } while (0)
+
+static PhaseFlags gas_flags(const tfsph_params *p, bool mass_array)
+{
+    return PhaseFlags{mass_array, p->eos == TFSPH_ADIABATIC, true};
+}
+
+static PhaseFlags dust_flags(bool mass_array) { return PhaseFlags{mass_array, false, false}; }
+
+extern "C" tfsph_status tfsph_workspace_size(const tfsph_params *p, int64_t n_gas, int64_t n_dust, size_t *bytes)
+{
+    tfsph_status s = tfsph_validate(p);
+    if (s != TFSPH_OK) return s;
+    if (!bytes) return fail(TFSPH_E_INVALID_ARG, "bytes is NULL");
+    if (n_gas < 0 || n_dust < 0 || n_gas > 0x7fffffffLL || n_dust > 0x7fffffffLL)
+        return fail(TFSPH_E_INVALID_ARG, "particle counts must be in [0, 2^31)");
+    // sized for per-particle masses on both phases (the largest layout)
+    PhaseFlags fg = gas_flags(p, true), fd = dust_flags(true);
+    *bytes = p->precision == TFSPH_F64 ? plan_bytes<double>(p, (int)n_gas, (int)n_dust, fg, fd)
+                                       : plan_bytes<float>(p, (int)n_gas, (int)n_dust, fg, fd);
+    return TFSPH_OK;
+}
+
+// ----------------------------------------------------------------------------
+// typed views
+// ----------------------------------------------------------------------------
+namespace {
+
+template <typename R>
+Geom<R> make_geom(const tfsph_params *p)
+{
+    Geom<R> G{};
+    static const double sig[4] = {0.0, 2.0 / 3.0, 10.0 / (7.0 * M_PI), 1.0 / M_PI};
+    G.dim = p->dim;
+    G.ncell = ncell_of(p);
+    for (int d = 0; d < 3; ++d) {
+        G.nc[d] = d < p->dim ? p->n_cells[d] : 1;
+        G.win[d] = d < p->dim ? window_of(p, d) : 0;
+        G.delta[d] = d < p->dim ? R((p->box_hi[d] - p->box_lo[d]) / p->n_cells[d]) : R(1);
+    }
+    G.h = R(p->h);
+    G.inv_h = R(1.0 / p->h);
+    G.support2 = R(4.0 * p->h * p->h);
+    G.wnorm = R(sig[p->dim] / std::pow(p->h, p->dim));
+    G.gnorm = R(sig[p->dim] / std::pow(p->h, p->dim + 1));
+    return G;
+}
+
+template <typename R>
+Phys<R> make_phys(const tfsph_params *p)
+{
+    Phys<R> P{};
+    P.eos = p->eos;
+    P.av = (p->av_alpha != 0.0 || p->av_beta != 0.0) ? 1 : 0;
+    P.cs = R(p->c_s);
+    P.cs2 = R(p->c_s * p->c_s);
+    P.gm1 = R(p->gamma - 1.0);
+    P.ggm1 = R(p->gamma * (p->gamma - 1.0));
+    P.tau = R(p->dt);
+    P.beta = R(p->dt / p->t_stop);
+    for (int d = 0; d < 3; ++d) P.g[d] = d < p->dim ? R(p->g[d]) : R(0);
+    P.av_alpha = R(p->av_alpha);
+    P.av_beta = R(p->av_beta);
+    P.eta2 = R(0.01 * p->h * p->h);
+    P.h = R(p->h);
+    return P;
+}
+
+template <typename R>
+Phase<R> make_phase(const tfsph_phase &ph, int dim)
+{
+    Phase<R> P{};
+    P.n = (int)ph.n;
+    P.cell = ph.cell;
+    for (int d = 0; d < 3; ++d) {
+        P.off[d] = d < dim ? static_cast<R *>(ph.off[d]) : nullptr;
+        P.vel[d] = d < dim ? static_cast<R *>(ph.vel[d]) : nullptr;
+    }
+    P.mass = static_cast<const R *>(ph.mass);
+    P.m_uniform = R(ph.mass_uniform);
+    P.rho = static_cast<R *>(ph.rho);
+    P.energy = static_cast<R *>(ph.energy);
+    P.id = ph.id;
+    return P;
+}
+
+struct Views {
+    char *base;
+};
+
+template <typename R>
+void carve_all(const tfsph_ctx *c, Sorted<R> &Sg, Sorted<R> &Sd, int *&partial, Flags &F)
+{
+    Carver cv;
+    cv.base = c->ws;
+    const int ncell = ncell_of(&c->p);
+    Sg = carve_phase<R>(cv, c->ng, c->p.dim, ncell, c->fg, R(c->mg_uniform));
+    Sd = carve_phase<R>(cv, c->nd, c->p.dim, ncell, c->fd, R(c->md_uniform));
+    partial = cv.take<int>(size_t(2) * ntiles_of(ncell));
+    F.word = cv.take<unsigned int>(64);
+    F.one_phase = cv.take<unsigned long long>(8);
+}
+
+inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
+
+tfsph_status check_phase(const tfsph_phase &ph, int dim, bool need_rho, bool need_energy, const char *name)
+{
+    if (ph.n < 0 || ph.n > 0x7fffffffLL) return fail(TFSPH_E_INVALID_ARG, "%s.n out of range", name);
+    if (ph.n == 0) return TFSPH_OK;
+    if (!ph.cell || !ph.id) return fail(TFSPH_E_INVALID_ARG, "%s.cell / %s.id is NULL", name, name);
+    for (int d = 0; d < dim; ++d)
+        if (!ph.off[d] || !ph.vel[d]) return fail(TFSPH_E_INVALID_ARG, "%s.off[%d] / vel[%d] is NULL", name, d, d);
+    if (!ph.mass && !(std::isfinite(ph.mass_uniform) && ph.mass_uniform > 0.0))
+        return fail(TFSPH_E_INVALID_ARG, "%s: mass is NULL and mass_uniform is not positive", name);
+    if (need_rho && !ph.rho) return fail(TFSPH_E_INVALID_ARG, "%s.rho is NULL", name);
+    if (need_energy && !ph.energy) return fail(TFSPH_E_INVALID_ARG, "%s.energy is NULL (adiabatic EOS)", name);
+    return TFSPH_OK;
+}
+
+tfsph_status check_state_matches(const tfsph_ctx *c, const tfsph_state *s)
+{
+    if (!s) return fail(TFSPH_E_INVALID_ARG, "state is NULL");
+    if (s->gas.n != c->ng || s->dust.n != c->nd)
+        return fail(TFSPH_E_STATE, "state sizes (%lld, %lld) differ from init (%d, %d)", (long long)s->gas.n,
+                    (long long)s->dust.n, c->ng, c->nd);
+    if ((s->gas.mass != nullptr) != c->fg.mass || (s->dust.mass != nullptr) != c->fd.mass)
+        return fail(TFSPH_E_STATE, "per-particle mass arrays present/absent differently from init");
+    tfsph_status st = check_phase(s->gas, c->p.dim, true, c->p.eos == TFSPH_ADIABATIC, "gas");
+    if (st != TFSPH_OK) return st;
+    return check_phase(s->dust, c->p.dim, false, false, "dust");
+}
+
+// zero + count + scan + scatter + rank/gather of both phases into the workspace
+template <typename R>
+tfsph_status enqueue_bin(const tfsph_ctx *c, const Geom<R> &G, const Phase<R> &Pg, const Phase<R> &Pd,
+                         Sorted<R> &Sg, Sorted<R> &Sd, int *partial, const Flags &F, hipStream_t st)
+{
+    const int ncell = G.ncell;
+    const int ntiles = ntiles_of(ncell);
+    const int bg = blocks_for(c->ng), bd = blocks_for(c->nd);
+    hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(ncell)), dim3(kBlock), 0, st, Sg.count, ncell, Sd.count, ncell);
+    LAUNCH_CHECK("fill_zero");
+    if (bg + bd > 0) {
+        hipLaunchKernelGGL(k_count, dim3(bg + bd), dim3(kBlock), 0, st, Pg.cell, c->ng, Sg.count, Sg.slot, Pd.cell,
+                           c->nd, Sd.count, Sd.slot, bg, ncell, F.word);
+        LAUNCH_CHECK("count");
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3(ntiles, 2), dim3(kBlock), 0, st, Sg.count, Sd.count, ncell, partial, ntiles);
+    LAUNCH_CHECK("scan_reduce");
+    hipLaunchKernelGGL(k_scan_top, dim3(1, 2), dim3(kBlock), 0, st, partial, ntiles, Sg.start, Sd.start, ncell);
+    LAUNCH_CHECK("scan_top");
+    hipLaunchKernelGGL(k_scan_down, dim3(ntiles, 2), dim3(kBlock), 0, st, Sg.count, Sd.count, ncell, partial, ntiles,
+                       Sg.start, Sd.start);
+    LAUNCH_CHECK("scan_down");
+    if (bg + bd > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(bg + bd), dim3(kBlock), 0, st, Pg.cell, Pg.id, Sg.slot, Sg.start, c->ng,
+                           Sg.tmp_idx, Sg.tmp_id, Pd.cell, Pd.id, Sd.slot, Sd.start, c->nd, Sd.tmp_idx, Sd.tmp_id, bg, ncell);
+        LAUNCH_CHECK("scatter");
+        hipLaunchKernelGGL(k_rank_gather<R>, dim3(bg + bd), dim3(kBlock), 0, st, G, Pg, Sg, Pd, Sd, bg, F.word);
+        LAUNCH_CHECK("rank_gather");
+    }
+    return TFSPH_OK;
+}
+
+template <typename R, int DIM>
+tfsph_status enqueue_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
+{
+    const Geom<R> G = make_geom<R>(&c->p);
+    const Phys<R> Ph = make_phys<R>(&c->p);
+    Phase<R> Pg = make_phase<R>(s->gas, DIM), Pd = make_phase<R>(s->dust, DIM);
+    Sorted<R> Sg, Sd;
+    int *partial;
+    Flags F;
+    carve_all<R>(c, Sg, Sd, partial, F);
+    MARK(TFSPH_KERNEL_BIN);
+    tfsph_status r = enqueue_bin<R>(c, G, Pg, Pd, Sg, Sd, partial, F, st);
+    if (r != TFSPH_OK) return r;
+    MARK(TFSPH_KERNEL_BIN);
+    if (c->ng > 0) {
+        MARK(TFSPH_KERNEL_DENSITY);
+        hipLaunchKernelGGL((k_density<R, DIM>), dim3(blocks_for(c->ng)), dim3(kBlock), 0, st, G, Ph, Sg, 1);
+        LAUNCH_CHECK("density");
+        MARK(TFSPH_KERNEL_DENSITY);
+    }
+    const int cpb = c->cells_per_block;
+    const int nblocks = (G.ncell + cpb - 1) / cpb;
+    const size_t lds = sizeof(CellSolve<R>) * cpb;
+    MARK(TFSPH_KERNEL_UPDATE);
+    hipLaunchKernelGGL((k_update<R, DIM>), dim3(nblocks), dim3(kBlock), lds, st, G, Ph, Sg, Sd, Pg, Pd, F, cpb, nblocks);
+    LAUNCH_CHECK("update");
+    MARK(TFSPH_KERNEL_UPDATE);
+    return TFSPH_OK;
+}
+
+template <typename R>
+tfsph_status enqueue_init(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
+{
+    const Geom<R> G = make_geom<R>(&c->p);
+    Phase<R> Pg = make_phase<R>(s->gas, c->p.dim), Pd = make_phase<R>(s->dust, c->p.dim);
+    Sorted<R> Sg, Sd;
+    int *partial;
+    Flags F;
+    carve_all<R>(c, Sg, Sd, partial, F);
+    HIP_TRY(hipMemsetAsync(F.word, 0, 256, st));
+    HIP_TRY(hipMemsetAsync(F.one_phase, 0, 64, st));
+    if (c->ng > 0) {
+        hipLaunchKernelGGL(k_canonicalize<R>, dim3(blocks_for(c->ng)), dim3(kBlock), 0, st, G, Pg, F);
+        LAUNCH_CHECK("canonicalize");
+    }
+    if (c->nd > 0) {
+        hipLaunchKernelGGL(k_canonicalize<R>, dim3(blocks_for(c->nd)), dim3(kBlock), 0, st, G, Pd, F);
+        LAUNCH_CHECK("canonicalize");
+    }
+    tfsph_status r = enqueue_bin<R>(c, G, Pg, Pd, Sg, Sd, partial, F, st);
+    if (r != TFSPH_OK) return r;
+    if (c->ng > 0) {
+        hipLaunchKernelGGL(k_copy_back<R>, dim3(blocks_for(c->ng)), dim3(kBlock), 0, st, G, Sg, Pg, 0);
+        LAUNCH_CHECK("copy_back");
+    }
+    if (c->nd > 0) {
+        hipLaunchKernelGGL(k_copy_back<R>, dim3(blocks_for(c->nd)), dim3(kBlock), 0, st, G, Sd, Pd, 0);
+        LAUNCH_CHECK("copy_back");
+    }
+    return TFSPH_OK;
+}
+
+template <typename R, int DIM>
+tfsph_status enqueue_density(tfsph_ctx *c, tfsph_state *s, int phase, hipStream_t st)
+{
+    const Geom<R> G = make_geom<R>(&c->p);
+    const Phys<R> Ph = make_phys<R>(&c->p);
+    Phase<R> Pg = make_phase<R>(s->gas, DIM), Pd = make_phase<R>(s->dust, DIM);
+    Sorted<R> Sg, Sd;
+    int *partial;
+    Flags F;
+    carve_all<R>(c, Sg, Sd, partial, F);
+    tfsph_status r = enqueue_bin<R>(c, G, Pg, Pd, Sg, Sd, partial, F, st);
+    if (r != TFSPH_OK) return r;
+    Sorted<R> &S = phase == 0 ? Sg : Sd;
+    if (S.n > 0) {
+        hipLaunchKernelGGL((k_density<R, DIM>), dim3(blocks_for(S.n)), dim3(kBlock), 0, st, G, Ph, S, 0);
+        LAUNCH_CHECK("density");
+    }
+    if (c->ng > 0) {
+        hipLaunchKernelGGL(k_copy_back<R>, dim3(blocks_for(c->ng)), dim3(kBlock), 0, st, G, Sg, Pg, phase == 0);
+        LAUNCH_CHECK("copy_back");
+    }
+    if (c->nd > 0) {
+        hipLaunchKernelGGL(k_copy_back<R>, dim3(blocks_for(c->nd)), dim3(kBlock), 0, st, G, Sd, Pd, phase == 1);
+        LAUNCH_CHECK("copy_back");
+    }
+    return TFSPH_OK;
+}
+
+template <typename R>
+tfsph_status dispatch_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
+{
+    switch (c->p.dim) {
+    case 1: return enqueue_step<R, 1>(c, s, st);
+    case 2: return enqueue_step<R, 2>(c, s, st);
+    default: return enqueue_step<R, 3>(c, s, st);
+    }
+}
+
+template <typename R>
+tfsph_status dispatch_density(tfsph_ctx *c, tfsph_state *s, int phase, hipStream_t st)
+{
+    switch (c->p.dim) {
+    case 1: return enqueue_density<R, 1>(c, s, phase, st);
+    case 2: return enqueue_density<R, 2>(c, s, phase, st);
+    default: return enqueue_density<R, 3>(c, s, phase, st);
+    }
+}
+
+int default_cells_per_block(int dim)
+{
+    return dim == 1 ? 128 : (dim == 2 ? 64 : 32);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// public entry points
+// ----------------------------------------------------------------------------
+extern "C" tfsph_status tfsph_init(tfsph_ctx **out, const tfsph_params *p, tfsph_state *s, void *workspace,
+                                   size_t ws_bytes, void *hip_stream)
+{
+    if (!out) return fail(TFSPH_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    tfsph_status r = tfsph_validate(p);
+    if (r != TFSPH_OK) return r;
+    if (!s) return fail(TFSPH_E_INVALID_ARG, "state is NULL");
+    r = check_phase(s->gas, p->dim, true, p->eos == TFSPH_ADIABATIC, "gas");
+    if (r != TFSPH_OK) return r;
+    r = check_phase(s->dust, p->dim, false, false, "dust");
+    if (r != TFSPH_OK) return r;
+    size_t need = 0;
+    r = tfsph_workspace_size(p, s->gas.n, s->dust.n, &need);
+    if (r != TFSPH_OK) return r;
+    if (!workspace) return fail(TFSPH_E_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(TFSPH_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) return fail(TFSPH_E_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    tfsph_ctx *c = new (std::nothrow) tfsph_ctx();
+    if (!c) return fail(TFSPH_E_INVALID_ARG, "out of host memory");
+    c->p = *p;
+    c->ng = (int)s->gas.n;
+    c->nd = (int)s->dust.n;
+    c->fg = gas_flags(p, s->gas.mass != nullptr);
+    c->fd = dust_flags(s->dust.mass != nullptr);
+    c->mg_uniform = s->gas.mass_uniform;
+    c->md_uniform = s->dust.mass_uniform;
+    c->ws = static_cast<char *>(workspace);
+    c->ws_bytes = ws_bytes;
+    c->last_stream = static_cast<hipStream_t>(hip_stream);
+    c->cells_per_block = default_cells_per_block(p->dim);
+    r = p->precision == TFSPH_F64 ? enqueue_init<double>(c, s, c->last_stream) : enqueue_init<float>(c, s, c->last_stream);
+    if (r != TFSPH_OK) {
+        delete c;
+        return r;
+    }
+    *out = c;
+    return TFSPH_OK;
+}
+
+extern "C" tfsph_status tfsph_step(tfsph_ctx *c, tfsph_state *s, int32_t n_steps, void *hip_stream)
+{
+    if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
+    if (n_steps < 0) return fail(TFSPH_E_INVALID_ARG, "n_steps must be >= 0");
+    tfsph_status r = check_state_matches(c, s);
+    if (r != TFSPH_OK) return r;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    c->last_stream = st;
+    for (int i = 0; i < n_steps; ++i) {
+        r = c->p.precision == TFSPH_F64 ? dispatch_step<double>(c, s, st) : dispatch_step<float>(c, s, st);
+        if (r != TFSPH_OK) return r;
+    }
+    return TFSPH_OK;
+}
+
+extern "C" tfsph_status tfsph_density(tfsph_ctx *c, tfsph_state *s, int32_t phase, void *hip_stream)
+{
+    if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
+    if (phase != 0 && phase != 1) return fail(TFSPH_E_INVALID_ARG, "phase must be 0 (gas) or 1 (dust)");
+    tfsph_status r = check_state_matches(c, s);
+    if (r != TFSPH_OK) return r;
+    if (phase == 1 && c->nd > 0 && !s->dust.rho) return fail(TFSPH_E_INVALID_ARG, "dust.rho is NULL");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    c->last_stream = st;
+    return c->p.precision == TFSPH_F64 ? dispatch_density<double>(c, s, phase, st)
+                                       : dispatch_density<float>(c, s, phase, st);
+}
+
+extern "C" tfsph_status tfsph_get_flags(tfsph_ctx *c, uint32_t *flags, int64_t *one_phase_cells)
+{
+    if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
+    Sorted<float> Sg, Sd;
+    int *partial;
+    Flags F;
+    if (c->p.precision == TFSPH_F64) {
+        Sorted<double> a, b;
+        carve_all<double>(c, a, b, partial, F);
+    } else {
+        carve_all<float>(c, Sg, Sd, partial, F);
+    }
+    unsigned int w = 0;
+    unsigned long long n = 0;
+    HIP_TRY(hipStreamSynchronize(c->last_stream));
+    HIP_TRY(hipMemcpy(&w, F.word, sizeof(w), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&n, F.one_phase, sizeof(n), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(F.word, 0, sizeof(w)));
+    HIP_TRY(hipMemset(F.one_phase, 0, sizeof(n)));
+    if (flags) *flags = w;
+    if (one_phase_cells) *one_phase_cells = (int64_t)n;
+    return TFSPH_OK;
+}
+
+extern "C" tfsph_status tfsph_profile(tfsph_ctx *c, int32_t enable)
+{
+    if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
+    if (enable) {
+        for (auto &T : c->timers) T.used = 0;
+    }
+    c->profiling = enable != 0;
+    return TFSPH_OK;
+}
+
+extern "C" tfsph_status tfsph_profile_read(tfsph_ctx *c, int32_t kernel, double *total_ms, int64_t *launches)
+{
+    if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
+    if (kernel < 0 || kernel > 2) return fail(TFSPH_E_INVALID_ARG, "unknown kernel id %d", kernel);
+    KernelTimer &T = c->timers[kernel];
+    double sum = 0.0;
+    for (size_t i = 0; i + 1 < T.used; i += 2) {
+        HIP_TRY(hipEventSynchronize(T.ev[i + 1]));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, T.ev[i], T.ev[i + 1]));
+        sum += ms;
+    }
+    if (total_ms) *total_ms = sum;
+    if (launches) *launches = (int64_t)(T.used / 2);
+    return TFSPH_OK;
+}
+
+extern "C" tfsph_status tfsph_destroy(tfsph_ctx *c)
+{
+    if (c)
+        for (auto &T : c->timers)
+            for (hipEvent_t e : T.ev) (void)hipEventDestroy(e);
+    delete c;
+    return TFSPH_OK;
+}
+
+namespace {
+template <typename R>
+tfsph_status enqueue_positions(const tfsph_params *p, int n, const double *x, int32_t *cell, void *const off[3],
+                               double *xout, bool to_cells, hipStream_t st)
+{
+    const Geom<R> G = make_geom<R>(p);
+    double D[3];
+    for (int d = 0; d < 3; ++d) D[d] = d < p->dim ? (p->box_hi[d] - p->box_lo[d]) / p->n_cells[d] : 1.0;
+    R *o[3];
+    for (int d = 0; d < 3; ++d) o[d] = d < p->dim ? static_cast<R *>(off[d]) : nullptr;
+    if (n == 0) return TFSPH_OK;
+    if (to_cells) {
+        hipLaunchKernelGGL(k_from_positions<R>, dim3(blocks_for(n)), dim3(kBlock), 0, st, G, p->box_lo[0], p->box_lo[1],
+                           p->box_lo[2], D[0], D[1], D[2], n, x, cell, o[0], o[1], o[2], (unsigned int *)nullptr);
+    } else {
+        hipLaunchKernelGGL(k_to_positions<R>, dim3(blocks_for(n)), dim3(kBlock), 0, st, G, p->box_lo[0], p->box_lo[1],
+                           p->box_lo[2], D[0], D[1], D[2], n, cell, o[0], o[1], o[2], xout);
+    }
+    LAUNCH_CHECK("positions");
+    return TFSPH_OK;
+}
+
+tfsph_status check_positions_args(const tfsph_params *p, int64_t n, const void *x, const int32_t *cell, void *const off[3])
+{
+    tfsph_status r = tfsph_validate(p);
+    if (r != TFSPH_OK) return r;
+    if (n < 0 || n > 0x7fffffffLL) return fail(TFSPH_E_INVALID_ARG, "n out of range");
+    if (n == 0) return TFSPH_OK;
+    if (!x || !cell || !off) return fail(TFSPH_E_INVALID_ARG, "NULL array");
+    for (int d = 0; d < p->dim; ++d)
+        if (!off[d]) return fail(TFSPH_E_INVALID_ARG, "off[%d] is NULL", d);
+    return TFSPH_OK;
+}
+}  // namespace
+
+extern "C" tfsph_status tfsph_positions_to_cells(const tfsph_params *p, int64_t n, const double *x, int32_t *cell,
+                                                 void *off[3], void *hip_stream)
+{
+    tfsph_status r = check_positions_args(p, n, x, cell, off);
+    if (r != TFSPH_OK) return r;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    return p->precision == TFSPH_F64 ? enqueue_positions<double>(p, (int)n, x, cell, off, nullptr, true, st)
+                                     : enqueue_positions<float>(p, (int)n, x, cell, off, nullptr, true, st);
+}
+
+extern "C" tfsph_status tfsph_cells_to_positions(const tfsph_params *p, int64_t n, const int32_t *cell,
+                                                 void *const off[3], double *x, void *hip_stream)
+{
+    tfsph_status r = check_positions_args(p, n, x, cell, off);
+    if (r != TFSPH_OK) return r;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    return p->precision == TFSPH_F64 ? enqueue_positions<double>(p, (int)n, nullptr, const_cast<int32_t *>(cell), off, x, false, st)
+                                     : enqueue_positions<float>(p, (int)n, nullptr, const_cast<int32_t *>(cell), off, x, false, st);
+}

@@ -1,0 +1,319 @@
+"""Thin Python binding of ``libtfsph.so`` (C ABI in ``include/tfsph.h``).
+
+Only argument marshalling lives here: every step of the method runs in the
+HIP kernels behind the C ABI.  PyTorch supplies device memory (tensors) and
+the HIP stream (``torch.cuda.current_stream()``).  If the compiled library is
+missing, every entry point raises -- there is no fallback path.
+
+Low-level functions carry the C names (``tfsph_init``, ``tfsph_step``, ...);
+``Simulation`` bundles a state, its workspace and a context.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtfsph.so")
+
+TFSPH_OK = 0
+TFSPH_F32, TFSPH_F64 = 0, 1
+TFSPH_FLAG_NONFINITE = 1
+TFSPH_FLAG_EMPTY_PHASE_CELL = 2
+
+STATUS = {0: "TFSPH_OK", -1: "TFSPH_E_INVALID_ARG", -2: "TFSPH_E_WORKSPACE", -3: "TFSPH_E_HIP",
+          -4: "TFSPH_E_UNSUPPORTED", -5: "TFSPH_E_STATE"}
+
+
+class TfsphError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_cells", ctypes.c_int32 * 3), ("box_lo", ctypes.c_double * 3),
+                ("box_hi", ctypes.c_double * 3), ("h", ctypes.c_double), ("eos", ctypes.c_int32),
+                ("c_s", ctypes.c_double), ("gamma", ctypes.c_double), ("t_stop", ctypes.c_double),
+                ("g", ctypes.c_double * 3), ("dt", ctypes.c_double), ("av_alpha", ctypes.c_double),
+                ("av_beta", ctypes.c_double), ("precision", ctypes.c_int32)]
+
+
+class PhaseC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("cell", ctypes.c_void_p), ("off", ctypes.c_void_p * 3),
+                ("vel", ctypes.c_void_p * 3), ("mass", ctypes.c_void_p), ("mass_uniform", ctypes.c_double),
+                ("rho", ctypes.c_void_p), ("energy", ctypes.c_void_p), ("id", ctypes.c_void_p)]
+
+
+class StateC(ctypes.Structure):
+    _fields_ = [("gas", PhaseC), ("dust", PhaseC)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the compiled library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1908_01682_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, P = ctypes.c_void_p, ctypes.POINTER(Params)
+        L.tfsph_status_string.restype = ctypes.c_char_p
+        L.tfsph_status_string.argtypes = [ctypes.c_int]
+        L.tfsph_last_error.restype = ctypes.c_char_p
+        L.tfsph_validate.argtypes = [P]
+        L.tfsph_workspace_size.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
+        L.tfsph_init.argtypes = [ctypes.POINTER(vp), P, ctypes.POINTER(StateC), vp, ctypes.c_size_t, vp]
+        L.tfsph_step.argtypes = [vp, ctypes.POINTER(StateC), ctypes.c_int32, vp]
+        L.tfsph_density.argtypes = [vp, ctypes.POINTER(StateC), ctypes.c_int32, vp]
+        L.tfsph_get_flags.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int64)]
+        L.tfsph_destroy.argtypes = [vp]
+        L.tfsph_positions_to_cells.argtypes = [P, ctypes.c_int64, vp, vp, ctypes.c_void_p * 3, vp]
+        L.tfsph_cells_to_positions.argtypes = [P, ctypes.c_int64, vp, ctypes.c_void_p * 3, vp, vp]
+        L.tfsph_profile.argtypes = [vp, ctypes.c_int32]
+        L.tfsph_profile_read.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64)]
+        for name in ("tfsph_validate", "tfsph_workspace_size", "tfsph_init", "tfsph_step", "tfsph_density",
+                     "tfsph_get_flags", "tfsph_destroy", "tfsph_positions_to_cells", "tfsph_cells_to_positions",
+                     "tfsph_profile", "tfsph_profile_read"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != TFSPH_OK:
+        raise TfsphError(status, where, lib().tfsph_last_error().decode())
+
+
+def _stream_handle(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+# ----------------------------------------------------------------------------
+# C-named entry points
+# ----------------------------------------------------------------------------
+
+def make_params(p, precision: int = TFSPH_F32) -> Params:
+    """``p``: an ``inputs.Params``-like object."""
+    c = Params()
+    c.dim = int(p.dim)
+    for k in range(3):
+        c.n_cells[k] = int(p.n_cells[k]) if k < p.dim else 1
+        c.box_lo[k] = float(p.lo[k])
+        c.box_hi[k] = float(p.hi[k])
+        c.g[k] = float(p.g[k])
+    c.h, c.eos, c.c_s, c.gamma = float(p.h), int(p.eos), float(p.c_s), float(p.gamma)
+    c.t_stop, c.dt = float(p.t_stop), float(p.dt)
+    c.av_alpha, c.av_beta = float(p.av_alpha), float(p.av_beta)
+    c.precision = int(precision)
+    return c
+
+
+def tfsph_validate(params: Params) -> None:
+    _check(lib().tfsph_validate(ctypes.byref(params)), "tfsph_validate")
+
+
+def tfsph_workspace_size(params: Params, n_gas: int, n_dust: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().tfsph_workspace_size(ctypes.byref(params), int(n_gas), int(n_dust), ctypes.byref(out)),
+           "tfsph_workspace_size")
+    return int(out.value)
+
+
+def tfsph_init(params: Params, state: StateC, workspace, ws_bytes: int, stream=None) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    _check(lib().tfsph_init(ctypes.byref(ctx), ctypes.byref(params), ctypes.byref(state), _ptr(workspace),
+                            int(ws_bytes), _stream_handle(stream)), "tfsph_init")
+    return ctx
+
+
+def tfsph_step(ctx, state: StateC, n_steps: int, stream=None) -> None:
+    _check(lib().tfsph_step(ctx, ctypes.byref(state), int(n_steps), _stream_handle(stream)), "tfsph_step")
+
+
+def tfsph_density(ctx, state: StateC, phase: int, stream=None) -> None:
+    _check(lib().tfsph_density(ctx, ctypes.byref(state), int(phase), _stream_handle(stream)), "tfsph_density")
+
+
+def tfsph_get_flags(ctx):
+    f = ctypes.c_uint32(0)
+    n = ctypes.c_int64(0)
+    _check(lib().tfsph_get_flags(ctx, ctypes.byref(f), ctypes.byref(n)), "tfsph_get_flags")
+    return int(f.value), int(n.value)
+
+
+TFSPH_KERNEL_UPDATE, TFSPH_KERNEL_DENSITY, TFSPH_KERNEL_BIN = 0, 1, 2
+
+
+def tfsph_profile(ctx, enable: bool) -> None:
+    _check(lib().tfsph_profile(ctx, 1 if enable else 0), "tfsph_profile")
+
+
+def tfsph_profile_read(ctx, kernel: int):
+    """(total_ms, launches) of one kernel kind since profiling was enabled."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().tfsph_profile_read(ctx, int(kernel), ctypes.byref(ms), ctypes.byref(n)), "tfsph_profile_read")
+    return float(ms.value), int(n.value)
+
+
+def tfsph_destroy(ctx) -> None:
+    if ctx:
+        _check(lib().tfsph_destroy(ctx), "tfsph_destroy")
+
+
+def tfsph_positions_to_cells(params: Params, x, cell, off, stream=None) -> None:
+    offs = (ctypes.c_void_p * 3)(*[_ptr(o) for o in off] + [None] * (3 - len(off)))
+    n = int(cell.numel())
+    _check(lib().tfsph_positions_to_cells(ctypes.byref(params), n, _ptr(x), _ptr(cell), offs,
+                                          _stream_handle(stream)), "tfsph_positions_to_cells")
+
+
+def tfsph_cells_to_positions(params: Params, cell, off, x, stream=None) -> None:
+    offs = (ctypes.c_void_p * 3)(*[_ptr(o) for o in off] + [None] * (3 - len(off)))
+    n = int(cell.numel())
+    _check(lib().tfsph_cells_to_positions(ctypes.byref(params), n, _ptr(cell), offs, _ptr(x),
+                                          _stream_handle(stream)), "tfsph_cells_to_positions")
+
+
+# ----------------------------------------------------------------------------
+# device state held in torch tensors
+# ----------------------------------------------------------------------------
+
+class DevicePhase:
+    """SoA device arrays of one phase (torch tensors)."""
+
+    def __init__(self, n, dim, dtype, device, mass_array: bool, energy: bool, rho: bool):
+        import torch
+        self.n, self.dim = n, dim
+        self.cell = torch.zeros(n, dtype=torch.int32, device=device)
+        self.off = [torch.zeros(n, dtype=dtype, device=device) for _ in range(dim)]
+        self.vel = [torch.zeros(n, dtype=dtype, device=device) for _ in range(dim)]
+        self.mass = torch.zeros(n, dtype=dtype, device=device) if mass_array else None
+        self.mass_uniform = 0.0
+        self.rho = torch.zeros(n, dtype=dtype, device=device) if rho else None
+        self.energy = torch.zeros(n, dtype=dtype, device=device) if energy else None
+        self.id = torch.zeros(n, dtype=torch.int32, device=device)
+
+    def cstruct(self) -> PhaseC:
+        c = PhaseC()
+        c.n = self.n
+        c.cell = _ptr(self.cell)
+        for d in range(3):
+            c.off[d] = _ptr(self.off[d]) if d < self.dim else None
+            c.vel[d] = _ptr(self.vel[d]) if d < self.dim else None
+        c.mass = _ptr(self.mass)
+        c.mass_uniform = float(self.mass_uniform)
+        c.rho = _ptr(self.rho)
+        c.energy = _ptr(self.energy)
+        c.id = _ptr(self.id)
+        return c
+
+    def numpy(self) -> dict:
+        """Host copy: cell, off (dim, n), vel (dim, n), mass, rho, energy, id (current order)."""
+        out = dict(cell=self.cell.cpu().numpy(), id=self.id.cpu().numpy(),
+                   off=np.stack([o.cpu().numpy() for o in self.off]) if self.dim else None,
+                   vel=np.stack([v.cpu().numpy() for v in self.vel]) if self.dim else None)
+        out["mass"] = self.mass.cpu().numpy() if self.mass is not None else np.full(self.n, self.mass_uniform)
+        out["rho"] = self.rho.cpu().numpy() if self.rho is not None else None
+        out["energy"] = self.energy.cpu().numpy() if self.energy is not None else None
+        return out
+
+    def load(self, cell, off, vel, ids, mass=None, energy=None):
+        """Copy host arrays (cell-relative form) into the device tensors."""
+        import torch
+        self.cell.copy_(torch.as_tensor(np.asarray(cell, dtype=np.int32)))
+        self.id.copy_(torch.as_tensor(np.asarray(ids, dtype=np.int32)))
+        for d in range(self.dim):
+            self.off[d].copy_(torch.as_tensor(np.asarray(off[d])).to(self.off[d].dtype))
+            self.vel[d].copy_(torch.as_tensor(np.asarray(vel[d])).to(self.vel[d].dtype))
+        if mass is not None and self.mass is not None:
+            self.mass.copy_(torch.as_tensor(np.asarray(mass)).to(self.mass.dtype))
+        if energy is not None and self.energy is not None:
+            self.energy.copy_(torch.as_tensor(np.asarray(energy)).to(self.energy.dtype))
+
+
+def _torch_dtype(precision):
+    import torch
+    return torch.float64 if precision == TFSPH_F64 else torch.float32
+
+
+class Simulation:
+    """A state + workspace + context for one problem on one GPU."""
+
+    def __init__(self, prob, precision: int = TFSPH_F32, device="cuda", stream=None, dust_rho: bool = True):
+        import torch
+        self.prob = prob
+        self.precision = precision
+        self.device = torch.device(device)
+        self.stream = stream
+        p = prob.params
+        self.params = make_params(p, precision)
+        tfsph_validate(self.params)
+        dt = _torch_dtype(precision)
+        self.dtype = dt
+        g, d = prob.gas, prob.dust
+        mg, md = g.uniform_mass(), d.uniform_mass()
+        self.gas = DevicePhase(g.n, p.dim, dt, self.device, mg is None, g.e is not None, True)
+        self.dust = DevicePhase(d.n, p.dim, dt, self.device, md is None, False, dust_rho)
+        for ph, src, mu in ((self.gas, g, mg), (self.dust, d, md)):
+            ph.mass_uniform = mu if mu is not None else 0.0
+            self._upload(ph, src)
+        self.state = StateC(self.gas.cstruct(), self.dust.cstruct())
+        self.ws_bytes = tfsph_workspace_size(self.params, g.n, d.n)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_off = (-base) % 256
+        self._ws = self.workspace[self._ws_off:]
+        self.ctx = tfsph_init(self.params, self.state, self._ws, self.ws_bytes, stream)
+
+    def _upload(self, ph: DevicePhase, src):
+        import torch
+        x = torch.as_tensor(np.ascontiguousarray(src.x.T), dtype=torch.float64).to(self.device)
+        tfsph_positions_to_cells(self.params, x, ph.cell, ph.off, self.stream)
+        for k in range(ph.dim):
+            ph.vel[k].copy_(torch.as_tensor(src.v[:, k]).to(ph.vel[k].dtype))
+        ph.id.copy_(torch.as_tensor(src.id.astype(np.int32)))
+        if ph.mass is not None:
+            ph.mass.copy_(torch.as_tensor(src.m).to(ph.mass.dtype))
+        if ph.energy is not None:
+            ph.energy.copy_(torch.as_tensor(src.e).to(ph.energy.dtype))
+
+    def step(self, n: int = 1) -> None:
+        tfsph_step(self.ctx, self.state, n, self.stream)
+
+    def density(self, phase: int) -> None:
+        tfsph_density(self.ctx, self.state, phase, self.stream)
+
+    def flags(self):
+        return tfsph_get_flags(self.ctx)
+
+    def positions(self, phase: int = 0) -> np.ndarray:
+        import torch
+        ph = self.gas if phase == 0 else self.dust
+        x = torch.empty(ph.dim * ph.n, dtype=torch.float64, device=self.device)
+        tfsph_cells_to_positions(self.params, ph.cell, ph.off, x, self.stream)
+        return x.view(ph.dim, ph.n).cpu().numpy().T
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            tfsph_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,120 @@
+"""Host-only checks of the C ABI: symbols, parameter validation, workspace sizing.
+
+No device call is made here, so these run on a machine without a GPU.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1908_01682_amd import inputs as I
+from paper_1908_01682_amd import tfsph as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for hdr in os.listdir(os.path.join(ROOT, "include")):
+        if not hdr.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", hdr)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"^[A-Za-z_][\w \*]*?\b(tfsph_\w+)\s*\(", src, flags=re.M))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(T.LIB_PATH):
+        from paper_1908_01682_amd import build
+        build.build(verbose=False)
+    return T.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 10, names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_no_cpu_fallback_symbols_or_torch_in_abi():
+    src = open(os.path.join(ROOT, "include", "tfsph.h")).read()
+    assert "torch" not in src.lower() and "at::" not in src
+
+
+def _good(dim=1, precision=T.TFSPH_F32):
+    prob = I.workload("wave1d") if dim == 1 else I.wave_2d(n_side=64)
+    return T.make_params(prob.params, precision)
+
+
+def _status(p):
+    return T.lib().tfsph_validate(ctypes.byref(p))
+
+
+def test_validate_accepts_workloads(lib):
+    for prob in (I.workload("wave1d"), I.dusty_shock(n=2000), I.wave_2d(n_side=64),
+                 I.dusty_box(n_side=16, cells_per_axis=8)):
+        assert _status(T.make_params(prob.params)) == 0, T.lib().tfsph_last_error()
+
+
+@pytest.mark.parametrize("field,value", [
+    ("dim", 0), ("dim", 4), ("h", 0.0), ("h", float("nan")), ("t_stop", 0.0), ("t_stop", -1.0),
+    ("dt", 0.0), ("dt", float("inf")), ("c_s", 0.0), ("eos", 7), ("precision", 3), ("av_alpha", -1.0),
+])
+def test_validate_rejects_bad_scalars(lib, field, value):
+    p = _good()
+    setattr(p, field, value)
+    assert _status(p) == -1
+    assert len(T.lib().tfsph_last_error()) > 0
+
+
+def test_validate_rejects_bad_geometry(lib):
+    p = _good()
+    p.n_cells[1] = 2            # unused axis must be 1
+    assert _status(p) == -1
+    p = _good()
+    p.box_hi[0] = p.box_lo[0]
+    assert _status(p) == -1
+    p = _good()
+    p.n_cells[0], p.h = 4, 0.2  # 2h / Delta = 1.6: window of 2 cells needs >= 5 cells
+    assert _status(p) == -1
+    p.n_cells[0] = 5
+    assert _status(p) == 0
+    p = _good()
+    p.h = 0.5                   # 2h spans 100 cells: window too large
+    assert _status(p) == -1
+    p = _good()
+    p.eos, p.gamma = 1, 1.0
+    assert _status(p) == -1
+
+
+def test_workspace_size(lib):
+    p = _good()
+    a = T.tfsph_workspace_size(p, 200, 200)
+    b = T.tfsph_workspace_size(p, 400, 400)
+    assert 0 < a < b
+    p64 = _good(precision=T.TFSPH_F64)
+    assert T.tfsph_workspace_size(p64, 200, 200) > a
+    assert T.tfsph_workspace_size(p, 0, 0) > 0
+    with pytest.raises(T.TfsphError):
+        T.tfsph_workspace_size(p, -1, 5)
+
+
+def test_init_rejects_bad_arguments_before_any_device_work(lib):
+    p = _good()
+    st = T.StateC()
+    st.gas.n = 10
+    st.dust.n = 10
+    ctx = ctypes.c_void_p()
+    # NULL arrays
+    r = T.lib().tfsph_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.byref(st), None, 0, None)
+    assert r == -1 and not ctx.value
+    # NULL state
+    r = T.lib().tfsph_init(ctypes.byref(ctx), ctypes.byref(p), None, None, 0, None)
+    assert r == -1
+    # NULL ctx pointer for step
+    assert T.lib().tfsph_step(None, ctypes.byref(st), 1, None) == -1
+    assert T.lib().tfsph_status_string(-2) == b"TFSPH_E_WORKSPACE"

@@ -1,0 +1,292 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Integer work (cell indices, carry rule, canonical order) must match bit for
+bit; floating point within the stated normalised tolerance: 1e-5 per step in
+FP32 (1e-11 in FP64), 1e-3 relative L2 over 1000 steps.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1908_01682_amd import inputs as I
+from tests.gpu_util import HAVE_GPU, banner, by_id, compare_states, needs_gpu, oracle_phase
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+if HAVE_GPU:
+    import torch
+    from paper_1908_01682_amd import tfsph as T
+
+
+TOL32 = 1e-5
+TOL64 = 1e-11
+
+
+def _sim(prob, precision):
+    banner(f"{prob.name} n=({prob.gas.n},{prob.dust.n}) precision={precision}")
+    return T.Simulation(prob, precision=precision)
+
+
+def _step_parity(orc, prob, precision, nsteps=1):
+    sim = _sim(prob, precision)
+    p = prob.params
+    g0, d0 = sim.gas.numpy(), sim.dust.numpy()
+    og, od = oracle_phase(orc, g0, p.dim), oracle_phase(orc, d0, p.dim)
+    orc.step(p, og, od, nsteps)
+    sim.step(nsteps)
+    torch.cuda.synchronize()
+    err = compare_states(p, sim.gas.numpy(), sim.dust.numpy(), og, od, p.c_s)
+    flags, _ = sim.flags()
+    sim.close()
+    return err, flags
+
+
+def _cases():
+    rng = np.random.default_rng(9)
+    out = [
+        ("wave1d", lambda: I.workload("wave1d"), 1),
+        ("wave1d_f32", lambda: I.workload("wave1d"), 0),
+        ("wave1d_big_amp_f32", lambda: I.dusty_wave(n_side=200, amp=1e-2, t_stop=1e-3, cells_per_axis=100), 0),
+        ("shock_ts1e-1", lambda: I.dusty_shock(n=4000, t_stop=1e-1), 0),
+        ("shock_ts1e-3", lambda: I.dusty_shock(n=4000, t_stop=1e-3), 0),
+        ("shock_ts1e-5", lambda: I.dusty_shock(n=4000, t_stop=1e-5), 0),
+        ("shock_ts1e-3_f64", lambda: I.dusty_shock(n=4000, t_stop=1e-3), 1),
+        ("shock_ragged_tiles", lambda: I.dusty_shock(n=10002, t_stop=1e-3), 0),   # 5001 cells: 3 scan tiles
+        ("box3d_small", lambda: I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4), 0),
+        ("box3d_small_f64", lambda: I.dusty_box(n_side=24, cells_per_axis=12, regions_per_axis=4), 1),
+        ("wave2d_small", lambda: I.wave_2d(n_side=64), 0),
+        ("batched_instance", lambda: I.batched_waves(n_inst=3, n_min=900, n_max=1200, seed=int(rng.integers(1 << 30)))[2], 0),
+    ]
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name,make,precision", CASES, ids=[c[0] for c in CASES])
+def test_one_step_parity(orc, name, make, precision):
+    prob = make()
+    err, flags = _step_parity(orc, prob, precision, 1)
+    tol = TOL64 if precision == 1 else TOL32
+    assert all(v <= tol for v in err.values()), err
+    assert not (flags & T.TFSPH_FLAG_NONFINITE)
+
+
+@pytest.mark.parametrize("name,make,precision", [CASES[0], CASES[3], CASES[8], CASES[10]],
+                         ids=["wave1d", "shock", "box3d", "wave2d"])
+def test_five_step_parity(orc, name, make, precision):
+    """Several steps: binning of moved particles, re-sorting and reuse of the workspace."""
+    prob = make()
+    err, _ = _step_parity(orc, prob, precision, 5)
+    tol = TOL64 if precision == 1 else 5 * TOL32
+    assert all(v <= tol for v in err.values()), err
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b - np.mean(b)), 1e-300))
+
+
+@pytest.mark.parametrize("precision,amp", [(1, 1e-4), (0, 1e-2)], ids=["fp64_amp1e-4", "fp32_amp1e-2"])
+def test_long_run_wave1d(orc, precision, amp):
+    """1000 steps of the 1D dusty wave: relative L2 of every field within 1e-3."""
+    prob = I.dusty_wave(n_side=200, amp=amp, t_stop=1e-3, cells_per_axis=100, steps=1000)
+    p = prob.params
+    sim = _sim(prob, precision)
+    og, od = oracle_phase(orc, sim.gas.numpy(), 1), oracle_phase(orc, sim.dust.numpy(), 1)
+    orc.step(p, og, od, 1000)
+    sim.step(1000)
+    torch.cuda.synchronize()
+    G, D = by_id(sim.gas.numpy()), by_id(sim.dust.numpy())
+    og, od = og.by_id(), od.by_id()
+    errs = {
+        "v": _rel_l2(G["vel"][0], og.vel[0]),
+        "u": _rel_l2(D["vel"][0], od.vel[0]),
+        "rho": _rel_l2(G["rho"], og.rho),
+        "x_gas": _rel_l2(sim.positions(0)[np.argsort(sim.gas.numpy()["id"]), 0], orc.positions(p, og)[:, 0]),
+    }
+    sim.close()
+    bound = 1e-9 if precision == 1 else 1e-3
+    assert all(v <= bound for v in errs.values()), errs
+
+
+def _low_level_init(prob, precision, cell, off, vel, ids):
+    """tfsph_init on host-supplied (cell, off) arrays (possibly non-canonical)."""
+    p = prob.params
+    params = T.make_params(p, precision)
+    dt = torch.float64 if precision == 1 else torch.float32
+    dev = torch.device("cuda")
+    phases = []
+    for k in range(2):
+        ph = T.DevicePhase(len(ids[k]), p.dim, dt, dev, False, False, True)
+        ph.mass_uniform = 1.0
+        ph.load(cell[k], off[k], vel[k], ids[k])
+        phases.append(ph)
+    st = T.StateC(phases[0].cstruct(), phases[1].cstruct())
+    nbytes = T.tfsph_workspace_size(params, phases[0].n, phases[1].n)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    ctx = T.tfsph_init(params, st, ws, nbytes)
+    torch.cuda.synchronize()
+    out = [ph.numpy() for ph in phases]
+    T.tfsph_destroy(ctx)
+    return out
+
+
+@pytest.mark.parametrize("dim,precision", [(1, 0), (2, 0), (3, 0), (3, 1)])
+def test_binning_bit_exact(orc, dim, precision):
+    """Carry rule, periodic wrap, linear index and (cell, id) order equal the numpy
+    definition evaluated in the kernel's precision, bit for bit."""
+    rng = np.random.default_rng(100 + dim)
+    nc = {1: (3000, 1, 1), 2: (70, 50, 1), 3: (24, 20, 18)}[dim]
+    p = I.Params(dim=dim, n_cells=nc, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), h=0.2 / max(nc))
+    npdt = np.float64 if precision == 1 else np.float32
+    D = [npdt((p.hi[k] - p.lo[k]) / nc[k]) for k in range(dim)]
+    cells, offs, vels, idss = [], [], [], []
+    for k, n in enumerate((50_000, 37_001)):
+        ncell = int(np.prod(nc[:dim]))
+        cell = rng.integers(0, ncell, n)
+        off = np.stack([(rng.uniform(-2.5, 3.5, n) * D[a]).astype(npdt) for a in range(dim)])
+        # exact faces, zeros and values one ulp below Delta
+        off[0, :50] = 0
+        off[0, 50:100] = D[0]
+        off[0, 100:150] = np.nextafter(D[0], npdt(0))
+        off[0, 150:200] = -np.nextafter(npdt(0), npdt(1))
+        vel = rng.standard_normal((dim, n)).astype(npdt)
+        ids = rng.permutation(n).astype(np.int32) * 3 + k
+        cells.append(cell), offs.append(off), vels.append(vel), idss.append(ids)
+    banner(f"binning dim={dim} precision={precision}")
+    out = _low_level_init(I.Problem("bin", p, None, None, 0), precision, cells, offs, vels, idss)
+    for k in range(2):
+        ref = orc.bin_reference(p, cells[k], offs[k], idss[k], dtype=npdt)
+        perm = ref["perm"]
+        assert np.array_equal(out[k]["cell"], ref["cell"][perm])
+        assert np.array_equal(out[k]["id"], idss[k][perm])
+        got_off = out[k]["off"].view(np.uint64 if precision == 1 else np.uint32)
+        ref_off = np.ascontiguousarray(ref["off"][:, perm]).view(np.uint64 if precision == 1 else np.uint32)
+        assert np.array_equal(got_off, ref_off)
+        assert np.array_equal(out[k]["vel"], vels[k][:, perm])
+        assert np.all(np.diff(out[k]["cell"]) >= 0)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_positions_to_cells(orc, dim):
+    """FP64 absolute positions -> (cell, offset): cell = floor in FP64, then the FP32
+    carry rule on the rounded offset, bit for bit."""
+    rng = np.random.default_rng(7 + dim)
+    nc = (50, 40, 30)[:dim] + (1,) * (3 - dim)
+    p = I.Params(dim=dim, n_cells=nc, lo=(-0.3, 0.1, 2.0), hi=(0.7, 1.1, 4.0), h=0.005)
+    n = 20000
+    x = np.stack([rng.uniform(p.lo[k] - 1.0, p.hi[k] + 1.0, n) for k in range(dim)], axis=1)
+    params = T.make_params(p, 0)
+    xt = torch.as_tensor(np.ascontiguousarray(x.T)).cuda()
+    cell = torch.zeros(n, dtype=torch.int32, device="cuda")
+    off = [torch.zeros(n, dtype=torch.float32, device="cuda") for _ in range(dim)]
+    T.tfsph_positions_to_cells(params, xt, cell, off)
+    torch.cuda.synchronize()
+    ref64 = orc.from_positions(p, x, np.zeros((n, dim)), np.ones(n), np.arange(n))
+    # the oracle's floor result, rounded to FP32 and carried in FP32
+    # (undo the oracle's FP64 carry: recompute floor cells exactly as the kernel does)
+    D = np.array([(p.hi[k] - p.lo[k]) / nc[k] for k in range(dim)])
+    rel = x - np.array(p.lo[:dim])
+    k = np.floor(rel / D)
+    o32 = (rel - k * D).astype(np.float32)
+    kk = np.mod(k.astype(np.int64), np.array(nc[:dim]))
+    lin = kk[:, 0].copy()
+    if dim > 1:
+        lin += nc[0] * kk[:, 1]
+    if dim > 2:
+        lin += nc[0] * nc[1] * kk[:, 2]
+    ref = orc.bin_reference(p, lin, o32.T, np.arange(n), dtype=np.float32)
+    assert np.array_equal(cell.cpu().numpy(), ref["cell"])
+    got = np.stack([o.cpu().numpy() for o in off])
+    assert np.array_equal(got.view(np.uint32), np.ascontiguousarray(ref["off"]).view(np.uint32))
+    # and it is the floor binning of the oracle except within FP32 rounding of a face
+    agree = np.mean(cell.cpu().numpy() == ref64.cell)
+    assert agree > 0.999
+
+
+def test_run_twice_bitwise_and_input_order_invariance():
+    prob = I.dusty_box(n_side=24, cells_per_axis=12, regions_per_axis=4)
+    rng = np.random.default_rng(1)
+    shuffled = prob.copy()
+    for ph in (shuffled.gas, shuffled.dust):
+        o = rng.permutation(ph.n)
+        ph.x, ph.v, ph.m, ph.id = ph.x[o], ph.v[o], ph.m[o], ph.id[o]
+    res = []
+    for pr in (prob, prob, shuffled):
+        sim = _sim(pr, 0)
+        sim.step(10)
+        torch.cuda.synchronize()
+        res.append((sim.gas.numpy(), sim.dust.numpy()))
+        sim.close()
+    for other in res[1:]:
+        for a, b in zip(res[0], other):
+            for k in ("cell", "id", "off", "vel", "mass"):
+                assert np.array_equal(a[k], b[k]), k
+
+
+def test_one_phase_cells_and_empty_dust(orc):
+    """Cells holding one phase only get no drag and are counted like the oracle counts them."""
+    prob = I.dusty_shock(n=3000, t_stop=1e-3)
+    # thin the dust so that many cells hold gas only
+    keep = np.arange(prob.dust.n) % 3 == 0
+    prob.dust = I.Phase(prob.dust.x[keep], prob.dust.v[keep], prob.dust.m[keep], prob.dust.id[keep])
+    sim = _sim(prob, 1)
+    og, od = oracle_phase(orc, sim.gas.numpy(), 1), oracle_phase(orc, sim.dust.numpy(), 1)
+    n_one = orc.step(prob.params, og, od, 1)
+    sim.step(1)
+    flags, count = sim.flags()
+    err = compare_states(prob.params, sim.gas.numpy(), sim.dust.numpy(), og, od, prob.params.c_s)
+    sim.close()
+    assert n_one > 0 and count == n_one
+    assert flags & T.TFSPH_FLAG_EMPTY_PHASE_CELL
+    assert all(v <= TOL64 for v in err.values()), err
+
+
+def test_gas_only_and_dust_only(orc):
+    prob = I.dusty_wave(n_side=100, amp=1e-2, cells_per_axis=50)
+    for drop in ("dust", "gas"):
+        pr = prob.copy()
+        empty = I.Phase(np.zeros((0, 1)), np.zeros((0, 1)), np.zeros(0), np.zeros(0, dtype=np.int32))
+        setattr(pr, drop, empty)
+        sim = _sim(pr, 1)
+        og, od = oracle_phase(orc, sim.gas.numpy(), 1), oracle_phase(orc, sim.dust.numpy(), 1)
+        orc.step(pr.params, og, od, 3)
+        sim.step(3)
+        err = compare_states(pr.params, sim.gas.numpy(), sim.dust.numpy(), og, od, pr.params.c_s)
+        sim.close()
+        assert all(v <= TOL64 for v in err.values()), (drop, err)
+
+
+def test_nonfinite_is_flagged_and_contained():
+    """A NaN velocity planted from the host is reported; cell indices stay valid."""
+    prob = I.dusty_wave(n_side=200, amp=1e-2, cells_per_axis=100)
+    sim = _sim(prob, 0)
+    sim.gas.vel[0][17] = float("nan")
+    sim.step(2)
+    flags, _ = sim.flags()
+    cells = sim.gas.numpy()["cell"]
+    sim.close()
+    assert flags & T.TFSPH_FLAG_NONFINITE
+    assert cells.min() >= 0 and cells.max() < 100
+
+
+def test_dust_density_diagnostic(orc):
+    prob = I.wave_2d(n_side=48, amp=1e-2)
+    sim = _sim(prob, 0)
+    od = oracle_phase(orc, sim.dust.numpy(), 2)
+    rho_ref = orc.density(prob.params, od)
+    sim.density(1)
+    got = by_id(sim.dust.numpy())
+    sim.close()
+    order = np.argsort(od.id)
+    assert np.max(np.abs(got["rho"] - rho_ref[order])) <= TOL32 * np.max(rho_ref)
+
+
+@pytest.mark.parametrize("name", ["box3d", "shock1d", "wave2d"])
+def test_full_size_one_step(orc, name):
+    """Full workload sizes, the launch configuration the benchmark times: one step."""
+    prob = I.workload(name)
+    err, flags = _step_parity(orc, prob, 0, 1)
+    assert all(v <= TOL32 for v in err.values()), err
+    assert not (flags & T.TFSPH_FLAG_NONFINITE)
