@@ -47,6 +47,29 @@ __global__ void __launch_bounds__(kBlock) k_fill_zero(int *a, int na, int *b, in
 }
 
 // --- histogram + slot claim (both phases in one grid) ---------------------------
+// Lanes of a wave usually hold a few runs of equal cell keys (the arrays are in
+// the previous step's cell order), so each run claims its slots with one atomic
+// issued by its first lane; slot = base + position inside the run.
+__device__ __forceinline__ int claim_slot(int *count, int key)
+{
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || key != prev;
+    int s = head ? lane : 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(s, off, 64);
+        if (lane >= off) s = max(s, t);
+    }
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long above = s == 63 ? 0ull : (heads & ~((2ull << s) - 1ull));
+    const int next = above ? __ffsll((long long)above) - 1 : 64;
+    int base = 0;
+    if (head && key >= 0) base = atomicAdd(count + key, next - s);
+    base = __shfl(base, s, 64);
+    return base + (lane - s);
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_count(const int *cell_g, int n_g, int *count_g, int *slot_g,
         const int *cell_d, int n_d, int *count_d, int *slot_d, int blocks_g, int ncell, unsigned int *flags)
@@ -54,13 +77,14 @@ k_count(const int *cell_g, int n_g, int *count_g, int *slot_g,
     const bool gas = int(blockIdx.x) < blocks_g;
     const int i = (gas ? blockIdx.x : blockIdx.x - blocks_g) * kBlock + threadIdx.x;
     const int n = gas ? n_g : n_d;
-    if (i >= n) return;
-    const int raw = gas ? cell_g[i] : cell_d[i];
-    const int c = safe_cell(raw, ncell);
-    if (c != raw) atomicOr(flags, 4u);
-    int *count = gas ? count_g : count_d;
-    const int s = atomicAdd(count + c, 1);
-    (gas ? slot_g : slot_d)[i] = s;
+    int key = -1;
+    if (i < n) {
+        const int raw = gas ? cell_g[i] : cell_d[i];
+        key = safe_cell(raw, ncell);
+        if (key != raw) atomicOr(flags, 4u);
+    }
+    const int s = claim_slot(gas ? count_g : count_d, key);
+    if (i < n) (gas ? slot_g : slot_d)[i] = s;
 }
 
 // --- block-wide exclusive scan of one int per thread (256 threads, wave64) ----
@@ -194,11 +218,12 @@ __device__ __forceinline__ void rank_gather_one(const Geom<R> &G, const Phase<R>
     const int dst = b + rank;
     S.cell[dst] = c;
     S.id[dst] = myid;
+    R o[3] = {R(0), R(0), R(0)};
     for (int d = 0; d < G.dim; ++d) {
-        S.off[d][dst] = P.off[d][i];
+        o[d] = P.off[d][i];
         S.vel[d][dst] = P.vel[d][i];
     }
-    if (S.mass) S.mass[dst] = P.mass[i];
+    S.pos[dst] = mk4<R>(o[0], o[1], o[2], P.mass ? P.mass[i] : P.m_uniform);
     if (S.energy) S.energy[dst] = P.energy[i];
 }
 
@@ -223,11 +248,13 @@ __global__ void __launch_bounds__(kBlock) k_copy_back(Geom<R> G, Sorted<R> S, Ph
     if (j >= S.n) return;
     P.cell[j] = S.cell[j];
     P.id[j] = S.id[j];
+    const R4<R> q = S.pos[j];
+    const R o[3] = {q.x, q.y, q.z};
     for (int d = 0; d < G.dim; ++d) {
-        P.off[d][j] = S.off[d][j];
+        P.off[d][j] = o[d];
         P.vel[d][j] = S.vel[d][j];
     }
-    if (S.mass) const_cast<R *>(P.mass)[j] = S.mass[j];
+    if (S.has_mass && P.mass) const_cast<R *>(P.mass)[j] = q.w;
     if (S.energy) P.energy[j] = S.energy[j];
     if (with_rho && P.rho) P.rho[j] = S.rho[j];
 }

@@ -83,20 +83,47 @@ struct Phase {
     int *id;
 };
 
+// Packed 4-vectors: float4 / double4.
+template <typename R> struct V4;
+template <> struct V4<float> { using T = float4; };
+template <> struct V4<double> { using T = double4; };
+template <typename R> using R4 = typename V4<R>::T;
+
+template <typename R>
+__device__ __forceinline__ R4<R> mk4(R a, R b, R c, R d)
+{
+    R4<R> v;
+    v.x = a;
+    v.y = b;
+    v.z = c;
+    v.w = d;
+    return v;
+}
+
+// Hardware square root / reciprocal square root / reciprocal in FP32 (about
+// 1 ulp); exact IEEE operations in FP64.
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+
 // Workspace arrays of one phase: the step's canonical (cell, id) ordered copy
-// plus binning scratch.
+// plus binning scratch.  Offsets and mass travel packed as pos = (ox, oy, oz, m)
+// so one 16-byte load serves a neighbour candidate; the gas force pass reads
+// frc = (ox, oy, oz, p / rho^2) written by the density pass.
 template <typename R>
 struct Sorted {
     int n;
+    int has_mass;        // per-particle masses (copied back to the caller)
     int *cell;
-    R *off[3];
+    R4<R> *pos;          // (ox, oy, oz, m)
+    R4<R> *frc;          // gas: (ox, oy, oz, p / rho^2)
     R *vel[3];
-    R *mass;             // nullable
-    R m_uniform;
     R *energy;           // nullable
     int *id;
     R *rho;              // summation density
-    R *prs;              // p / rho^2 (gas)
     R *vt[3];            // predictor velocity v~ (gas)
     int *count;          // [ncell] histogram
     int *start;          // [ncell + 1] exclusive offsets

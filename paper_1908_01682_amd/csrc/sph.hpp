@@ -15,12 +15,13 @@
 
 namespace tfsph {
 
-// Visit every particle of phase (start, off) in the neighbour window of a
-// point with offsets oa[] in cell (cx, cy, cz).  fn(b, rx, ry, rz) gets
-// r = x_a - x_b.  Order: window z, y, x offsets ascending, then cell order.
+// Visit every particle of a phase in the neighbour window of a point with
+// offsets oa[] in cell (cx, cy, cz).  fn(b, q, rx, ry, rz) gets the packed
+// record q = data[b] and r = x_a - x_b.  Order: window z, y, x offsets
+// ascending, then cell order.
 template <typename R, int DIM, typename Fn>
 __device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
-                                           const int *__restrict__ start, R *const off[3], Fn &&fn)
+                                           const int *__restrict__ start, const R4<R> *__restrict__ data, Fn &&fn)
 {
     const int wz = DIM > 2 ? G.win[2] : 0;
     const int wy = DIM > 1 ? G.win[1] : 0;
@@ -39,10 +40,11 @@ __device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int
                 const int b0 = start[lin];
                 const int b1 = start[lin + 1];
                 for (int b = b0; b < b1; ++b) {
-                    const R rx = rx0 - off[0][b];
-                    const R ry = DIM > 1 ? ry0 - off[1][b] : R(0);
-                    const R rz = DIM > 2 ? rz0 - off[2][b] : R(0);
-                    fn(b, rx, ry, rz);
+                    const R4<R> q = data[b];
+                    const R rx = rx0 - q.x;
+                    const R ry = DIM > 1 ? ry0 - q.y : R(0);
+                    const R rz = DIM > 2 ? rz0 - q.z : R(0);
+                    fn(b, q, rx, ry, rz);
                 }
             }
         }
@@ -69,30 +71,27 @@ __device__ __forceinline__ R density_at(const Geom<R> &G, const Sorted<R> &S, in
 {
     int cx, cy, cz;
     split_cell(G, S.cell[a], cx, cy, cz);
-    R oa[3] = {S.off[0][a], DIM > 1 ? S.off[1][a] : R(0), DIM > 2 ? S.off[2][a] : R(0)};
+    const R4<R> me = S.pos[a];
+    const R oa[3] = {me.x, me.y, me.z};
     R acc = R(0);
-    const R *mass = S.mass;
-    const R mu = S.m_uniform;
-    for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.off, [&](int b, R rx, R ry, R rz) {
+    for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz) {
         const R r2 = rx * rx + ry * ry + rz * rz;
-        if (r2 < G.support2) {
-            const R q = sqrt(r2) * G.inv_h;
-            acc += mass_of(mass, mu, b) * spline_f(q);
-        }
+        if (r2 < G.support2) acc += q.w * spline_f(fsqrt(r2) * G.inv_h);
     });
     return acc * G.wnorm;
 }
 
 template <typename R, int DIM>
-__global__ void __launch_bounds__(kBlock) k_density(Geom<R> G, Phys<R> Ph, Sorted<R> S, int want_prs)
+__global__ void __launch_bounds__(kBlock) k_density(Geom<R> G, Phys<R> Ph, Sorted<R> S, int want_frc)
 {
     const int a = blockIdx.x * kBlock + threadIdx.x;
     if (a >= S.n) return;
     const R rho = density_at<R, DIM>(G, S, a);
     S.rho[a] = rho;
-    if (want_prs) {
+    if (want_frc) {
         const R e = S.energy ? S.energy[a] : R(0);
-        S.prs[a] = pressure_of(Ph, rho, e) / (rho * rho);
+        const R4<R> me = S.pos[a];
+        S.frc[a] = mk4<R>(me.x, me.y, me.z, pressure_of(Ph, rho, e) / (rho * rho));
     }
 }
 
@@ -110,17 +109,20 @@ __device__ __forceinline__ void gas_force_at(const Geom<R> &G, const Phys<R> &Ph
 {
     int cx, cy, cz;
     split_cell(G, S.cell[a], cx, cy, cz);
-    R oa[3] = {S.off[0][a], DIM > 1 ? S.off[1][a] : R(0), DIM > 2 ? S.off[2][a] : R(0)};
-    const R Pa = S.prs[a];
-    const R *mass = S.mass;
-    const R mu_m = S.m_uniform;
+    const R4<R> me = S.frc[a];
+    const R oa[3] = {me.x, me.y, me.z};
+    const R Pa = me.w;
+    const bool per_mass = S.has_mass != 0;
+    const R4<R> *pos = S.pos;
+    const R mu_m = S.pos[a].w;        // uniform mass (only used when !per_mass)
     R ax = R(0), ay = R(0), az = R(0), de = R(0);
     if (!Ph.av && Ph.eos == 0) {
-        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.off, [&](int b, R rx, R ry, R rz) {
+        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz) {
             const R r2 = rx * rx + ry * ry + rz * rz;
             if (r2 < G.support2 && r2 > R(0)) {
-                const R r = sqrt(r2);
-                const R fac = mass_of(mass, mu_m, b) * (Pa + S.prs[b]) * spline_df(r * G.inv_h) / r;
+                const R ir = frsq(r2);
+                const R mb = per_mass ? pos[b].w : mu_m;
+                const R fac = mb * (Pa + q.w) * spline_df(r2 * ir * G.inv_h) * ir;
                 ax -= fac * rx;
                 ay -= fac * ry;
                 az -= fac * rz;
@@ -130,11 +132,11 @@ __device__ __forceinline__ void gas_force_at(const Geom<R> &G, const Phys<R> &Ph
         const R va[3] = {S.vel[0][a], DIM > 1 ? S.vel[1][a] : R(0), DIM > 2 ? S.vel[2][a] : R(0)};
         const R rhoa = S.rho[a];
         const R ca = sound_of(Ph, S.energy ? S.energy[a] : R(0));
-        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.off, [&](int b, R rx, R ry, R rz) {
+        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz) {
             const R r2 = rx * rx + ry * ry + rz * rz;
             if (r2 < G.support2 && r2 > R(0)) {
-                const R r = sqrt(r2);
-                const R gfac = spline_df(r * G.inv_h) / r;   // grad_a W = gfac * gnorm * r_vec
+                const R ir = frsq(r2);
+                const R gfac = spline_df(r2 * ir * G.inv_h) * ir;   // grad_a W = gfac * gnorm * r_vec
                 const R vx = va[0] - S.vel[0][b];
                 const R vy = DIM > 1 ? va[1] - S.vel[1][b] : R(0);
                 const R vz = DIM > 2 ? va[2] - S.vel[2][b] : R(0);
@@ -147,8 +149,8 @@ __device__ __forceinline__ void gas_force_at(const Geom<R> &G, const Phys<R> &Ph
                     const R rbar = R(0.5) * (rhoa + S.rho[b]);
                     Pi = (-Ph.av_alpha * cbar * mu + Ph.av_beta * mu * mu) / rbar;
                 }
-                const R mb = mass_of(mass, mu_m, b);
-                const R fac = mb * (Pa + S.prs[b] + Pi) * gfac;
+                const R mb = per_mass ? pos[b].w : mu_m;
+                const R fac = mb * (Pa + q.w + Pi) * gfac;
                 ax -= fac * rx;
                 ay -= fac * ry;
                 az -= fac * rz;
@@ -186,13 +188,13 @@ __device__ __forceinline__ bool solve_cell(const Phys<R> &Ph, const Sorted<R> &S
     R Mg = R(0), Md = R(0);
     R Pg[3] = {R(0), R(0), R(0)}, Pd[3] = {R(0), R(0), R(0)};
     for (int a = g0; a < g1; ++a) {
-        const R m = mass_of(Sg.mass, Sg.m_uniform, a);
+        const R m = Sg.pos[a].w;
         Mg += m;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) Pg[d] += m * Sg.vt[d][a];
     }
     for (int j = d0; j < d1; ++j) {
-        const R m = mass_of(Sd.mass, Sd.m_uniform, j);
+        const R m = Sd.pos[j].w;
         Md += m;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) Pd[d] += m * (Sd.vel[d][j] + Ph.tau * Ph.g[d]);
@@ -267,11 +269,13 @@ k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R
         const R inv = R(1) / (R(1) + C.alpha);
         int cc[3];
         split_cell(G, c, cc[0], cc[1], cc[2]);
+        const R4<R> me = Sg.pos[a];
+        const R oo[3] = {me.x, me.y, me.z};
         bool ok = true;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
             const R v = (Sg.vt[d][a] + C.alpha * C.U[d]) * inv;
-            R o = Sg.off[d][a] + Ph.tau * v;
+            R o = oo[d] + Ph.tau * v;
             ok &= finite_r(v);
             ok &= carry(o, cc[d], G.delta[d], G.nc[d]);
             Pg.vel[d][a] = v;
@@ -279,7 +283,7 @@ k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R
         }
         Pg.cell[a] = join_cell(G, cc[0], cc[1], cc[2]);
         Pg.id[a] = Sg.id[a];
-        if (Sg.mass) const_cast<R *>(Pg.mass)[a] = Sg.mass[a];
+        if (Sg.has_mass && Pg.mass) const_cast<R *>(Pg.mass)[a] = me.w;
         Pg.rho[a] = Sg.rho[a];
         bad |= !ok;
     }
@@ -290,12 +294,14 @@ k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R
         const R inv = R(1) / (R(1) + C.beta);
         int cc[3];
         split_cell(G, c, cc[0], cc[1], cc[2]);
+        const R4<R> me = Sd.pos[j];
+        const R oo[3] = {me.x, me.y, me.z};
         bool ok = true;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
             const R ut = Sd.vel[d][j] + Ph.tau * Ph.g[d];
             const R u = (ut + C.beta * C.V[d]) * inv;
-            R o = Sd.off[d][j] + Ph.tau * u;
+            R o = oo[d] + Ph.tau * u;
             ok &= finite_r(u);
             ok &= carry(o, cc[d], G.delta[d], G.nc[d]);
             Pd.vel[d][j] = u;
@@ -303,7 +309,7 @@ k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R
         }
         Pd.cell[j] = join_cell(G, cc[0], cc[1], cc[2]);
         Pd.id[j] = Sd.id[j];
-        if (Sd.mass) const_cast<R *>(Pd.mass)[j] = Sd.mass[j];
+        if (Sd.has_mass && Pd.mass) const_cast<R *>(Pd.mass)[j] = me.w;
         bad |= !ok;
     }
     if (bad) atomicOr(&s_bad, 1);

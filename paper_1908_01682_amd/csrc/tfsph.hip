@@ -133,22 +133,21 @@ struct PhaseFlags {
 };
 
 template <typename R>
-Sorted<R> carve_phase(Carver &cv, int n, int dim, int ncell, PhaseFlags f, R m_uniform)
+Sorted<R> carve_phase(Carver &cv, int n, int dim, int ncell, PhaseFlags f)
 {
     Sorted<R> S{};
     S.n = n;
+    S.has_mass = f.mass ? 1 : 0;
     S.cell = cv.take<int>(n);
     S.id = cv.take<int>(n);
+    S.pos = cv.take<R4<R>>(n);
+    S.frc = f.prs ? cv.take<R4<R>>(n) : nullptr;
     for (int d = 0; d < 3; ++d) {
-        S.off[d] = d < dim ? cv.take<R>(n) : nullptr;
         S.vel[d] = d < dim ? cv.take<R>(n) : nullptr;
         S.vt[d] = (f.prs && d < dim) ? cv.take<R>(n) : nullptr;
     }
-    S.mass = f.mass ? cv.take<R>(n) : nullptr;
-    S.m_uniform = m_uniform;
     S.energy = f.energy ? cv.take<R>(n) : nullptr;
     S.rho = cv.take<R>(n);
-    S.prs = f.prs ? cv.take<R>(n) : nullptr;
     S.count = cv.take<int>(ncell);
     S.start = cv.take<int>(size_t(ncell) + 1);
     S.slot = cv.take<int>(n);
@@ -171,8 +170,8 @@ size_t plan_bytes(const tfsph_params *p, int ng, int nd, PhaseFlags fg, PhaseFla
 {
     Carver cv;
     const int ncell = ncell_of(p);
-    carve_phase<R>(cv, ng, p->dim, ncell, fg, R(0));
-    carve_phase<R>(cv, nd, p->dim, ncell, fd, R(0));
+    carve_phase<R>(cv, ng, p->dim, ncell, fg);
+    carve_phase<R>(cv, nd, p->dim, ncell, fd);
     cv.take<int>(size_t(2) * ntiles_of(ncell));
     cv.take<unsigned int>(64);
     cv.take<unsigned long long>(8);
@@ -314,8 +313,8 @@ void carve_all(const tfsph_ctx *c, Sorted<R> &Sg, Sorted<R> &Sd, int *&partial, 
     Carver cv;
     cv.base = c->ws;
     const int ncell = ncell_of(&c->p);
-    Sg = carve_phase<R>(cv, c->ng, c->p.dim, ncell, c->fg, R(c->mg_uniform));
-    Sd = carve_phase<R>(cv, c->nd, c->p.dim, ncell, c->fd, R(c->md_uniform));
+    Sg = carve_phase<R>(cv, c->ng, c->p.dim, ncell, c->fg);
+    Sd = carve_phase<R>(cv, c->nd, c->p.dim, ncell, c->fd);
     partial = cv.take<int>(size_t(2) * ntiles_of(ncell));
     F.word = cv.take<unsigned int>(64);
     F.one_phase = cv.take<unsigned long long>(8);
