@@ -162,6 +162,65 @@ tfsph_status tfsph_density(tfsph_ctx *ctx, tfsph_state *s, int32_t phase, void *
  * since the last call.  Synchronises the context's last stream. */
 tfsph_status tfsph_get_flags(tfsph_ctx *ctx, uint32_t *flags, int64_t *one_phase_cells);
 
+/* Replay form of tfsph_step: the launches of `chunk` consecutive steps are
+ * captured once into a hipGraph (on a private stream of default priority,
+ * no memset nodes) and the graph is replayed on hip_stream; n_steps need not
+ * be a multiple of chunk (the remainder runs eagerly).  Results are bitwise
+ * those of tfsph_step.  The graph is tied to the state's array addresses:
+ * a state with other addresses is captured anew.  chunk in 1..256. */
+tfsph_status tfsph_step_graph(tfsph_ctx *ctx, tfsph_state *s, int32_t n_steps, int32_t chunk, void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent problems (instances) with their own
+ * parameters, advanced together by ONE persistent kernel launch per call.
+ * The packed state holds every instance's particles back to back: instance i
+ * owns gas particles [gas_offset[i], gas_offset[i+1]) and dust particles
+ * [dust_offset[i], dust_offset[i+1]) of the packed arrays; its cell indices
+ * are local to its own grid.  Each instance's offsets must already be in
+ * [0, Delta_i) (tfsph_positions_to_cells with that instance's params).
+ * One workgroup advances one instance for all n_steps (block barriers only,
+ * no inter-workgroup waiting); instances start largest first.  Every
+ * instance evolves bitwise as it would alone through tfsph_step.
+ * ------------------------------------------------------------------------- */
+typedef struct tfsph_batch tfsph_batch;
+
+typedef struct {
+    int32_t n_inst;
+    const tfsph_params *params;     /* host [n_inst]; all with the same dim (1 or 2) and precision */
+    const int64_t *gas_offset;      /* host [n_inst + 1], non-decreasing, [0] = 0, [n_inst] = packed gas.n */
+    const int64_t *dust_offset;     /* host [n_inst + 1] */
+    const double *mass_gas;         /* host [n_inst]: uniform gas mass of each instance (packed gas.mass NULL) */
+    const double *mass_dust;        /* host [n_inst]: uniform dust mass (packed dust.mass NULL) */
+} tfsph_batch_desc;
+
+typedef struct {
+    int32_t block;                  /* threads per workgroup, multiple of 64 in 64..1024 (0 = 512) */
+} tfsph_batch_tuning;
+
+/* Host-only: workspace bytes for a batch (256-byte aligned buffer). */
+tfsph_status tfsph_batch_workspace_size(const tfsph_batch_desc *desc, size_t *bytes);
+
+/* Validate every instance (tfsph_validate), bind the packed state and the
+ * workspace, upload the instance table and the launch order.  The host
+ * arrays of desc may be freed after return.  tuning may be NULL. */
+tfsph_status tfsph_batch_init(tfsph_batch **out, const tfsph_batch_desc *desc, tfsph_state *packed,
+                              const tfsph_batch_tuning *tuning, void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Change the launch shape (results do not depend on it). */
+tfsph_status tfsph_batch_set_tuning(tfsph_batch *b, const tfsph_batch_tuning *tuning);
+
+/* Advance every instance n_steps IDIC steps with one kernel launch.  The
+ * packed state must be the one bound at init (TFSPH_E_STATE otherwise). */
+tfsph_status tfsph_step_batched(tfsph_batch *b, tfsph_state *packed, int32_t n_steps, void *hip_stream);
+
+/* Same, through a hipGraph captured once per (n_steps, tuning) and replayed. */
+tfsph_status tfsph_step_batched_graph(tfsph_batch *b, tfsph_state *packed, int32_t n_steps, void *hip_stream);
+
+/* Flags and one-phase-cell count over all instances since the last call (syncs). */
+tfsph_status tfsph_batch_get_flags(tfsph_batch *b, uint32_t *flags, int64_t *one_phase_cells);
+
+tfsph_status tfsph_batch_destroy(tfsph_batch *b);
+
 /* Kernel timing for measurement.  tfsph_profile(ctx, 1) starts recording a
  * HIP event pair around every launch of the timed kernels on the stream the
  * launch uses (it creates the events on the host; nothing is allocated on the

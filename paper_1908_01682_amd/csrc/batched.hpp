@@ -1,0 +1,148 @@
+// Batched form: many independent problems (different N, t_stop, dust-to-gas
+// ratio, cell count) advanced n_steps in ONE persistent launch.
+//
+// Each workgroup owns one problem instance for the whole launch and runs the
+// full IDIC step (bin -> density -> predictor -> cell solve -> update) with
+// block barriers between the phases.  No workgroup ever waits on another, so
+// the launch cannot deadlock whatever the residency.  Instances are dispatched
+// largest first (longest-processing-time order) so that the big ones start
+// early.  Every per-particle and per-cell computation calls the same device
+// functions as the single-problem kernels, so an instance evolves bitwise as
+// it would alone through tfsph_step.
+#pragma once
+
+#include "binning.hpp"
+#include "sph.hpp"
+
+namespace tfsph {
+
+constexpr int kBatchMaxBlock = 1024;
+
+template <typename R>
+struct Inst {
+    Geom<R> G;
+    Phys<R> Ph;
+    Phase<R> Pg, Pd;     // caller arrays of this instance (slices of the packed state)
+    Sorted<R> Sg, Sd;    // workspace slices
+    CellSolve<R> *cs;    // [ncell] per-cell solve
+};
+
+// exclusive scan of one int per thread for any blockDim.x <= 1024 (wave64)
+__device__ __forceinline__ int block_scan_any(int v, int *lds_waves, int &total)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = (blockDim.x + 63) >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) lds_waves[wave] = x;
+    __syncthreads();
+    int pre = 0;
+    total = 0;
+    for (int w = 0; w < nwaves; ++w) {
+        const int t = lds_waves[w];
+        if (w < wave) pre += t;
+        total += t;
+    }
+    __syncthreads();
+    return pre + x - v;
+}
+
+// start[c] = sum of count[0..c), start[ncell] = total, for one instance
+__device__ __forceinline__ void block_scan_cells(const int *count, int *start, int ncell, int *lds)
+{
+    int carry = 0;
+    for (int base = 0; base < ncell; base += blockDim.x) {
+        const int c = base + threadIdx.x;
+        const int v = c < ncell ? count[c] : 0;
+        int total;
+        const int ex = block_scan_any(v, lds, total);
+        if (c < ncell) start[c] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) start[ncell] = carry;
+}
+
+template <typename R, int DIM>
+__device__ void batched_step(const Inst<R> &I, int *lds, unsigned int *flags, int &bad, int &one)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const Geom<R> &G = I.G;
+    const int ncell = G.ncell;
+    const int ng = I.Sg.n, nd = I.Sd.n;
+
+    for (int c = tid; c < ncell; c += nt) {
+        I.Sg.count[c] = 0;
+        I.Sd.count[c] = 0;
+    }
+    __syncthreads();
+    // slot claims; loop bounds are uniform across each wave (claim_slot shuffles)
+    for (int base = 0; base < ng; base += nt) {
+        const int i = base + tid;
+        const int key = i < ng ? safe_cell(I.Pg.cell[i], ncell) : -1;
+        const int sl = claim_slot(I.Sg.count, key);
+        if (i < ng) I.Sg.slot[i] = sl;
+    }
+    for (int base = 0; base < nd; base += nt) {
+        const int i = base + tid;
+        const int key = i < nd ? safe_cell(I.Pd.cell[i], ncell) : -1;
+        const int sl = claim_slot(I.Sd.count, key);
+        if (i < nd) I.Sd.slot[i] = sl;
+    }
+    __syncthreads();
+    block_scan_cells(I.Sg.count, I.Sg.start, ncell, lds);
+    block_scan_cells(I.Sd.count, I.Sd.start, ncell, lds);
+    __syncthreads();
+    for (int i = tid; i < ng; i += nt) {
+        const int pos = I.Sg.start[safe_cell(I.Pg.cell[i], ncell)] + I.Sg.slot[i];
+        I.Sg.tmp_idx[pos] = i;
+        I.Sg.tmp_id[pos] = I.Pg.id[i];
+    }
+    for (int i = tid; i < nd; i += nt) {
+        const int pos = I.Sd.start[safe_cell(I.Pd.cell[i], ncell)] + I.Sd.slot[i];
+        I.Sd.tmp_idx[pos] = i;
+        I.Sd.tmp_id[pos] = I.Pd.id[i];
+    }
+    __syncthreads();
+    for (int j = tid; j < ng; j += nt) rank_gather_one(G, I.Pg, I.Sg, j, flags);
+    for (int j = tid; j < nd; j += nt) rank_gather_one(G, I.Pd, I.Sd, j, flags);
+    __syncthreads();
+    for (int a = tid; a < ng; a += nt) density_store<R, DIM>(G, I.Ph, I.Sg, a, 1);
+    __syncthreads();
+    for (int a = tid; a < ng; a += nt) gas_predict<R, DIM>(G, I.Ph, I.Sg, I.Pg, a);
+    __syncthreads();
+    for (int c = tid; c < ncell; c += nt) one += solve_cell<R, DIM>(I.Ph, I.Sg, I.Sd, c, I.cs[c]) ? 1 : 0;
+    __syncthreads();
+    for (int a = tid; a < ng; a += nt) bad |= !gas_finish<R, DIM>(G, I.Ph, I.Sg, I.Pg, a, I.cs[I.Sg.cell[a]]);
+    for (int j = tid; j < nd; j += nt) bad |= !dust_finish<R, DIM>(G, I.Ph, I.Sd, I.Pd, j, I.cs[I.Sd.cell[j]]);
+    __syncthreads();
+}
+
+// grid = number of instances; block b advances instance order[b] by n_steps
+template <typename R, int DIM>
+__global__ void __launch_bounds__(kBatchMaxBlock)
+k_batched(const Inst<R> *__restrict__ insts, const int *__restrict__ order, int n_steps, Flags F)
+{
+    __shared__ int lds[kBatchMaxBlock / 64];
+    __shared__ int s_bad, s_one;
+    if (threadIdx.x == 0) { s_bad = 0; s_one = 0; }
+    const Inst<R> &I = insts[order[blockIdx.x]];
+    int bad = 0, one = 0;
+    for (int s = 0; s < n_steps; ++s) batched_step<R, DIM>(I, lds, F.word, bad, one);
+    if (bad) atomicOr(&s_bad, 1);
+    if (one) atomicAdd(&s_one, one);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_bad) atomicOr(F.word, 1u);
+        if (s_one) {
+            atomicOr(F.word, 2u);
+            atomicAdd(F.one_phase, (unsigned long long)s_one);
+        }
+    }
+}
+
+}  // namespace tfsph

@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(kBlock) k_canonicalize(Geom<R> G, Phase<R> P, 
 }
 
 // --- zero the histograms of both phases ---------------------------------------
-__global__ void __launch_bounds__(kBlock) k_fill_zero(int *a, int na, int *b, int nb)
+static __global__ void __launch_bounds__(kBlock) k_fill_zero(int *a, int na, int *b, int nb)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < na) a[i] = 0;
@@ -70,7 +70,7 @@ __device__ __forceinline__ int claim_slot(int *count, int key)
     return base + (lane - s);
 }
 
-__global__ void __launch_bounds__(kBlock)
+static __global__ void __launch_bounds__(kBlock)
 k_count(const int *cell_g, int n_g, int *count_g, int *slot_g,
         const int *cell_d, int n_d, int *count_d, int *slot_d, int blocks_g, int ncell, unsigned int *flags)
 {
@@ -113,7 +113,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *lds_waves, int &
 }
 
 // tile sums: grid (tiles, 2 phases)
-__global__ void __launch_bounds__(kBlock)
+static __global__ void __launch_bounds__(kBlock)
 k_scan_reduce(const int *count_g, const int *count_d, int ncell, int *partial, int ntiles)
 {
     const int *count = blockIdx.y == 0 ? count_g : count_d;
@@ -131,7 +131,7 @@ k_scan_reduce(const int *count_g, const int *count_d, int ncell, int *partial, i
 }
 
 // exclusive scan of the tile sums, one block per phase; writes start[ncell] = n
-__global__ void __launch_bounds__(kBlock)
+static __global__ void __launch_bounds__(kBlock)
 k_scan_top(int *partial, int ntiles, int *start_g, int *start_d, int ncell)
 {
     int *p = partial + blockIdx.y * ntiles;
@@ -149,7 +149,7 @@ k_scan_top(int *partial, int ntiles, int *start_g, int *start_d, int ncell)
 }
 
 // per-tile exclusive scan plus tile prefix -> start[]
-__global__ void __launch_bounds__(kBlock)
+static __global__ void __launch_bounds__(kBlock)
 k_scan_down(const int *count_g, const int *count_d, int ncell, const int *partial, int ntiles,
             int *start_g, int *start_d)
 {
@@ -184,7 +184,7 @@ k_scan_down(const int *count_g, const int *count_d, int ncell, const int *partia
 }
 
 // --- scatter (index, id) into cell ranges ----------------------------------------
-__global__ void __launch_bounds__(kBlock)
+static __global__ void __launch_bounds__(kBlock)
 k_scatter(const int *cell_g, const int *id_g, const int *slot_g, const int *start_g, int n_g, int *idx_g, int *tid_g,
           const int *cell_d, const int *id_d, const int *slot_d, const int *start_d, int n_d, int *idx_d, int *tid_d,
           int blocks_g, int ncell)
@@ -200,7 +200,7 @@ k_scatter(const int *cell_g, const int *id_g, const int *slot_g, const int *star
 
 // --- rank by id inside the cell and gather every field ---------------------------
 template <typename R>
-__device__ __forceinline__ void rank_gather_one(const Geom<R> &G, const Phase<R> &P, Sorted<R> &S, int j,
+__device__ __forceinline__ void rank_gather_one(const Geom<R> &G, const Phase<R> &P, const Sorted<R> &S, int j,
                                                 unsigned int *flags)
 {
     const int i = S.tmp_idx[j];

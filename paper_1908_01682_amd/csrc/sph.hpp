@@ -81,11 +81,12 @@ __device__ __forceinline__ R density_at(const Geom<R> &G, const Sorted<R> &S, in
     return acc * G.wnorm;
 }
 
+// density of particle a into S.rho[a]; with want_frc also the force-pass
+// record (ox, oy, oz, p / rho^2)
 template <typename R, int DIM>
-__global__ void __launch_bounds__(kBlock) k_density(Geom<R> G, Phys<R> Ph, Sorted<R> S, int want_frc)
+__device__ __forceinline__ void density_store(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &S, int a,
+                                              int want_frc)
 {
-    const int a = blockIdx.x * kBlock + threadIdx.x;
-    if (a >= S.n) return;
     const R rho = density_at<R, DIM>(G, S, a);
     S.rho[a] = rho;
     if (want_frc) {
@@ -93,6 +94,14 @@ __global__ void __launch_bounds__(kBlock) k_density(Geom<R> G, Phys<R> Ph, Sorte
         const R4<R> me = S.pos[a];
         S.frc[a] = mk4<R>(me.x, me.y, me.z, pressure_of(Ph, rho, e) / (rho * rho));
     }
+}
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(kBlock) k_density(Geom<R> G, Phys<R> Ph, Sorted<R> S, int want_frc)
+{
+    const int a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= S.n) return;
+    density_store<R, DIM>(G, Ph, S, a, want_frc);
 }
 
 // --------------------------------------------------------------------------
@@ -230,6 +239,76 @@ __device__ __forceinline__ int xcd_block(int nblocks)
     return (b % 8) * per + b / 8;
 }
 
+// Explicit part of eq. (19) for sorted gas particle a: v~ = v + tau (A + g)
+// into the predictor scratch, e += tau de/dt into the caller's energy array.
+template <typename R, int DIM>
+__device__ __forceinline__ void gas_predict(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg,
+                                            const Phase<R> &Pg, int a)
+{
+    R acc[3], dedt;
+    gas_force_at<R, DIM>(G, Ph, Sg, a, acc, dedt);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Sg.vt[d][a] = Sg.vel[d][a] + Ph.tau * (acc[d] + Ph.g[d]);
+    if (Sg.energy) Pg.energy[a] = Sg.energy[a] + Ph.tau * dedt;
+}
+
+// Implicit update of eq. (19) for gas particle a of cell C, then
+// x^{n+1} = x^n + tau v^{n+1} and the carry; writes the caller's arrays at a.
+template <typename R, int DIM>
+__device__ __forceinline__ bool gas_finish(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg,
+                                           const Phase<R> &Pg, int a, const CellSolve<R> &C)
+{
+    const int c = Sg.cell[a];
+    const R inv = R(1) / (R(1) + C.alpha);
+    int cc[3];
+    split_cell(G, c, cc[0], cc[1], cc[2]);
+    const R4<R> me = Sg.pos[a];
+    const R oo[3] = {me.x, me.y, me.z};
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const R v = (Sg.vt[d][a] + C.alpha * C.U[d]) * inv;
+        R o = oo[d] + Ph.tau * v;
+        ok &= finite_r(v);
+        ok &= carry(o, cc[d], G.delta[d], G.nc[d]);
+        Pg.vel[d][a] = v;
+        Pg.off[d][a] = o;
+    }
+    Pg.cell[a] = join_cell(G, cc[0], cc[1], cc[2]);
+    Pg.id[a] = Sg.id[a];
+    if (Sg.has_mass && Pg.mass) const_cast<R *>(Pg.mass)[a] = me.w;
+    Pg.rho[a] = Sg.rho[a];
+    return ok;
+}
+
+// Implicit update of eq. (20) for dust particle j of cell C, then move + carry.
+template <typename R, int DIM>
+__device__ __forceinline__ bool dust_finish(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sd,
+                                            const Phase<R> &Pd, int j, const CellSolve<R> &C)
+{
+    const int c = Sd.cell[j];
+    const R inv = R(1) / (R(1) + C.beta);
+    int cc[3];
+    split_cell(G, c, cc[0], cc[1], cc[2]);
+    const R4<R> me = Sd.pos[j];
+    const R oo[3] = {me.x, me.y, me.z};
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const R ut = Sd.vel[d][j] + Ph.tau * Ph.g[d];
+        const R u = (ut + C.beta * C.V[d]) * inv;
+        R o = oo[d] + Ph.tau * u;
+        ok &= finite_r(u);
+        ok &= carry(o, cc[d], G.delta[d], G.nc[d]);
+        Pd.vel[d][j] = u;
+        Pd.off[d][j] = o;
+    }
+    Pd.cell[j] = join_cell(G, cc[0], cc[1], cc[2]);
+    Pd.id[j] = Sd.id[j];
+    if (Sd.has_mass && Pd.mass) const_cast<R *>(Pd.mass)[j] = me.w;
+    return ok;
+}
+
 template <typename R, int DIM>
 __global__ void __launch_bounds__(kBlock)
 k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R> Pd, Flags F, int cells_per_block,
@@ -245,13 +324,7 @@ k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R
 
     // (1) explicit gas terms and predictor v~ (eq. 19, explicit part)
     const int ga = Sg.start[c0], gb = Sg.start[c1];
-    for (int a = ga + threadIdx.x; a < gb; a += kBlock) {
-        R acc[3], dedt;
-        gas_force_at<R, DIM>(G, Ph, Sg, a, acc, dedt);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) Sg.vt[d][a] = Sg.vel[d][a] + Ph.tau * (acc[d] + Ph.g[d]);
-        if (Sg.energy) Pg.energy[a] = Sg.energy[a] + Ph.tau * dedt;
-    }
+    for (int a = ga + threadIdx.x; a < gb; a += kBlock) gas_predict<R, DIM>(G, Ph, Sg, Pg, a);
     __syncthreads();
 
     // (2) per-cell sums in canonical order and the implicit solve
@@ -263,55 +336,11 @@ k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R
 
     // (3) implicit particle update (eqs. 19-20), position update, carry
     int bad = 0;
-    for (int a = ga + threadIdx.x; a < gb; a += kBlock) {
-        const int c = Sg.cell[a];
-        const CellSolve<R> &C = cs[c - c0];
-        const R inv = R(1) / (R(1) + C.alpha);
-        int cc[3];
-        split_cell(G, c, cc[0], cc[1], cc[2]);
-        const R4<R> me = Sg.pos[a];
-        const R oo[3] = {me.x, me.y, me.z};
-        bool ok = true;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            const R v = (Sg.vt[d][a] + C.alpha * C.U[d]) * inv;
-            R o = oo[d] + Ph.tau * v;
-            ok &= finite_r(v);
-            ok &= carry(o, cc[d], G.delta[d], G.nc[d]);
-            Pg.vel[d][a] = v;
-            Pg.off[d][a] = o;
-        }
-        Pg.cell[a] = join_cell(G, cc[0], cc[1], cc[2]);
-        Pg.id[a] = Sg.id[a];
-        if (Sg.has_mass && Pg.mass) const_cast<R *>(Pg.mass)[a] = me.w;
-        Pg.rho[a] = Sg.rho[a];
-        bad |= !ok;
-    }
+    for (int a = ga + threadIdx.x; a < gb; a += kBlock)
+        bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0]);
     const int da = Sd.start[c0], db = Sd.start[c1];
-    for (int j = da + threadIdx.x; j < db; j += kBlock) {
-        const int c = Sd.cell[j];
-        const CellSolve<R> &C = cs[c - c0];
-        const R inv = R(1) / (R(1) + C.beta);
-        int cc[3];
-        split_cell(G, c, cc[0], cc[1], cc[2]);
-        const R4<R> me = Sd.pos[j];
-        const R oo[3] = {me.x, me.y, me.z};
-        bool ok = true;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            const R ut = Sd.vel[d][j] + Ph.tau * Ph.g[d];
-            const R u = (ut + C.beta * C.V[d]) * inv;
-            R o = oo[d] + Ph.tau * u;
-            ok &= finite_r(u);
-            ok &= carry(o, cc[d], G.delta[d], G.nc[d]);
-            Pd.vel[d][j] = u;
-            Pd.off[d][j] = o;
-        }
-        Pd.cell[j] = join_cell(G, cc[0], cc[1], cc[2]);
-        Pd.id[j] = Sd.id[j];
-        if (Sd.has_mass && Pd.mass) const_cast<R *>(Pd.mass)[j] = me.w;
-        bad |= !ok;
-    }
+    for (int j = da + threadIdx.x; j < db; j += kBlock)
+        bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[Sd.cell[j] - c0]);
     if (bad) atomicOr(&s_bad, 1);
     __syncthreads();
     if (threadIdx.x == 0) {

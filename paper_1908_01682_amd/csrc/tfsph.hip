@@ -7,43 +7,21 @@
 
 #include <algorithm>
 #include <cmath>
-#include <cstdarg>
-#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
 
 #include "binning.hpp"
 #include "common.hpp"
+#include "host.hpp"
 #include "sph.hpp"
 
 using namespace tfsph;
+using namespace tfsph_host;
 
-// ----------------------------------------------------------------------------
-// errors
-// ----------------------------------------------------------------------------
-static thread_local char g_last_error[512] = "";
-
-static tfsph_status fail(tfsph_status s, const char *fmt, ...)
-{
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
-    va_end(ap);
-    return s;
+namespace tfsph_host {
+thread_local char g_last_error[512] = "";
 }
-
-#define HIP_TRY(expr)                                                                          \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess) return fail(TFSPH_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-#define LAUNCH_CHECK(name)                                                                          \
-    do {                                                                                            \
-        hipError_t e_ = hipGetLastError();                                                          \
-        if (e_ != hipSuccess) return fail(TFSPH_E_HIP, "launch %s: %s", name, hipGetErrorString(e_)); \
-    } while (0)
 
 extern "C" const char *tfsph_status_string(tfsph_status s)
 {
@@ -63,12 +41,6 @@ extern "C" const char *tfsph_last_error(void) { return g_last_error; }
 // ----------------------------------------------------------------------------
 // validation (host only)
 // ----------------------------------------------------------------------------
-static int window_of(const tfsph_params *p, int d)
-{
-    const double D = (p->box_hi[d] - p->box_lo[d]) / p->n_cells[d];
-    return (int)std::ceil(2.0 * p->h / D - 1e-12);
-}
-
 static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 extern "C" tfsph_status tfsph_validate(const tfsph_params *p)
@@ -113,56 +85,6 @@ extern "C" tfsph_status tfsph_validate(const tfsph_params *p)
 // ----------------------------------------------------------------------------
 namespace {
 
-struct Carver {
-    size_t off = 0;
-    char *base = nullptr;
-    template <typename T>
-    T *take(size_t count)
-    {
-        off = (off + 255) & ~size_t(255);
-        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
-        off += sizeof(T) * (count ? count : 1);
-        return p;
-    }
-};
-
-struct PhaseFlags {
-    bool mass;      // per-particle mass array present
-    bool energy;    // energy array present
-    bool prs;       // needs p / rho^2 and predictor scratch (gas)
-};
-
-template <typename R>
-Sorted<R> carve_phase(Carver &cv, int n, int dim, int ncell, PhaseFlags f)
-{
-    Sorted<R> S{};
-    S.n = n;
-    S.has_mass = f.mass ? 1 : 0;
-    S.cell = cv.take<int>(n);
-    S.id = cv.take<int>(n);
-    S.pos = cv.take<R4<R>>(n);
-    S.frc = f.prs ? cv.take<R4<R>>(n) : nullptr;
-    for (int d = 0; d < 3; ++d) {
-        S.vel[d] = d < dim ? cv.take<R>(n) : nullptr;
-        S.vt[d] = (f.prs && d < dim) ? cv.take<R>(n) : nullptr;
-    }
-    S.energy = f.energy ? cv.take<R>(n) : nullptr;
-    S.rho = cv.take<R>(n);
-    S.count = cv.take<int>(ncell);
-    S.start = cv.take<int>(size_t(ncell) + 1);
-    S.slot = cv.take<int>(n);
-    S.tmp_idx = cv.take<int>(n);
-    S.tmp_id = cv.take<int>(n);
-    return S;
-}
-
-int ncell_of(const tfsph_params *p)
-{
-    int n = 1;
-    for (int d = 0; d < p->dim; ++d) n *= p->n_cells[d];
-    return n;
-}
-
 int ntiles_of(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
 
 template <typename R>
@@ -186,10 +108,19 @@ struct KernelTimer {
     size_t used = 0;              // events recorded so far
 };
 
+// one captured chunk of steps, tied to the state's array addresses
+struct StepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long key = 0;
+};
+
 struct tfsph_ctx {
     tfsph_params p;
     bool profiling = false;
     KernelTimer timers[3];
+    StepGraph sg;
+    hipStream_t capture_stream = nullptr;
     int ng, nd;
     PhaseFlags fg, fd;
     double mg_uniform, md_uniform;
@@ -246,68 +177,6 @@ extern "C" tfsph_status tfsph_workspace_size(const tfsph_params *p, int64_t n_ga
 namespace {
 
 template <typename R>
-Geom<R> make_geom(const tfsph_params *p)
-{
-    Geom<R> G{};
-    static const double sig[4] = {0.0, 2.0 / 3.0, 10.0 / (7.0 * M_PI), 1.0 / M_PI};
-    G.dim = p->dim;
-    G.ncell = ncell_of(p);
-    for (int d = 0; d < 3; ++d) {
-        G.nc[d] = d < p->dim ? p->n_cells[d] : 1;
-        G.win[d] = d < p->dim ? window_of(p, d) : 0;
-        G.delta[d] = d < p->dim ? R((p->box_hi[d] - p->box_lo[d]) / p->n_cells[d]) : R(1);
-    }
-    G.h = R(p->h);
-    G.inv_h = R(1.0 / p->h);
-    G.support2 = R(4.0 * p->h * p->h);
-    G.wnorm = R(sig[p->dim] / std::pow(p->h, p->dim));
-    G.gnorm = R(sig[p->dim] / std::pow(p->h, p->dim + 1));
-    return G;
-}
-
-template <typename R>
-Phys<R> make_phys(const tfsph_params *p)
-{
-    Phys<R> P{};
-    P.eos = p->eos;
-    P.av = (p->av_alpha != 0.0 || p->av_beta != 0.0) ? 1 : 0;
-    P.cs = R(p->c_s);
-    P.cs2 = R(p->c_s * p->c_s);
-    P.gm1 = R(p->gamma - 1.0);
-    P.ggm1 = R(p->gamma * (p->gamma - 1.0));
-    P.tau = R(p->dt);
-    P.beta = R(p->dt / p->t_stop);
-    for (int d = 0; d < 3; ++d) P.g[d] = d < p->dim ? R(p->g[d]) : R(0);
-    P.av_alpha = R(p->av_alpha);
-    P.av_beta = R(p->av_beta);
-    P.eta2 = R(0.01 * p->h * p->h);
-    P.h = R(p->h);
-    return P;
-}
-
-template <typename R>
-Phase<R> make_phase(const tfsph_phase &ph, int dim)
-{
-    Phase<R> P{};
-    P.n = (int)ph.n;
-    P.cell = ph.cell;
-    for (int d = 0; d < 3; ++d) {
-        P.off[d] = d < dim ? static_cast<R *>(ph.off[d]) : nullptr;
-        P.vel[d] = d < dim ? static_cast<R *>(ph.vel[d]) : nullptr;
-    }
-    P.mass = static_cast<const R *>(ph.mass);
-    P.m_uniform = R(ph.mass_uniform);
-    P.rho = static_cast<R *>(ph.rho);
-    P.energy = static_cast<R *>(ph.energy);
-    P.id = ph.id;
-    return P;
-}
-
-struct Views {
-    char *base;
-};
-
-template <typename R>
 void carve_all(const tfsph_ctx *c, Sorted<R> &Sg, Sorted<R> &Sd, int *&partial, Flags &F)
 {
     Carver cv;
@@ -320,9 +189,9 @@ void carve_all(const tfsph_ctx *c, Sorted<R> &Sg, Sorted<R> &Sd, int *&partial, 
     F.one_phase = cv.take<unsigned long long>(8);
 }
 
-inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
+}  // namespace
 
-tfsph_status check_phase(const tfsph_phase &ph, int dim, bool need_rho, bool need_energy, const char *name)
+tfsph_status tfsph_host::check_phase(const tfsph_phase &ph, int dim, bool need_rho, bool need_energy, const char *name)
 {
     if (ph.n < 0 || ph.n > 0x7fffffffLL) return fail(TFSPH_E_INVALID_ARG, "%s.n out of range", name);
     if (ph.n == 0) return TFSPH_OK;
@@ -335,6 +204,8 @@ tfsph_status check_phase(const tfsph_phase &ph, int dim, bool need_rho, bool nee
     if (need_energy && !ph.energy) return fail(TFSPH_E_INVALID_ARG, "%s.energy is NULL (adiabatic EOS)", name);
     return TFSPH_OK;
 }
+
+namespace {
 
 tfsph_status check_state_matches(const tfsph_ctx *c, const tfsph_state *s)
 {
@@ -620,11 +491,82 @@ extern "C" tfsph_status tfsph_profile_read(tfsph_ctx *c, int32_t kernel, double 
     return TFSPH_OK;
 }
 
+static unsigned long long state_key(const tfsph_state *s, int chunk)
+{
+    // FNV-1a over every array address and the chunk length
+    unsigned long long h = 1469598103934665603ull;
+    auto mix = [&h](const void *p) {
+        unsigned long long v = (unsigned long long)(uintptr_t)p;
+        for (int i = 0; i < 8; ++i) {
+            h ^= (v >> (8 * i)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    for (const tfsph_phase *ph : {&s->gas, &s->dust}) {
+        mix(ph->cell), mix(ph->mass), mix(ph->rho), mix(ph->energy), mix(ph->id);
+        for (int d = 0; d < 3; ++d) mix(ph->off[d]), mix(ph->vel[d]);
+    }
+    mix((const void *)(uintptr_t)chunk);
+    return h;
+}
+
+static void drop_graph(StepGraph &g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = StepGraph{};
+}
+
+extern "C" tfsph_status tfsph_step_graph(tfsph_ctx *c, tfsph_state *s, int32_t n_steps, int32_t chunk, void *hip_stream)
+{
+    if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
+    if (n_steps < 0) return fail(TFSPH_E_INVALID_ARG, "n_steps must be >= 0");
+    if (chunk < 1 || chunk > 256) return fail(TFSPH_E_INVALID_ARG, "chunk must be in 1..256");
+    tfsph_status r = check_state_matches(c, s);
+    if (r != TFSPH_OK) return r;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    c->last_stream = st;
+    const int n_full = n_steps / chunk, rem = n_steps % chunk;
+    if (n_full > 0) {
+        const unsigned long long key = state_key(s, chunk);
+        if (!c->sg.exec || c->sg.key != key) {
+            drop_graph(c->sg);
+            if (!c->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+            const bool prof = c->profiling;
+            c->profiling = false;
+            HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < chunk && r == TFSPH_OK; ++i)
+                r = c->p.precision == TFSPH_F64 ? dispatch_step<double>(c, s, c->capture_stream)
+                                                : dispatch_step<float>(c, s, c->capture_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+            c->profiling = prof;
+            if (r != TFSPH_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return r;
+            }
+            if (e != hipSuccess) return fail(TFSPH_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            c->sg.graph = g;
+            HIP_TRY(hipGraphInstantiate(&c->sg.exec, g, nullptr, nullptr, 0));
+            c->sg.key = key;
+        }
+        for (int k = 0; k < n_full; ++k) HIP_TRY(hipGraphLaunch(c->sg.exec, st));
+    }
+    for (int i = 0; i < rem; ++i) {
+        r = c->p.precision == TFSPH_F64 ? dispatch_step<double>(c, s, st) : dispatch_step<float>(c, s, st);
+        if (r != TFSPH_OK) return r;
+    }
+    return TFSPH_OK;
+}
+
 extern "C" tfsph_status tfsph_destroy(tfsph_ctx *c)
 {
-    if (c)
+    if (c) {
         for (auto &T : c->timers)
             for (hipEvent_t e : T.ev) (void)hipEventDestroy(e);
+        drop_graph(c->sg);
+        if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    }
     delete c;
     return TFSPH_OK;
 }

@@ -52,6 +52,16 @@ class StateC(ctypes.Structure):
     _fields_ = [("gas", PhaseC), ("dust", PhaseC)]
 
 
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("n_inst", ctypes.c_int32), ("params", ctypes.POINTER(Params)),
+                ("gas_offset", ctypes.POINTER(ctypes.c_int64)), ("dust_offset", ctypes.POINTER(ctypes.c_int64)),
+                ("mass_gas", ctypes.POINTER(ctypes.c_double)), ("mass_dust", ctypes.POINTER(ctypes.c_double))]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -78,9 +88,20 @@ def lib():
         L.tfsph_profile.argtypes = [vp, ctypes.c_int32]
         L.tfsph_profile_read.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]
+        L.tfsph_step_graph.argtypes = [vp, ctypes.POINTER(StateC), ctypes.c_int32, ctypes.c_int32, vp]
+        BD, BT, ST = ctypes.POINTER(BatchDesc), ctypes.POINTER(BatchTuning), ctypes.POINTER(StateC)
+        L.tfsph_batch_workspace_size.argtypes = [BD, ctypes.POINTER(ctypes.c_size_t)]
+        L.tfsph_batch_init.argtypes = [ctypes.POINTER(vp), BD, ST, BT, vp, ctypes.c_size_t, vp]
+        L.tfsph_batch_set_tuning.argtypes = [vp, BT]
+        L.tfsph_step_batched.argtypes = [vp, ST, ctypes.c_int32, vp]
+        L.tfsph_step_batched_graph.argtypes = [vp, ST, ctypes.c_int32, vp]
+        L.tfsph_batch_get_flags.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int64)]
+        L.tfsph_batch_destroy.argtypes = [vp]
         for name in ("tfsph_validate", "tfsph_workspace_size", "tfsph_init", "tfsph_step", "tfsph_density",
                      "tfsph_get_flags", "tfsph_destroy", "tfsph_positions_to_cells", "tfsph_cells_to_positions",
-                     "tfsph_profile", "tfsph_profile_read"):
+                     "tfsph_profile", "tfsph_profile_read", "tfsph_step_graph", "tfsph_batch_workspace_size",
+                     "tfsph_batch_init", "tfsph_batch_set_tuning", "tfsph_step_batched", "tfsph_step_batched_graph",
+                     "tfsph_batch_get_flags", "tfsph_batch_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -141,6 +162,11 @@ def tfsph_init(params: Params, state: StateC, workspace, ws_bytes: int, stream=N
 
 def tfsph_step(ctx, state: StateC, n_steps: int, stream=None) -> None:
     _check(lib().tfsph_step(ctx, ctypes.byref(state), int(n_steps), _stream_handle(stream)), "tfsph_step")
+
+
+def tfsph_step_graph(ctx, state: StateC, n_steps: int, chunk: int, stream=None) -> None:
+    _check(lib().tfsph_step_graph(ctx, ctypes.byref(state), int(n_steps), int(chunk), _stream_handle(stream)),
+           "tfsph_step_graph")
 
 
 def tfsph_density(ctx, state: StateC, phase: int, stream=None) -> None:
@@ -311,6 +337,134 @@ class Simulation:
         if getattr(self, "ctx", None):
             tfsph_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step_graph(self, n: int, chunk: int = 16) -> None:
+        tfsph_step_graph(self.ctx, self.state, n, chunk, self.stream)
+
+
+# ----------------------------------------------------------------------------
+# batched form
+# ----------------------------------------------------------------------------
+
+def tfsph_batch_workspace_size(desc: BatchDesc) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().tfsph_batch_workspace_size(ctypes.byref(desc), ctypes.byref(out)), "tfsph_batch_workspace_size")
+    return int(out.value)
+
+
+def tfsph_batch_init(desc: BatchDesc, state: StateC, tuning: Optional[BatchTuning], workspace, ws_bytes: int,
+                     stream=None):
+    b = ctypes.c_void_p()
+    _check(lib().tfsph_batch_init(ctypes.byref(b), ctypes.byref(desc), ctypes.byref(state),
+                                  ctypes.byref(tuning) if tuning is not None else None, _ptr(workspace),
+                                  int(ws_bytes), _stream_handle(stream)), "tfsph_batch_init")
+    return b
+
+
+def tfsph_batch_set_tuning(b, tuning: BatchTuning) -> None:
+    _check(lib().tfsph_batch_set_tuning(b, ctypes.byref(tuning)), "tfsph_batch_set_tuning")
+
+
+def tfsph_step_batched(b, state: StateC, n_steps: int, stream=None) -> None:
+    _check(lib().tfsph_step_batched(b, ctypes.byref(state), int(n_steps), _stream_handle(stream)),
+           "tfsph_step_batched")
+
+
+def tfsph_step_batched_graph(b, state: StateC, n_steps: int, stream=None) -> None:
+    _check(lib().tfsph_step_batched_graph(b, ctypes.byref(state), int(n_steps), _stream_handle(stream)),
+           "tfsph_step_batched_graph")
+
+
+def tfsph_batch_get_flags(b):
+    f = ctypes.c_uint32(0)
+    n = ctypes.c_int64(0)
+    _check(lib().tfsph_batch_get_flags(b, ctypes.byref(f), ctypes.byref(n)), "tfsph_batch_get_flags")
+    return int(f.value), int(n.value)
+
+
+def tfsph_batch_destroy(b) -> None:
+    if b:
+        _check(lib().tfsph_batch_destroy(b), "tfsph_batch_destroy")
+
+
+class BatchedSimulation:
+    """Many independent problems (same dim, isothermal) in packed device arrays,
+    advanced together by one persistent launch per call."""
+
+    def __init__(self, probs, precision: int = TFSPH_F32, device="cuda", block: int = 0, stream=None):
+        import torch
+        self.probs = list(probs)
+        self.precision = precision
+        self.device = torch.device(device)
+        self.stream = stream
+        dim = self.probs[0].params.dim
+        dt = _torch_dtype(precision)
+        ng = [p.gas.n for p in self.probs]
+        nd = [p.dust.n for p in self.probs]
+        self.goff = np.concatenate([[0], np.cumsum(ng)]).astype(np.int64)
+        self.doff = np.concatenate([[0], np.cumsum(nd)]).astype(np.int64)
+        self.gas = DevicePhase(int(self.goff[-1]), dim, dt, self.device, False, False, True)
+        self.dust = DevicePhase(int(self.doff[-1]), dim, dt, self.device, False, False, True)
+        n = len(self.probs)
+        self._params = (Params * n)(*[make_params(p.params, precision) for p in self.probs])
+        self._goff = (ctypes.c_int64 * (n + 1))(*self.goff.tolist())
+        self._doff = (ctypes.c_int64 * (n + 1))(*self.doff.tolist())
+        mg = [p.gas.uniform_mass() for p in self.probs]
+        md = [p.dust.uniform_mass() for p in self.probs]
+        if any(m is None for m in mg + md):
+            raise ValueError("batched instances need a uniform mass per phase")
+        self._mg = (ctypes.c_double * n)(*mg)
+        self._md = (ctypes.c_double * n)(*md)
+        self.desc = BatchDesc(n, self._params, self._goff, self._doff, self._mg, self._md)
+        for i, p in enumerate(self.probs):
+            for ph, src, o in ((self.gas, p.gas, self.goff), (self.dust, p.dust, self.doff)):
+                a, b = int(o[i]), int(o[i + 1])
+                if b == a:
+                    continue
+                x = torch.as_tensor(np.ascontiguousarray(src.x.T), dtype=torch.float64).to(self.device)
+                tfsph_positions_to_cells(self._params[i], x, ph.cell[a:b], [t[a:b] for t in ph.off], stream)
+                for k in range(dim):
+                    ph.vel[k][a:b].copy_(torch.as_tensor(src.v[:, k]).to(dt))
+                ph.id[a:b].copy_(torch.as_tensor(src.id.astype(np.int32)))
+        self.state = StateC(self.gas.cstruct(), self.dust.cstruct())
+        self.ws_bytes = tfsph_batch_workspace_size(self.desc)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:]
+        self.handle = tfsph_batch_init(self.desc, self.state, BatchTuning(block), self._ws, self.ws_bytes, stream)
+
+    def set_block(self, block: int) -> None:
+        tfsph_batch_set_tuning(self.handle, BatchTuning(block))
+
+    def step(self, n: int) -> None:
+        tfsph_step_batched(self.handle, self.state, n, self.stream)
+
+    def step_graph(self, n: int) -> None:
+        tfsph_step_batched_graph(self.handle, self.state, n, self.stream)
+
+    def flags(self):
+        return tfsph_batch_get_flags(self.handle)
+
+    def instance(self, i: int) -> tuple:
+        """(gas, dust) numpy dicts of instance i (current order)."""
+        out = []
+        for ph, o in ((self.gas, self.goff), (self.dust, self.doff)):
+            a, b = int(o[i]), int(o[i + 1])
+            d = ph.numpy()
+            out.append({k: (None if v is None else (v[..., a:b] if k in ("off", "vel") else v[a:b]))
+                        for k, v in d.items()})
+        return tuple(out)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            tfsph_batch_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

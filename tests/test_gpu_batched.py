@@ -1,0 +1,144 @@
+"""Batched persistent form and hipGraph replay.
+
+Every instance of a batch must evolve bitwise as it does alone through
+tfsph_step; results must not depend on the launch shape; graph replays must
+equal eager launches on every replay.
+"""
+import numpy as np
+import pytest
+
+from paper_1908_01682_amd import inputs as I
+from tests.gpu_util import HAVE_GPU, banner, by_id, compare_states, needs_gpu, oracle_phase
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+if HAVE_GPU:
+    import torch
+    from paper_1908_01682_amd import tfsph as T
+
+KEYS = ("cell", "id", "off", "vel", "rho")
+
+
+def _batch_1d(seed=11, n_inst=6):
+    probs = I.batched_waves(n_inst=n_inst, n_min=500, n_max=3000, seed=seed, amp=1e-2)
+    probs.append(I.dusty_wave(n_side=41, amp=1e-2, t_stop=3e-4, eps=0.2, cells_per_axis=20))   # tiny, odd N
+    return probs
+
+
+def _batch_2d():
+    rng = np.random.default_rng(3)
+    out = []
+    for n in (24, 40, 32):
+        p = I.wave_2d(n_side=n, amp=1e-2, t_stop=float(10 ** rng.uniform(-4, -2)), eps=float(10 ** rng.uniform(-1, 1)))
+        out.append(p)
+    return out
+
+
+def _same(a, b):
+    A, B = by_id(a), by_id(b)
+    for k in KEYS:
+        if A[k] is None:
+            continue
+        assert np.array_equal(A[k], B[k]), k
+
+
+@pytest.mark.parametrize("dim,precision", [(1, 0), (1, 1), (2, 0)])
+def test_batched_equals_plain_bitwise(dim, precision):
+    probs = _batch_1d() if dim == 1 else _batch_2d()
+    banner(f"batched dim={dim} precision={precision} n_inst={len(probs)}")
+    bs = T.BatchedSimulation(probs, precision=precision)
+    bs.step(7)
+    bs.step(13)
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        sim = T.Simulation(p, precision=precision)
+        sim.step(20)
+        torch.cuda.synchronize()
+        g, d = bs.instance(i)
+        _same(g, sim.gas.numpy())
+        _same(d, sim.dust.numpy())
+        sim.close()
+    flags, _ = bs.flags()
+    bs.close()
+    assert not (flags & T.TFSPH_FLAG_NONFINITE)
+
+
+def test_batched_matches_oracle(orc):
+    probs = _batch_1d(seed=5, n_inst=3)
+    bs = T.BatchedSimulation(probs, precision=0)
+    # oracle from the batched initial state
+    init = [bs.instance(i) for i in range(len(probs))]
+    bs.step(5)
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        for ph, src in ((init[i][0], p.gas), (init[i][1], p.dust)):
+            ph["mass"] = src.m[ph["id"]]        # packed batches carry per-instance masses in the descriptor
+        og, od = oracle_phase(orc, init[i][0], 1), oracle_phase(orc, init[i][1], 1)
+        orc.step(p.params, og, od, 5)
+        g, d = bs.instance(i)
+        g["mass"], d["mass"] = p.gas.m[g["id"]], p.dust.m[d["id"]]
+        err = compare_states(p.params, g, d, og, od, p.params.c_s)
+        assert all(v <= 5e-5 for v in err.values()), (i, err)
+    bs.close()
+
+
+def test_batched_launch_shape_invariance():
+    probs = _batch_1d(seed=8, n_inst=5)
+    res = []
+    for blk in (64, 256, 1024):
+        bs = T.BatchedSimulation(probs, precision=0, block=blk)
+        bs.step(15)
+        torch.cuda.synchronize()
+        res.append([bs.instance(i) for i in range(len(probs))])
+        bs.close()
+    for other in res[1:]:
+        for (g0, d0), (g1, d1) in zip(res[0], other):
+            _same(g0, g1)
+            _same(d0, d1)
+
+
+def test_batched_graph_replays_equal_eager():
+    probs = _batch_1d(seed=9, n_inst=4)
+    eager = T.BatchedSimulation(probs, precision=0)
+    graph = T.BatchedSimulation(probs, precision=0)
+    for rep in range(4):
+        eager.step(6)
+        graph.step_graph(6)
+        torch.cuda.synchronize()
+        # eager host work and a synchronisation between replays
+        ge = [eager.instance(i) for i in range(len(probs))]
+        gg = [graph.instance(i) for i in range(len(probs))]
+        for (a0, a1), (b0, b1) in zip(ge, gg):
+            _same(a0, b0)
+            _same(a1, b1)
+    eager.close()
+    graph.close()
+
+
+@pytest.mark.parametrize("chunk", [1, 8])
+def test_step_graph_equals_eager(chunk):
+    prob = I.dusty_shock(n=6000, t_stop=1e-3)
+    a = T.Simulation(prob, precision=0)
+    b = T.Simulation(prob, precision=0)
+    for rep in range(3):
+        a.step(19)
+        b.step_graph(19, chunk=chunk)
+        torch.cuda.synchronize()
+        _same(a.gas.numpy(), b.gas.numpy())
+        _same(a.dust.numpy(), b.dust.numpy())
+        e = a.gas.numpy()["energy"]
+        assert np.array_equal(e, b.gas.numpy()["energy"])
+    a.close()
+    b.close()
+
+
+def test_batched_rejects_bad_desc():
+    probs = _batch_1d(seed=1, n_inst=2)
+    bs = T.BatchedSimulation(probs, precision=0)
+    other = T.BatchedSimulation(probs, precision=0)
+    with pytest.raises(T.TfsphError):
+        T.tfsph_step_batched(bs.handle, other.state, 1)       # state not bound to this batch
+    with pytest.raises(T.TfsphError):
+        bs.set_block(100)                                       # not a multiple of 64
+    bs.close()
+    other.close()
