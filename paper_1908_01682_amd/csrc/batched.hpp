@@ -52,48 +52,57 @@ __device__ __forceinline__ int block_scan_any(int v, int *lds_waves, int &total)
     return pre + x - v;
 }
 
-// start[c] = sum of count[0..c), start[ncell] = total, for one instance
+// start[c] = sum of count[0..c), start[ncell] = total, for one instance: each
+// thread sums a contiguous run of cells, one block scan combines the runs.
 __device__ __forceinline__ void block_scan_cells(const int *count, int *start, int ncell, int *lds)
 {
-    int carry = 0;
-    for (int base = 0; base < ncell; base += blockDim.x) {
-        const int c = base + threadIdx.x;
-        const int v = c < ncell ? count[c] : 0;
-        int total;
-        const int ex = block_scan_any(v, lds, total);
-        if (c < ncell) start[c] = carry + ex;
-        carry += total;
+    const int per = (ncell + blockDim.x - 1) / blockDim.x;
+    const int c0 = min(int(threadIdx.x) * per, ncell), c1 = min(c0 + per, ncell);
+    int s = 0;
+    for (int c = c0; c < c1; ++c) s += count[c];
+    int total;
+    int ex = block_scan_any(s, lds, total);
+    for (int c = c0; c < c1; ++c) {
+        const int v = count[c];
+        start[c] = ex;
+        ex += v;
     }
-    if (threadIdx.x == 0) start[ncell] = carry;
+    if (threadIdx.x == 0) start[ncell] = total;
 }
 
+// One IDIC step of instance I by the whole block.  Slots for the next step's
+// counting sort are claimed while the particles are finished (the new cell is
+// known there); `first` does the counting from scratch for the first step of
+// a launch, since the state may have been written outside this kernel.
 template <typename R, int DIM>
-__device__ void batched_step(const Inst<R> &I, int *lds, unsigned int *flags, int &bad, int &one)
+__device__ void batched_step(const Inst<R> &I, int *lds, unsigned int *flags, int &bad, int &one, bool first)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     const Geom<R> &G = I.G;
     const int ncell = G.ncell;
     const int ng = I.Sg.n, nd = I.Sd.n;
 
-    for (int c = tid; c < ncell; c += nt) {
-        I.Sg.count[c] = 0;
-        I.Sd.count[c] = 0;
+    if (first) {
+        for (int c = tid; c < ncell; c += nt) {
+            I.Sg.count[c] = 0;
+            I.Sd.count[c] = 0;
+        }
+        __syncthreads();
+        // loop bounds are uniform across each wave (claim_slot shuffles)
+        for (int base = 0; base < ng; base += nt) {
+            const int i = base + tid;
+            const int key = i < ng ? safe_cell(I.Pg.cell[i], ncell) : -1;
+            const int sl = claim_slot(I.Sg.count, key);
+            if (i < ng) I.Sg.slot[i] = sl;
+        }
+        for (int base = 0; base < nd; base += nt) {
+            const int i = base + tid;
+            const int key = i < nd ? safe_cell(I.Pd.cell[i], ncell) : -1;
+            const int sl = claim_slot(I.Sd.count, key);
+            if (i < nd) I.Sd.slot[i] = sl;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    // slot claims; loop bounds are uniform across each wave (claim_slot shuffles)
-    for (int base = 0; base < ng; base += nt) {
-        const int i = base + tid;
-        const int key = i < ng ? safe_cell(I.Pg.cell[i], ncell) : -1;
-        const int sl = claim_slot(I.Sg.count, key);
-        if (i < ng) I.Sg.slot[i] = sl;
-    }
-    for (int base = 0; base < nd; base += nt) {
-        const int i = base + tid;
-        const int key = i < nd ? safe_cell(I.Pd.cell[i], ncell) : -1;
-        const int sl = claim_slot(I.Sd.count, key);
-        if (i < nd) I.Sd.slot[i] = sl;
-    }
-    __syncthreads();
     block_scan_cells(I.Sg.count, I.Sg.start, ncell, lds);
     block_scan_cells(I.Sd.count, I.Sd.start, ncell, lds);
     __syncthreads();
@@ -107,6 +116,10 @@ __device__ void batched_step(const Inst<R> &I, int *lds, unsigned int *flags, in
         I.Sd.tmp_idx[pos] = i;
         I.Sd.tmp_id[pos] = I.Pd.id[i];
     }
+    for (int c = tid; c < ncell; c += nt) {       // counts are consumed: clear for the claims below
+        I.Sg.count[c] = 0;
+        I.Sd.count[c] = 0;
+    }
     __syncthreads();
     for (int j = tid; j < ng; j += nt) rank_gather_one(G, I.Pg, I.Sg, j, flags);
     for (int j = tid; j < nd; j += nt) rank_gather_one(G, I.Pd, I.Sd, j, flags);
@@ -117,8 +130,26 @@ __device__ void batched_step(const Inst<R> &I, int *lds, unsigned int *flags, in
     __syncthreads();
     for (int c = tid; c < ncell; c += nt) one += solve_cell<R, DIM>(I.Ph, I.Sg, I.Sd, c, I.cs[c]) ? 1 : 0;
     __syncthreads();
-    for (int a = tid; a < ng; a += nt) bad |= !gas_finish<R, DIM>(G, I.Ph, I.Sg, I.Pg, a, I.cs[I.Sg.cell[a]]);
-    for (int j = tid; j < nd; j += nt) bad |= !dust_finish<R, DIM>(G, I.Ph, I.Sd, I.Pd, j, I.cs[I.Sd.cell[j]]);
+    for (int base = 0; base < ng; base += nt) {
+        const int a = base + tid;
+        int key = -1;
+        if (a < ng) {
+            bad |= !gas_finish<R, DIM>(G, I.Ph, I.Sg, I.Pg, a, I.cs[I.Sg.cell[a]]);
+            key = I.Pg.cell[a];
+        }
+        const int sl = claim_slot(I.Sg.count, key);
+        if (a < ng) I.Sg.slot[a] = sl;
+    }
+    for (int base = 0; base < nd; base += nt) {
+        const int j = base + tid;
+        int key = -1;
+        if (j < nd) {
+            bad |= !dust_finish<R, DIM>(G, I.Ph, I.Sd, I.Pd, j, I.cs[I.Sd.cell[j]]);
+            key = I.Pd.cell[j];
+        }
+        const int sl = claim_slot(I.Sd.count, key);
+        if (j < nd) I.Sd.slot[j] = sl;
+    }
     __syncthreads();
 }
 
@@ -132,7 +163,7 @@ k_batched(const Inst<R> *__restrict__ insts, const int *__restrict__ order, int 
     if (threadIdx.x == 0) { s_bad = 0; s_one = 0; }
     const Inst<R> &I = insts[order[blockIdx.x]];
     int bad = 0, one = 0;
-    for (int s = 0; s < n_steps; ++s) batched_step<R, DIM>(I, lds, F.word, bad, one);
+    for (int s = 0; s < n_steps; ++s) batched_step<R, DIM>(I, lds, F.word, bad, one, s == 0);
     if (bad) atomicOr(&s_bad, 1);
     if (one) atomicAdd(&s_one, one);
     __syncthreads();

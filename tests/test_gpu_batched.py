@@ -142,3 +142,20 @@ def test_batched_rejects_bad_desc():
         bs.set_block(100)                                       # not a multiple of 64
     bs.close()
     other.close()
+
+
+def test_autotuner_picks_a_shape_and_caches(tmp_path):
+    from paper_1908_01682_amd import autotune as A
+    probs = _batch_1d(seed=12, n_inst=4)
+    bs = T.BatchedSimulation(probs, precision=0)
+    path = str(tmp_path / "tune.json")
+    before = [bs.instance(i) for i in range(len(probs))]
+    r1 = A.tune(bs, steps=4, blocks=(256, 512, 1024), path=path)
+    assert r1["block"] in (256, 512, 1024) and r1["bitwise_identical"] and not r1["cached"]
+    after = [bs.instance(i) for i in range(len(probs))]      # state restored
+    for (g0, d0), (g1, d1) in zip(before, after):
+        for k in ("cell", "id", "off", "vel"):
+            assert np.array_equal(g0[k], g1[k]) and np.array_equal(d0[k], d1[k])
+    r2 = A.tune(bs, steps=4, blocks=(256, 512, 1024), path=path)
+    assert r2["cached"] and r2["block"] == r1["block"]
+    bs.close()
