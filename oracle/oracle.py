@@ -148,11 +148,12 @@ def from_positions(p, x, v, m, ids, e=None) -> OPhase:
         lin = lin + p.n_cells[0] * (c[:, 1] % p.n_cells[1])
     if d > 2:
         lin = lin + p.n_cells[0] * p.n_cells[1] * (c[:, 2] % p.n_cells[2])
-    ph = OPhase(cell=lin.astype(np.int32), off=np.ascontiguousarray(off),
-                vel=np.ascontiguousarray(np.asarray(v, dtype=np.float64).T.reshape(d, n)),
-                mass=np.ascontiguousarray(np.asarray(m, dtype=np.float64)),
-                id=np.ascontiguousarray(np.asarray(ids, dtype=np.int32)), rho=np.zeros(n),
-                energy=None if e is None else np.ascontiguousarray(np.asarray(e, dtype=np.float64)))
+    # every array is a fresh copy: the oracle steps and sorts its state in place
+    ph = OPhase(cell=lin.astype(np.int32), off=np.array(off, dtype=np.float64, order="C", copy=True),
+                vel=np.array(np.asarray(v, dtype=np.float64).T.reshape(d, n), order="C", copy=True),
+                mass=np.array(m, dtype=np.float64, order="C", copy=True),
+                id=np.array(ids, dtype=np.int32, order="C", copy=True), rho=np.zeros(n),
+                energy=None if e is None else np.array(e, dtype=np.float64, order="C", copy=True))
     lib().orc_canonicalize(ctypes.byref(params_struct(p)), ctypes.byref(ph._struct()))
     return ph
 
