@@ -221,6 +221,36 @@ tfsph_status tfsph_batch_get_flags(tfsph_batch *b, uint32_t *flags, int64_t *one
 
 tfsph_status tfsph_batch_destroy(tfsph_batch *b);
 
+/* ---------------------------------------------------------------------------
+ * Hand-written adjoint (reverse mode) of n_steps IDIC steps for the
+ * dust-density misfit
+ *     L = (1/N_d) sum_j (rho_d,j(T) - target[id_j])^2,
+ *     rho_d,j = sum_k m_k W(|x_j - x_k|, h)   (dust only, at the final state),
+ * with respect to log t_stop and the initial velocities v0 (gas) and u0
+ * (dust).  Cells and neighbour sets are held at their forward values (they
+ * are piecewise constant in the inputs).  Memory is bounded by checkpointing:
+ * the state is saved every ckpt_every steps in a forward sweep; then for each
+ * segment, last first, the segment is replayed from its checkpoint with every
+ * step's sorted state taped, and reversed step by step.  All sums are in
+ * gather form (no atomics) and reduced in a fixed order: bitwise
+ * reproducible.  Isothermal EOS without artificial viscosity only
+ * (TFSPH_E_UNSUPPORTED otherwise).
+ *
+ *   initial      device state at t = 0; read only.  Offsets must lie in
+ *                [0, Delta); ids must be a permutation of 0..n-1 per phase.
+ *   target       device [n_dust] real, indexed by dust id
+ *   dL_dv0_gas   device [dim] arrays of [n_gas] real, indexed by gas id (out)
+ *   dL_du0_dust  device [dim] arrays of [n_dust] real, indexed by dust id (out)
+ *   dL_dlog_tstop, loss   device double (out)
+ * ------------------------------------------------------------------------- */
+tfsph_status tfsph_adjoint_workspace_size(const tfsph_params *p, int64_t n_gas, int64_t n_dust, int32_t n_steps,
+                                          int32_t ckpt_every, size_t *bytes);
+
+tfsph_status tfsph_step_adjoint(const tfsph_params *p, const tfsph_state *initial, int32_t n_steps,
+                                int32_t ckpt_every, const void *target, void *dL_dv0_gas[3], void *dL_du0_dust[3],
+                                double *dL_dlog_tstop, double *loss, void *workspace, size_t ws_bytes,
+                                void *hip_stream);
+
 /* Kernel timing for measurement.  tfsph_profile(ctx, 1) starts recording a
  * HIP event pair around every launch of the timed kernels on the stream the
  * launch uses (it creates the events on the host; nothing is allocated on the

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtfsph.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("tfsph.hip", "batch.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("tfsph.hip", "batch.hip", "adjoint.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))] + \
     [os.path.join(ROOT, "include", "tfsph.h")]
 

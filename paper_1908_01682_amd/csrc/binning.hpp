@@ -216,6 +216,7 @@ __device__ __forceinline__ void rank_gather_one(const Geom<R> &G, const Phase<R>
         atomicOr(flags, 8u);
     }
     const int dst = b + rank;
+    if (S.src) S.src[dst] = i;
     S.cell[dst] = c;
     S.id[dst] = myid;
     R o[3] = {R(0), R(0), R(0)};

@@ -130,6 +130,7 @@ struct Sorted {
     int *slot;           // [n] slot claimed inside the cell during counting
     int *tmp_idx;        // [n] unsorted-within-cell scatter of source indices
     int *tmp_id;         // [n] ids in the same layout
+    int *src;            // nullable [n]: index in the unsorted arrays of sorted particle dst
 };
 
 struct Flags {

@@ -1,0 +1,70 @@
+// Launch sequences of one IDIC step shared by the library's entry points:
+// binning (counting sort into canonical (cell, id) order), gas density, and
+// the fused force + predictor + cell solve + update kernel.
+#pragma once
+
+#include "binning.hpp"
+#include "host.hpp"
+#include "sph.hpp"
+
+namespace tfsph_host {
+
+inline int ntiles_of(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
+
+inline int default_cells_per_block(int dim) { return dim == 1 ? 128 : (dim == 2 ? 64 : 32); }
+
+// zero + count + scan + scatter + rank/gather of both phases into the workspace
+template <typename R>
+inline tfsph_status enqueue_bin(int ng, int nd, const Geom<R> &G, const Phase<R> &Pg, const Phase<R> &Pd,
+                         Sorted<R> &Sg, Sorted<R> &Sd, int *partial, const Flags &F, hipStream_t st)
+{
+    const int ncell = G.ncell;
+    const int ntiles = ntiles_of(ncell);
+    const int bg = blocks_for(ng), bd = blocks_for(nd);
+    hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(ncell)), dim3(kBlock), 0, st, Sg.count, ncell, Sd.count, ncell);
+    LAUNCH_CHECK("fill_zero");
+    if (bg + bd > 0) {
+        hipLaunchKernelGGL(k_count, dim3(bg + bd), dim3(kBlock), 0, st, Pg.cell, ng, Sg.count, Sg.slot, Pd.cell,
+                           nd, Sd.count, Sd.slot, bg, ncell, F.word);
+        LAUNCH_CHECK("count");
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3(ntiles, 2), dim3(kBlock), 0, st, Sg.count, Sd.count, ncell, partial, ntiles);
+    LAUNCH_CHECK("scan_reduce");
+    hipLaunchKernelGGL(k_scan_top, dim3(1, 2), dim3(kBlock), 0, st, partial, ntiles, Sg.start, Sd.start, ncell);
+    LAUNCH_CHECK("scan_top");
+    hipLaunchKernelGGL(k_scan_down, dim3(ntiles, 2), dim3(kBlock), 0, st, Sg.count, Sd.count, ncell, partial, ntiles,
+                       Sg.start, Sd.start);
+    LAUNCH_CHECK("scan_down");
+    if (bg + bd > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(bg + bd), dim3(kBlock), 0, st, Pg.cell, Pg.id, Sg.slot, Sg.start, ng,
+                           Sg.tmp_idx, Sg.tmp_id, Pd.cell, Pd.id, Sd.slot, Sd.start, nd, Sd.tmp_idx, Sd.tmp_id, bg, ncell);
+        LAUNCH_CHECK("scatter");
+        hipLaunchKernelGGL(k_rank_gather<R>, dim3(bg + bd), dim3(kBlock), 0, st, G, Pg, Sg, Pd, Sd, bg, F.word);
+        LAUNCH_CHECK("rank_gather");
+    }
+    return TFSPH_OK;
+}
+
+
+template <typename R, int DIM>
+inline tfsph_status enqueue_density(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &S, int want_frc,
+                                    hipStream_t st)
+{
+    if (S.n == 0) return TFSPH_OK;
+    hipLaunchKernelGGL((k_density<R, DIM>), dim3(blocks_for(S.n)), dim3(kBlock), 0, st, G, Ph, S, want_frc);
+    LAUNCH_CHECK("density");
+    return TFSPH_OK;
+}
+
+template <typename R, int DIM>
+inline tfsph_status enqueue_update(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg, const Sorted<R> &Sd,
+                                   const Phase<R> &Pg, const Phase<R> &Pd, const Flags &F, int cpb, hipStream_t st)
+{
+    const int nblocks = (G.ncell + cpb - 1) / cpb;
+    const size_t lds = sizeof(CellSolve<R>) * cpb;
+    hipLaunchKernelGGL((k_update<R, DIM>), dim3(nblocks), dim3(kBlock), lds, st, G, Ph, Sg, Sd, Pg, Pd, F, cpb, nblocks);
+    LAUNCH_CHECK("update");
+    return TFSPH_OK;
+}
+
+}  // namespace tfsph_host

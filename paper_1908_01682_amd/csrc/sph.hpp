@@ -188,9 +188,18 @@ struct CellSolve {
     R V[3], U[3];
 };
 
+// Mass and mean predictor velocity of each phase in cell c, summed serially
+// in canonical (cell, id) order (eqs. 17, 21 with mass weights).
+template <typename R>
+struct CellSums {
+    int ng, nd;
+    R Mg, Md;
+    R Vt[3], Ut[3];
+};
+
 template <typename R, int DIM>
-__device__ __forceinline__ bool solve_cell(const Phys<R> &Ph, const Sorted<R> &Sg, const Sorted<R> &Sd, int c,
-                                           CellSolve<R> &out)
+__device__ __forceinline__ void cell_sums(const Phys<R> &Ph, const Sorted<R> &Sg, const Sorted<R> &Sd, int c,
+                                          CellSums<R> &S)
 {
     const int g0 = Sg.start[c], g1 = Sg.start[c + 1];
     const int d0 = Sd.start[c], d1 = Sd.start[c + 1];
@@ -208,24 +217,47 @@ __device__ __forceinline__ bool solve_cell(const Phys<R> &Ph, const Sorted<R> &S
 #pragma unroll
         for (int d = 0; d < DIM; ++d) Pd[d] += m * (Sd.vel[d][j] + Ph.tau * Ph.g[d]);
     }
-    const bool both = g1 > g0 && d1 > d0;
+    S.ng = g1 - g0;
+    S.nd = d1 - d0;
+    S.Mg = Mg;
+    S.Md = Md;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        S.Vt[d] = S.ng > 0 ? Pg[d] / Mg : R(0);
+        S.Ut[d] = S.nd > 0 ? Pd[d] / Md : R(0);
+    }
+}
+
+// closed-form implicit solve from the cell sums; true for a one-phase cell
+template <typename R, int DIM>
+__device__ __forceinline__ bool solve_from_sums(const Phys<R> &Ph, const CellSums<R> &S, CellSolve<R> &out)
+{
+    const bool both = S.ng > 0 && S.nd > 0;
     if (both) {
-        const R eps = Md / Mg;
+        const R eps = S.Md / S.Mg;
         out.beta = Ph.beta;
         out.alpha = eps * Ph.beta;
         const R D = R(1) + out.alpha + out.beta;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            const R Vt = Pg[d] / Mg, Ut = Pd[d] / Md;
-            out.V[d] = ((R(1) + out.beta) * Vt + out.alpha * Ut) / D;
-            out.U[d] = (out.beta * Vt + (R(1) + out.alpha) * Ut) / D;
+            out.V[d] = ((R(1) + out.beta) * S.Vt[d] + out.alpha * S.Ut[d]) / D;
+            out.U[d] = (out.beta * S.Vt[d] + (R(1) + out.alpha) * S.Ut[d]) / D;
         }
     } else {
         out.alpha = out.beta = R(0);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) out.V[d] = out.U[d] = R(0);
     }
-    return !both && (g1 > g0 || d1 > d0);
+    return !both && (S.ng > 0 || S.nd > 0);
+}
+
+template <typename R, int DIM>
+__device__ __forceinline__ bool solve_cell(const Phys<R> &Ph, const Sorted<R> &Sg, const Sorted<R> &Sd, int c,
+                                           CellSolve<R> &out)
+{
+    CellSums<R> S;
+    cell_sums<R, DIM>(Ph, Sg, Sd, c, S);
+    return solve_from_sums<R, DIM>(Ph, S, out);
 }
 
 // Block-to-cell-range map.  Consecutive block ids land on different XCDs

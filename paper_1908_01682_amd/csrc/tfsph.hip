@@ -15,6 +15,7 @@
 #include "common.hpp"
 #include "host.hpp"
 #include "sph.hpp"
+#include "enqueue.hpp"
 
 using namespace tfsph;
 using namespace tfsph_host;
@@ -85,7 +86,6 @@ extern "C" tfsph_status tfsph_validate(const tfsph_params *p)
 // ----------------------------------------------------------------------------
 namespace {
 
-int ntiles_of(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
 
 template <typename R>
 size_t plan_bytes(const tfsph_params *p, int ng, int nd, PhaseFlags fg, PhaseFlags fd)
@@ -220,38 +220,6 @@ tfsph_status check_state_matches(const tfsph_ctx *c, const tfsph_state *s)
     return check_phase(s->dust, c->p.dim, false, false, "dust");
 }
 
-// zero + count + scan + scatter + rank/gather of both phases into the workspace
-template <typename R>
-tfsph_status enqueue_bin(const tfsph_ctx *c, const Geom<R> &G, const Phase<R> &Pg, const Phase<R> &Pd,
-                         Sorted<R> &Sg, Sorted<R> &Sd, int *partial, const Flags &F, hipStream_t st)
-{
-    const int ncell = G.ncell;
-    const int ntiles = ntiles_of(ncell);
-    const int bg = blocks_for(c->ng), bd = blocks_for(c->nd);
-    hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(ncell)), dim3(kBlock), 0, st, Sg.count, ncell, Sd.count, ncell);
-    LAUNCH_CHECK("fill_zero");
-    if (bg + bd > 0) {
-        hipLaunchKernelGGL(k_count, dim3(bg + bd), dim3(kBlock), 0, st, Pg.cell, c->ng, Sg.count, Sg.slot, Pd.cell,
-                           c->nd, Sd.count, Sd.slot, bg, ncell, F.word);
-        LAUNCH_CHECK("count");
-    }
-    hipLaunchKernelGGL(k_scan_reduce, dim3(ntiles, 2), dim3(kBlock), 0, st, Sg.count, Sd.count, ncell, partial, ntiles);
-    LAUNCH_CHECK("scan_reduce");
-    hipLaunchKernelGGL(k_scan_top, dim3(1, 2), dim3(kBlock), 0, st, partial, ntiles, Sg.start, Sd.start, ncell);
-    LAUNCH_CHECK("scan_top");
-    hipLaunchKernelGGL(k_scan_down, dim3(ntiles, 2), dim3(kBlock), 0, st, Sg.count, Sd.count, ncell, partial, ntiles,
-                       Sg.start, Sd.start);
-    LAUNCH_CHECK("scan_down");
-    if (bg + bd > 0) {
-        hipLaunchKernelGGL(k_scatter, dim3(bg + bd), dim3(kBlock), 0, st, Pg.cell, Pg.id, Sg.slot, Sg.start, c->ng,
-                           Sg.tmp_idx, Sg.tmp_id, Pd.cell, Pd.id, Sd.slot, Sd.start, c->nd, Sd.tmp_idx, Sd.tmp_id, bg, ncell);
-        LAUNCH_CHECK("scatter");
-        hipLaunchKernelGGL(k_rank_gather<R>, dim3(bg + bd), dim3(kBlock), 0, st, G, Pg, Sg, Pd, Sd, bg, F.word);
-        LAUNCH_CHECK("rank_gather");
-    }
-    return TFSPH_OK;
-}
-
 template <typename R, int DIM>
 tfsph_status enqueue_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
 {
@@ -263,21 +231,18 @@ tfsph_status enqueue_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
     Flags F;
     carve_all<R>(c, Sg, Sd, partial, F);
     MARK(TFSPH_KERNEL_BIN);
-    tfsph_status r = enqueue_bin<R>(c, G, Pg, Pd, Sg, Sd, partial, F, st);
+    tfsph_status r = enqueue_bin<R>(c->ng, c->nd, G, Pg, Pd, Sg, Sd, partial, F, st);
     if (r != TFSPH_OK) return r;
     MARK(TFSPH_KERNEL_BIN);
     if (c->ng > 0) {
         MARK(TFSPH_KERNEL_DENSITY);
-        hipLaunchKernelGGL((k_density<R, DIM>), dim3(blocks_for(c->ng)), dim3(kBlock), 0, st, G, Ph, Sg, 1);
-        LAUNCH_CHECK("density");
+        r = enqueue_density<R, DIM>(G, Ph, Sg, 1, st);
+        if (r != TFSPH_OK) return r;
         MARK(TFSPH_KERNEL_DENSITY);
     }
-    const int cpb = c->cells_per_block;
-    const int nblocks = (G.ncell + cpb - 1) / cpb;
-    const size_t lds = sizeof(CellSolve<R>) * cpb;
     MARK(TFSPH_KERNEL_UPDATE);
-    hipLaunchKernelGGL((k_update<R, DIM>), dim3(nblocks), dim3(kBlock), lds, st, G, Ph, Sg, Sd, Pg, Pd, F, cpb, nblocks);
-    LAUNCH_CHECK("update");
+    r = enqueue_update<R, DIM>(G, Ph, Sg, Sd, Pg, Pd, F, c->cells_per_block, st);
+    if (r != TFSPH_OK) return r;
     MARK(TFSPH_KERNEL_UPDATE);
     return TFSPH_OK;
 }
@@ -301,7 +266,7 @@ tfsph_status enqueue_init(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
         hipLaunchKernelGGL(k_canonicalize<R>, dim3(blocks_for(c->nd)), dim3(kBlock), 0, st, G, Pd, F);
         LAUNCH_CHECK("canonicalize");
     }
-    tfsph_status r = enqueue_bin<R>(c, G, Pg, Pd, Sg, Sd, partial, F, st);
+    tfsph_status r = enqueue_bin<R>(c->ng, c->nd, G, Pg, Pd, Sg, Sd, partial, F, st);
     if (r != TFSPH_OK) return r;
     if (c->ng > 0) {
         hipLaunchKernelGGL(k_copy_back<R>, dim3(blocks_for(c->ng)), dim3(kBlock), 0, st, G, Sg, Pg, 0);
@@ -324,7 +289,7 @@ tfsph_status enqueue_density(tfsph_ctx *c, tfsph_state *s, int phase, hipStream_
     int *partial;
     Flags F;
     carve_all<R>(c, Sg, Sd, partial, F);
-    tfsph_status r = enqueue_bin<R>(c, G, Pg, Pd, Sg, Sd, partial, F, st);
+    tfsph_status r = enqueue_bin<R>(c->ng, c->nd, G, Pg, Pd, Sg, Sd, partial, F, st);
     if (r != TFSPH_OK) return r;
     Sorted<R> &S = phase == 0 ? Sg : Sd;
     if (S.n > 0) {
@@ -362,10 +327,6 @@ tfsph_status dispatch_density(tfsph_ctx *c, tfsph_state *s, int phase, hipStream
     }
 }
 
-int default_cells_per_block(int dim)
-{
-    return dim == 1 ? 128 : (dim == 2 ? 64 : 32);
-}
 
 }  // namespace
 

@@ -97,11 +97,16 @@ def lib():
         L.tfsph_step_batched_graph.argtypes = [vp, ST, ctypes.c_int32, vp]
         L.tfsph_batch_get_flags.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int64)]
         L.tfsph_batch_destroy.argtypes = [vp]
+        L.tfsph_adjoint_workspace_size.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                                   ctypes.POINTER(ctypes.c_size_t)]
+        L.tfsph_step_adjoint.argtypes = [P, ST, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_void_p * 3,
+                                         ctypes.c_void_p * 3, vp, vp, vp, ctypes.c_size_t, vp]
         for name in ("tfsph_validate", "tfsph_workspace_size", "tfsph_init", "tfsph_step", "tfsph_density",
                      "tfsph_get_flags", "tfsph_destroy", "tfsph_positions_to_cells", "tfsph_cells_to_positions",
                      "tfsph_profile", "tfsph_profile_read", "tfsph_step_graph", "tfsph_batch_workspace_size",
                      "tfsph_batch_init", "tfsph_batch_set_tuning", "tfsph_step_batched", "tfsph_step_batched_graph",
-                     "tfsph_batch_get_flags", "tfsph_batch_destroy"):
+                     "tfsph_batch_get_flags", "tfsph_batch_destroy", "tfsph_adjoint_workspace_size",
+                     "tfsph_step_adjoint"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -471,3 +476,124 @@ class BatchedSimulation:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------
+# adjoint
+# ----------------------------------------------------------------------------
+
+def tfsph_adjoint_workspace_size(params: Params, n_gas: int, n_dust: int, n_steps: int, ckpt_every: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().tfsph_adjoint_workspace_size(ctypes.byref(params), int(n_gas), int(n_dust), int(n_steps),
+                                              int(ckpt_every), ctypes.byref(out)), "tfsph_adjoint_workspace_size")
+    return int(out.value)
+
+
+def tfsph_step_adjoint(params: Params, state: StateC, n_steps: int, ckpt_every: int, target, dv0, du0, dlogt, loss,
+                       workspace, ws_bytes: int, stream=None) -> None:
+    g = (ctypes.c_void_p * 3)(*[_ptr(t) for t in dv0] + [None] * (3 - len(dv0)))
+    d = (ctypes.c_void_p * 3)(*[_ptr(t) for t in du0] + [None] * (3 - len(du0)))
+    _check(lib().tfsph_step_adjoint(ctypes.byref(params), ctypes.byref(state), int(n_steps), int(ckpt_every),
+                                    _ptr(target), g, d, _ptr(dlogt), _ptr(loss), _ptr(workspace), int(ws_bytes),
+                                    _stream_handle(stream)), "tfsph_step_adjoint")
+
+
+class AdjointRunner:
+    """Initial state of a problem on the device plus the adjoint workspace.
+
+    ``run(target)`` returns (loss, dL/dlog t_stop, dL/dv0, dL/du0) with the
+    velocity gradients as (n, dim) tensors indexed by particle id.  The initial
+    arrays stay in id order, so ``set_velocities`` takes (n, dim) by id.
+    """
+
+    def __init__(self, prob, n_steps: int, ckpt_every: int, precision: int = TFSPH_F32, device="cuda",
+                 stream=None):
+        import torch
+        self.prob = prob
+        self.n_steps, self.ckpt_every = int(n_steps), int(ckpt_every)
+        self.precision = precision
+        self.device = torch.device(device)
+        self.stream = stream
+        p = prob.params
+        self.dim = p.dim
+        self.params = make_params(p, precision)
+        tfsph_validate(self.params)
+        self.dtype = _torch_dtype(precision)
+        g, d = prob.gas, prob.dust
+        if not (np.array_equal(g.id, np.arange(g.n)) and np.array_equal(d.id, np.arange(d.n))):
+            raise ValueError("AdjointRunner expects particles given in id order 0..n-1")
+        mg, md = g.uniform_mass(), d.uniform_mass()
+        self.gas = DevicePhase(g.n, p.dim, self.dtype, self.device, mg is None, False, True)
+        self.dust = DevicePhase(d.n, p.dim, self.dtype, self.device, md is None, False, True)
+        for ph, src, mu in ((self.gas, g, mg), (self.dust, d, md)):
+            ph.mass_uniform = mu if mu is not None else 0.0
+            x = torch.as_tensor(np.ascontiguousarray(src.x.T), dtype=torch.float64).to(self.device)
+            tfsph_positions_to_cells(self.params, x, ph.cell, ph.off, stream)
+            for k in range(ph.dim):
+                ph.vel[k].copy_(torch.as_tensor(src.v[:, k]).to(self.dtype))
+            ph.id.copy_(torch.as_tensor(src.id.astype(np.int32)))
+            if ph.mass is not None:
+                ph.mass.copy_(torch.as_tensor(src.m).to(self.dtype))
+        self.state = StateC(self.gas.cstruct(), self.dust.cstruct())
+        self.ws_bytes = tfsph_adjoint_workspace_size(self.params, g.n, d.n, self.n_steps, self.ckpt_every)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:]
+        self.dv0 = [torch.zeros(g.n, dtype=self.dtype, device=self.device) for _ in range(p.dim)]
+        self.du0 = [torch.zeros(d.n, dtype=self.dtype, device=self.device) for _ in range(p.dim)]
+        self.out = torch.zeros(2, dtype=torch.float64, device=self.device)
+
+    def set_t_stop(self, t_stop: float) -> None:
+        self.params.t_stop = float(t_stop)
+
+    def set_velocities(self, v0g=None, v0d=None) -> None:
+        for ph, v in ((self.gas, v0g), (self.dust, v0d)):
+            if v is None:
+                continue
+            for k in range(self.dim):
+                ph.vel[k].copy_(v[:, k].to(self.dtype))
+
+    def run(self, target):
+        import torch
+        t = torch.as_tensor(target).to(device=self.device, dtype=self.dtype).contiguous()
+        tfsph_step_adjoint(self.params, self.state, self.n_steps, self.ckpt_every, t, self.dv0, self.du0,
+                           self.out[1:2], self.out[0:1], self._ws, self.ws_bytes, self.stream)
+        out = self.out.clone()
+        return (out[0], out[1], torch.stack(self.dv0, dim=1).clone(), torch.stack(self.du0, dim=1).clone())
+
+
+def _make_loss_function():
+    import torch
+
+    class TFSPHLoss(torch.autograd.Function):
+        """loss = TFSPHLoss.apply(v0_gas, v0_dust, log_t_stop, runner, target).
+
+        The forward call runs the C-ABI adjoint once (its forward sweep gives the
+        loss, its reverse sweep the gradients); backward scales the stored
+        gradients by the incoming scalar gradient."""
+
+        @staticmethod
+        def forward(ctx, v0g, v0d, log_tstop, runner, target):
+            runner.set_velocities(v0g.detach(), v0d.detach())
+            runner.set_t_stop(float(torch.exp(log_tstop.detach())))
+            loss, dlogt, gv, gu = runner.run(target)
+            ctx.save_for_backward(gv.to(v0g.dtype), gu.to(v0d.dtype), dlogt.to(log_tstop.dtype))
+            return loss.to(log_tstop.dtype)
+
+        @staticmethod
+        def backward(ctx, gout):
+            gv, gu, dlogt = ctx.saved_tensors
+            return gout * gv, gout * gu, gout * dlogt, None, None
+
+    return TFSPHLoss
+
+
+_loss_fn = None
+
+
+def tfsph_loss(v0g, v0d, log_tstop, runner: AdjointRunner, target):
+    """Differentiable dust-density misfit of ``runner``'s problem (see TFSPHLoss)."""
+    global _loss_fn
+    if _loss_fn is None:
+        _loss_fn = _make_loss_function()
+    return _loss_fn.apply(v0g, v0d, log_tstop, runner, target)

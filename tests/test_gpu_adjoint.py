@@ -1,0 +1,140 @@
+"""Checkpointed adjoint through the C ABI against the FP64 gradient reference.
+
+FP64 device runs must match the autograd reference to ~1e-9; FP32 runs within
+1e-3 relative on dL/dlog t_stop and 1e-2 relative L2 on the velocity-gradient
+fields.  The checkpoint interval must not change a single bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1908_01682_amd import inputs as I
+from tests.gpu_util import HAVE_GPU, banner, needs_gpu
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+if HAVE_GPU:
+    import torch
+    from paper_1908_01682_amd import tfsph as T
+
+
+def _prob(dim, n, seed=0, t_stop=1e-3, mass_jitter=False):
+    if dim == 1:
+        prob = I.dusty_wave(n_side=n, amp=1e-2, t_stop=t_stop, eps=0.8, cells_per_axis=n // 2)
+    else:
+        prob = I.wave_2d(n_side=n, amp=1e-2, t_stop=t_stop, eps=1.0)
+    rng = np.random.default_rng(seed)
+    prob.gas.v = prob.gas.v + 0.01 * rng.standard_normal(prob.gas.v.shape)
+    prob.dust.v = prob.dust.v + 0.01 * rng.standard_normal(prob.dust.v.shape)
+    if mass_jitter:
+        prob.dust.m = prob.dust.m * rng.uniform(0.7, 1.3, prob.dust.n)
+    return prob
+
+
+def _target(orc, prob, steps):
+    """Dust density by id after a twin run with t_stop doubled (FP64 oracle)."""
+    p = prob.params.replace(t_stop=2.0 * prob.params.t_stop)
+    g, d = orc.from_problem(prob)
+    orc.step(p, g, d, steps)
+    rho = orc.density(p, d)
+    t = np.zeros(prob.dust.n)
+    t[d.id] = rho
+    return t
+
+
+def _device_positions(runner, prob):
+    """FP64 absolute positions (by id) of the runner's initial (cell, offset) state."""
+    out = []
+    p = prob.params
+    D = [(p.hi[k] - p.lo[k]) / p.n_cells[k] for k in range(p.dim)]
+    for ph in (runner.gas, runner.dust):
+        a = ph.numpy()
+        c = a["cell"].astype(np.int64)
+        cs = [c % p.n_cells[0]]
+        if p.dim > 1:
+            cs.append((c // p.n_cells[0]) % p.n_cells[1])
+        x = np.stack([p.lo[k] + cs[k] * D[k] + a["off"][k].astype(np.float64) for k in range(p.dim)], axis=1)
+        out.append(x)
+    return out
+
+
+def _reference(orc, prob, runner, target, steps):
+    from oracle import adjoint_torch as AT
+    xg, xd = _device_positions(runner, prob)
+    vg = np.stack([v.cpu().numpy().astype(np.float64) for v in runner.gas.vel], axis=1)
+    vd = np.stack([v.cpu().numpy().astype(np.float64) for v in runner.dust.vel], axis=1)
+    return AT.gradients(prob.params, xg, xd, prob.gas.m, prob.dust.m, vg, vd, prob.params.t_stop, target, steps)
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("dim,n,steps,ckpt,mass", [(2, 24, 12, 5, False), (1, 160, 15, 4, True), (2, 20, 7, 7, True)])
+def test_adjoint_fp64_matches_reference(orc, dim, n, steps, ckpt, mass):
+    prob = _prob(dim, n, seed=dim, mass_jitter=mass)
+    target = _target(orc, prob, steps)
+    banner(f"adjoint fp64 dim={dim} n={n} steps={steps} ckpt={ckpt}")
+    runner = T.AdjointRunner(prob, steps, ckpt, precision=T.TFSPH_F64)
+    loss, dlogt, gv, gu = runner.run(target)
+    torch.cuda.synchronize()
+    ref_loss, ref_s, ref_gv, ref_gu = _reference(orc, prob, runner, target, steps)
+    assert abs(float(loss) - ref_loss) <= 1e-10 * ref_loss
+    assert abs(float(dlogt) - ref_s) <= 1e-8 * abs(ref_s)
+    assert np.max(np.abs(gv.cpu().numpy() - ref_gv)) <= 1e-8 * np.max(np.abs(ref_gv))
+    assert np.max(np.abs(gu.cpu().numpy() - ref_gu)) <= 1e-8 * np.max(np.abs(ref_gu))
+
+
+@pytest.mark.parametrize("dim,n,steps,ckpt", [(2, 32, 20, 6), (1, 400, 40, 10)])
+def test_adjoint_fp32_matches_reference(orc, dim, n, steps, ckpt):
+    prob = _prob(dim, n, seed=5 + dim)
+    target = _target(orc, prob, steps)
+    banner(f"adjoint fp32 dim={dim} n={n} steps={steps} ckpt={ckpt}")
+    runner = T.AdjointRunner(prob, steps, ckpt, precision=T.TFSPH_F32)
+    loss, dlogt, gv, gu = runner.run(target.astype(np.float32))
+    torch.cuda.synchronize()
+    ref_loss, ref_s, ref_gv, ref_gu = _reference(orc, prob, runner, target.astype(np.float32).astype(np.float64),
+                                                 steps)
+    assert abs(float(loss) - ref_loss) <= 1e-3 * ref_loss, (float(loss), ref_loss)
+    assert abs(float(dlogt) - ref_s) <= 1e-3 * abs(ref_s), (float(dlogt), ref_s)
+    assert _rel_l2(gv.cpu().numpy(), ref_gv) <= 1e-2
+    assert _rel_l2(gu.cpu().numpy(), ref_gu) <= 1e-2
+
+
+def test_checkpoint_interval_and_rerun_are_bitwise_identical():
+    prob = _prob(2, 24, seed=3)
+    target = np.full(prob.dust.n, 1.0, dtype=np.float32)
+    res = []
+    for ckpt in (1, 4, 13, 13):
+        runner = T.AdjointRunner(prob, 13, ckpt, precision=T.TFSPH_F32)
+        out = runner.run(target)
+        torch.cuda.synchronize()
+        res.append([o.cpu().numpy() for o in out])
+    for other in res[1:]:
+        for a, b in zip(res[0], other):
+            assert np.array_equal(a, b)
+
+
+def test_autograd_function(orc):
+    prob = _prob(2, 20, seed=4)
+    steps = 6
+    target = _target(orc, prob, steps)
+    runner = T.AdjointRunner(prob, steps, 3, precision=T.TFSPH_F64)
+    v0g = torch.tensor(prob.gas.v, dtype=torch.float64, device="cuda", requires_grad=True)
+    v0d = torch.tensor(prob.dust.v, dtype=torch.float64, device="cuda", requires_grad=True)
+    s = torch.tensor(math.log(prob.params.t_stop), dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = T.tfsph_loss(v0g, v0d, s, runner, target)
+    (3.0 * loss).backward()
+    ref_loss, ref_s, ref_gv, ref_gu = _reference(orc, prob, runner, target, steps)
+    assert abs(float(loss) - ref_loss) <= 1e-10 * ref_loss
+    assert abs(float(s.grad) - 3.0 * ref_s) <= 1e-8 * abs(3.0 * ref_s)
+    assert np.max(np.abs(v0g.grad.cpu().numpy() - 3.0 * ref_gv)) <= 1e-8 * np.max(np.abs(3.0 * ref_gv))
+    assert np.max(np.abs(v0d.grad.cpu().numpy() - 3.0 * ref_gu)) <= 1e-8 * np.max(np.abs(3.0 * ref_gu))
+
+
+def test_adjoint_rejects_unsupported():
+    prob = I.dusty_shock(n=400)
+    params = T.make_params(prob.params, T.TFSPH_F32)
+    with pytest.raises(T.TfsphError):
+        T.tfsph_adjoint_workspace_size(params, 400, 400, 10, 5)       # adiabatic + viscosity
