@@ -251,6 +251,18 @@ tfsph_status tfsph_step_adjoint(const tfsph_params *p, const tfsph_state *initia
                                 double *dL_dlog_tstop, double *loss, void *workspace, size_t ws_bytes,
                                 void *hip_stream);
 
+/* Pair-loop implementation of a context's steps.  TFSPH_VARIANT_AUTO (the
+ * default) and TFSPH_VARIANT_GLOBAL read neighbours from global memory;
+ * TFSPH_VARIANT_LDS_BRICKS stages blocks of cells and their halos in LDS for
+ * 2D/3D (density always; the fused update only when isothermal, without
+ * viscosity and with uniform gas mass, else the global loops run).  Every
+ * variant walks the neighbour window in the same order with the same
+ * arithmetic, so results are bitwise equal.  Selecting a variant drops the
+ * context's cached step graph.  Returns TFSPH_E_INVALID_ARG for an unknown
+ * variant or a null context. */
+enum { TFSPH_VARIANT_AUTO = 0, TFSPH_VARIANT_GLOBAL = 1, TFSPH_VARIANT_LDS_BRICKS = 2 };
+tfsph_status tfsph_set_kernel_variant(tfsph_ctx *ctx, int32_t variant);
+
 /* Kernel timing for measurement.  tfsph_profile(ctx, 1) starts recording a
  * HIP event pair around every launch of the timed kernels on the stream the
  * launch uses (it creates the events on the host; nothing is allocated on the

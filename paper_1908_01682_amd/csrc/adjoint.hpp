@@ -26,13 +26,13 @@
 
 namespace tfsph {
 
-// f''(q) of the cubic spline
+// f''(q) = 1.5 max(2-q, 0) - 6 max(1-q, 0) of the cubic spline
 template <typename R>
 __device__ __forceinline__ R spline_ddf(R q)
 {
-    const R inner = R(4.5) * q - R(3);
-    const R outer = R(1.5) * (R(2) - q);
-    return q < R(1) ? inner : (q < R(2) ? outer : R(0));
+    const R t2 = fmax(R(2) - q, R(0));
+    const R t1 = fmax(R(1) - q, R(0));
+    return R(1.5) * t2 - R(6) * t1;
 }
 
 // Adjoint arrays of one phase (SoA, per axis).
@@ -163,9 +163,9 @@ k_adj_force(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, const R *abar0, const R *abar1,
     R Pbar = R(0);
     R xb[3] = {R(0), R(0), R(0)};
     const R inv_h = G.inv_h;
-    for_window<R, DIM>(G, cx, cy, cz, oa, Sg.start, Sg.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz) {
+    for_window<R, DIM>(G, cx, cy, cz, oa, Sg.start, Sg.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
         const R r2 = rx * rx + ry * ry + rz * rz;
-        if (r2 < G.support2 && r2 > R(0)) {
+        if (ok && r2 < G.support2 && r2 > R(0)) {
             const R ir = frsq(r2);
             const R r = r2 * ir;
             const R qq = r * inv_h;
@@ -207,9 +207,9 @@ k_adj_density(Geom<R> G, Sorted<R> S, const R *rhobar, R *xacc0, R *xacc1, R *xa
     const R ma = me.w;
     const R ra = rhobar[a];
     R xb[3] = {R(0), R(0), R(0)};
-    for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz) {
+    for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
         const R r2 = rx * rx + ry * ry + rz * rz;
-        if (r2 < G.support2 && r2 > R(0)) {
+        if (ok && r2 < G.support2 && r2 > R(0)) {
             const R ir = frsq(r2);
             const R f1 = spline_df(r2 * ir * G.inv_h) * ir;
             const R c = (q.w * ra + ma * rhobar[b]) * f1;

@@ -16,26 +16,28 @@ constexpr int kBlock = 256;          // threads per block of the streaming kerne
 constexpr int kMaxWindow = 8;        // largest neighbour window half-width (cells)
 
 // --------------------------------------------------------------------------
-// Smoothing kernel W(h, r) of Section 2.1: M4 cubic spline, support 2h.
-// f(q) = 1 - 1.5 q^2 + 0.75 q^3 on [0,1), 0.25 (2-q)^3 on [1,2), 0 beyond;
-// W = sigma_d h^-d f(r/h).  The device code evaluates f and f' branch-free.
+// Smoothing kernel W(h, r) of Section 2.1: M4 cubic spline, support 2h,
+// W = sigma_d h^-d f(r/h) with f = 1 - 1.5 q^2 + 0.75 q^3 on [0,1),
+// 0.25 (2-q)^3 on [1,2), 0 beyond.  The same function is written here without
+// branches as f = 0.25 max(2-q, 0)^3 - max(1-q, 0)^3 (for q < 1 the two cubes
+// expand to the first polynomial), so f, f' and f'' vanish beyond the support
+// and a pair loop needs no range test.
 // --------------------------------------------------------------------------
 template <typename R>
 __device__ __forceinline__ R spline_f(R q)
 {
-    const R t = R(2) - q;
-    const R inner = R(1) + q * q * (R(0.75) * q - R(1.5));
-    const R outer = R(0.25) * t * t * t;
-    return q < R(1) ? inner : (q < R(2) ? outer : R(0));
+    const R t2 = fmax(R(2) - q, R(0));
+    const R t1 = fmax(R(1) - q, R(0));
+    return R(0.25) * t2 * t2 * t2 - t1 * t1 * t1;
 }
 
+// f'(q) = 3 max(1-q, 0)^2 - 0.75 max(2-q, 0)^2
 template <typename R>
 __device__ __forceinline__ R spline_df(R q)
 {
-    const R t = R(2) - q;
-    const R inner = q * (R(2.25) * q - R(3));
-    const R outer = R(-0.75) * t * t;
-    return q < R(1) ? inner : (q < R(2) ? outer : R(0));
+    const R t2 = fmax(R(2) - q, R(0));
+    const R t1 = fmax(R(1) - q, R(0));
+    return R(3) * t1 * t1 - R(0.75) * t2 * t2;
 }
 
 // Grid + kernel geometry of one problem (uniform periodic cells, Section 2.3).

@@ -15,10 +15,34 @@
 
 namespace tfsph {
 
+constexpr int kChunk = 4;      // candidates loaded together before any is used
+
+// Visit candidates [b0, b1) of one cell: records are loaded kChunk at a time
+// (indices clamped to the range) so one memory wait serves several candidates;
+// fn(b, q, rx, ry, rz, valid) gets the record, r = x_a - x_b and whether b is a
+// real candidate (false for the clamped padding of the last chunk).
+template <typename R, int DIM, typename Fn>
+__device__ __forceinline__ void visit_range(int b0, int b1, const R4<R> *__restrict__ data, R rx0, R ry0, R rz0,
+                                            Fn &fn)
+{
+    for (int b = b0; b < b1; b += kChunk) {
+        R4<R> q[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) q[k] = data[min(b + k, b1 - 1)];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            const R rx = rx0 - q[k].x;
+            const R ry = DIM > 1 ? ry0 - q[k].y : R(0);
+            const R rz = DIM > 2 ? rz0 - q[k].z : R(0);
+            fn(b + k, q[k], rx, ry, rz, b + k < b1);
+        }
+    }
+}
+
 // Visit every particle of a phase in the neighbour window of a point with
-// offsets oa[] in cell (cx, cy, cz).  fn(b, q, rx, ry, rz) gets the packed
-// record q = data[b] and r = x_a - x_b.  Order: window z, y, x offsets
-// ascending, then cell order.
+// offsets oa[] in cell (cx, cy, cz).  Order: window z, y, x offsets
+// ascending, then cell order.  The cell ranges of a row of the window (up to
+// 5 cells) are loaded together before the row is walked.
 template <typename R, int DIM, typename Fn>
 __device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
                                            const int *__restrict__ start, const R4<R> *__restrict__ data, Fn &&fn)
@@ -33,18 +57,28 @@ __device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int
             const int y = DIM > 1 ? wrap_index(cy + dy, G.nc[1]) : 0;
             const R ry0 = DIM > 1 ? oa[1] - R(dy) * G.delta[1] : R(0);
             const int row = G.nc[0] * (y + G.nc[1] * z);
-            for (int dx = -wx; dx <= wx; ++dx) {
-                const int x = wrap_index(cx + dx, G.nc[0]);
-                const R rx0 = oa[0] - R(dx) * G.delta[0];
-                const int lin = x + row;
-                const int b0 = start[lin];
-                const int b1 = start[lin + 1];
-                for (int b = b0; b < b1; ++b) {
-                    const R4<R> q = data[b];
-                    const R rx = rx0 - q.x;
-                    const R ry = DIM > 1 ? ry0 - q.y : R(0);
-                    const R rz = DIM > 2 ? rz0 - q.z : R(0);
-                    fn(b, q, rx, ry, rz);
+            if (wx <= 2) {
+                int bs[5], be[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    if (k <= 2 * wx) {
+                        const int lin = wrap_index(cx - wx + k, G.nc[0]) + row;
+                        bs[k] = start[lin];
+                        be[k] = start[lin + 1];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    if (k <= 2 * wx) {
+                        const R rx0 = oa[0] - R(k - wx) * G.delta[0];
+                        visit_range<R, DIM>(bs[k], be[k], data, rx0, ry0, rz0, fn);
+                    }
+                }
+            } else {
+                for (int dx = -wx; dx <= wx; ++dx) {
+                    const int lin = wrap_index(cx + dx, G.nc[0]) + row;
+                    const R rx0 = oa[0] - R(dx) * G.delta[0];
+                    visit_range<R, DIM>(start[lin], start[lin + 1], data, rx0, ry0, rz0, fn);
                 }
             }
         }
@@ -74,9 +108,10 @@ __device__ __forceinline__ R density_at(const Geom<R> &G, const Sorted<R> &S, in
     const R4<R> me = S.pos[a];
     const R oa[3] = {me.x, me.y, me.z};
     R acc = R(0);
-    for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz) {
+    for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.pos, [&](int, const R4<R> &q, R rx, R ry, R rz, bool ok) {
         const R r2 = rx * rx + ry * ry + rz * rz;
-        if (r2 < G.support2) acc += q.w * spline_f(fsqrt(r2) * G.inv_h);
+        const R m = ok ? q.w : R(0);
+        acc += m * spline_f(fsqrt(r2) * G.inv_h);
     });
     return acc * G.wnorm;
 }
@@ -126,24 +161,22 @@ __device__ __forceinline__ void gas_force_at(const Geom<R> &G, const Phys<R> &Ph
     const R mu_m = S.pos[a].w;        // uniform mass (only used when !per_mass)
     R ax = R(0), ay = R(0), az = R(0), de = R(0);
     if (!Ph.av && Ph.eos == 0) {
-        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz) {
+        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
             const R r2 = rx * rx + ry * ry + rz * rz;
-            if (r2 < G.support2 && r2 > R(0)) {
-                const R ir = frsq(r2);
-                const R mb = per_mass ? pos[b].w : mu_m;
-                const R fac = mb * (Pa + q.w) * spline_df(r2 * ir * G.inv_h) * ir;
-                ax -= fac * rx;
-                ay -= fac * ry;
-                az -= fac * rz;
-            }
+            const R ir = (ok && r2 > R(0)) ? frsq(r2) : R(0);    // self pair and padding contribute 0
+            const R mb = per_mass ? pos[b].w : mu_m;
+            const R fac = mb * (Pa + q.w) * spline_df(r2 * ir * G.inv_h) * ir;
+            ax -= fac * rx;
+            ay -= fac * ry;
+            az -= fac * rz;
         });
     } else {
         const R va[3] = {S.vel[0][a], DIM > 1 ? S.vel[1][a] : R(0), DIM > 2 ? S.vel[2][a] : R(0)};
         const R rhoa = S.rho[a];
         const R ca = sound_of(Ph, S.energy ? S.energy[a] : R(0));
-        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz) {
+        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
             const R r2 = rx * rx + ry * ry + rz * rz;
-            if (r2 < G.support2 && r2 > R(0)) {
+            if (ok && r2 < G.support2 && r2 > R(0)) {
                 const R ir = frsq(r2);
                 const R gfac = spline_df(r2 * ir * G.inv_h) * ir;   // grad_a W = gfac * gnorm * r_vec
                 const R vx = va[0] - S.vel[0][b];

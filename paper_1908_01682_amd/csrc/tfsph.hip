@@ -121,6 +121,7 @@ struct tfsph_ctx {
     KernelTimer timers[3];
     StepGraph sg;
     hipStream_t capture_stream = nullptr;
+    int variant = 0;            // 0 (auto), 1: global-memory pair loops; 2: LDS bricks where eligible
     int ng, nd;
     PhaseFlags fg, fd;
     double mg_uniform, md_uniform;
@@ -236,12 +237,12 @@ tfsph_status enqueue_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
     MARK(TFSPH_KERNEL_BIN);
     if (c->ng > 0) {
         MARK(TFSPH_KERNEL_DENSITY);
-        r = enqueue_density<R, DIM>(G, Ph, Sg, 1, st);
+        r = enqueue_density<R, DIM>(G, Ph, Sg, 1, st, c->variant);
         if (r != TFSPH_OK) return r;
         MARK(TFSPH_KERNEL_DENSITY);
     }
     MARK(TFSPH_KERNEL_UPDATE);
-    r = enqueue_update<R, DIM>(G, Ph, Sg, Sd, Pg, Pd, F, c->cells_per_block, st);
+    r = enqueue_update<R, DIM>(G, Ph, Sg, Sd, Pg, Pd, F, c->cells_per_block, st, c->variant);
     if (r != TFSPH_OK) return r;
     MARK(TFSPH_KERNEL_UPDATE);
     return TFSPH_OK;
@@ -425,6 +426,23 @@ extern "C" tfsph_status tfsph_get_flags(tfsph_ctx *c, uint32_t *flags, int64_t *
     return TFSPH_OK;
 }
 
+static void drop_graph(StepGraph &g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = StepGraph{};
+}
+
+extern "C" tfsph_status tfsph_set_kernel_variant(tfsph_ctx *c, int32_t variant)
+{
+    if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
+    if (variant < 0 || variant > 2)
+        return fail(TFSPH_E_INVALID_ARG, "unknown kernel variant %d", variant);
+    c->variant = variant;
+    drop_graph(c->sg);
+    return TFSPH_OK;
+}
+
 extern "C" tfsph_status tfsph_profile(tfsph_ctx *c, int32_t enable)
 {
     if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
@@ -471,12 +489,6 @@ static unsigned long long state_key(const tfsph_state *s, int chunk)
     return h;
 }
 
-static void drop_graph(StepGraph &g)
-{
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    if (g.graph) (void)hipGraphDestroy(g.graph);
-    g = StepGraph{};
-}
 
 extern "C" tfsph_status tfsph_step_graph(tfsph_ctx *c, tfsph_state *s, int32_t n_steps, int32_t chunk, void *hip_stream)
 {
