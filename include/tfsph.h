@@ -251,17 +251,30 @@ tfsph_status tfsph_step_adjoint(const tfsph_params *p, const tfsph_state *initia
                                 double *dL_dlog_tstop, double *loss, void *workspace, size_t ws_bytes,
                                 void *hip_stream);
 
-/* Pair-loop implementation of a context's steps.  TFSPH_VARIANT_AUTO (the
- * default) and TFSPH_VARIANT_GLOBAL read neighbours from global memory;
- * TFSPH_VARIANT_LDS_BRICKS stages blocks of cells and their halos in LDS for
- * 2D/3D (density always; the fused update only when isothermal, without
- * viscosity and with uniform gas mass, else the global loops run).  Every
- * variant walks the neighbour window in the same order with the same
- * arithmetic, so results are bitwise equal.  Selecting a variant drops the
- * context's cached step graph.  Returns TFSPH_E_INVALID_ARG for an unknown
- * variant or a null context. */
+/* Pair-loop implementation of a context's steps.
+ *  - TFSPH_VARIANT_AUTO (the default): the density pass scans the neighbour
+ *    window in global memory and records, per gas particle and window row, a
+ *    64-bit mask of the candidates inside the support (rows of at most 64
+ *    candidates, windows of at most 5 cells along x); the force pass visits
+ *    only those and scans the rest.  The masks take 8 bytes per gas particle
+ *    and row of the window in the workspace (tfsph_workspace_size).
+ *  - TFSPH_VARIANT_GLOBAL: both passes scan the whole window in global memory.
+ *  - TFSPH_VARIANT_LDS_BRICKS: blocks of cells and their halos are staged in
+ *    LDS for 2D/3D (density always; the fused update only when isothermal,
+ *    without viscosity and with uniform gas mass, else as GLOBAL).
+ * Every variant visits neighbours in the same order with the same arithmetic,
+ * and terms outside the support are exactly zero, so results are bitwise
+ * equal.  Selecting a variant drops the context's cached step graph.  Returns
+ * TFSPH_E_INVALID_ARG for an unknown variant or a null context. */
 enum { TFSPH_VARIANT_AUTO = 0, TFSPH_VARIANT_GLOBAL = 1, TFSPH_VARIANT_LDS_BRICKS = 2 };
 tfsph_status tfsph_set_kernel_variant(tfsph_ctx *ctx, int32_t variant);
+
+/* Cells owned by one 256-thread block of the update kernel (cell sums,
+ * implicit solve, particle update), in [1, 512]; the default depends on the
+ * dimension.  Results do not depend on it (each cell is summed serially by
+ * one thread).  Drops the context's cached step graph.  Returns
+ * TFSPH_E_INVALID_ARG outside that range or for a null context. */
+tfsph_status tfsph_set_cells_per_block(tfsph_ctx *ctx, int32_t cells);
 
 /* Kernel timing for measurement.  tfsph_profile(ctx, 1) starts recording a
  * HIP event pair around every launch of the timed kernels on the stream the
@@ -269,10 +282,13 @@ tfsph_status tfsph_set_kernel_variant(tfsph_ctx *ctx, int32_t variant);
  * device); tfsph_profile(ctx, 0) stops and keeps what was recorded.
  * tfsph_profile_read() synchronises, then returns the summed duration in ms
  * and the number of launches of one kernel:
- *   TFSPH_KERNEL_UPDATE  (force + predictor + cell solve + particle update),
- *   TFSPH_KERNEL_DENSITY (gas summation density),
- *   TFSPH_KERNEL_BIN     (count + scan + scatter + rank/gather, as one span). */
-enum { TFSPH_KERNEL_UPDATE = 0, TFSPH_KERNEL_DENSITY = 1, TFSPH_KERNEL_BIN = 2 };
+ *   TFSPH_KERNEL_UPDATE  (cell sums + implicit solve + particle update; with
+ *                         TFSPH_VARIANT_LDS_BRICKS also the gas force),
+ *   TFSPH_KERNEL_DENSITY (gas summation density and neighbour masks),
+ *   TFSPH_KERNEL_BIN     (count + scan + scatter + rank/gather, as one span),
+ *   TFSPH_KERNEL_FORCE   (gas pressure force + predictor).
+ * Returns TFSPH_E_INVALID_ARG for another kernel id. */
+enum { TFSPH_KERNEL_UPDATE = 0, TFSPH_KERNEL_DENSITY = 1, TFSPH_KERNEL_BIN = 2, TFSPH_KERNEL_FORCE = 3 };
 tfsph_status tfsph_profile(tfsph_ctx *ctx, int32_t enable);
 tfsph_status tfsph_profile_read(tfsph_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 

@@ -154,6 +154,7 @@ tfsph_status fwd_step(const Geom<R> &G, const Phys<R> &Ph, AdjLayout<R> &L, int 
     Sorted<R> &Sg = L.tg[slot], &Sd = L.td[slot];
     TRY(enqueue_bin<R>(L.W.g.n, L.W.d.n, G, L.W.g, L.W.d, Sg, Sd, L.partial, L.F, st));
     TRY((enqueue_density<R, DIM>(G, Ph, Sg, 1, st)));
+    TRY((enqueue_force<R, DIM>(G, Ph, Sg, L.W.g, st)));
     TRY((enqueue_update<R, DIM>(G, Ph, Sg, Sd, L.W.g, L.W.d, L.F, default_cells_per_block(DIM), st)));
     return TFSPH_OK;
 }

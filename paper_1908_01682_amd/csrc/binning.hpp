@@ -210,7 +210,13 @@ __device__ __forceinline__ void rank_gather_one(const Geom<R> &G, const Phase<R>
     const int e = S.start[c + 1];
     int rank = 0;
     if (e - b <= kMaxRankCell) {
-        for (int k = b; k < e; ++k) rank += S.tmp_id[k] < myid ? 1 : 0;
+        for (int k = b; k < e; k += kChunk) {
+            int t[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) t[u] = S.tmp_id[min(k + u, e - 1)];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) rank += (k + u < e && t[u] < myid) ? 1 : 0;
+        }
     } else {
         rank = j - b;
         atomicOr(flags, 8u);
@@ -226,6 +232,13 @@ __device__ __forceinline__ void rank_gather_one(const Geom<R> &G, const Phase<R>
     }
     S.pos[dst] = mk4<R>(o[0], o[1], o[2], P.mass ? P.mass[i] : P.m_uniform);
     if (S.energy) S.energy[dst] = P.energy[i];
+    if (j == 0) {
+        // the pair loops read up to kPad records past the end: keep them finite
+        for (int k = 0; k < kPad; ++k) {
+            S.pos[S.n + k] = mk4<R>(R(0), R(0), R(0), R(0));
+            if (S.frc) S.frc[S.n + k] = mk4<R>(R(0), R(0), R(0), R(0));
+        }
+    }
 }
 
 template <typename R>

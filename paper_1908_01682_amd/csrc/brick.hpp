@@ -155,7 +155,7 @@ __device__ __forceinline__ void for_window_halo(const Geom<R> &G, const BrickGri
             for (int dx = -wx; dx <= wx; ++dx) {
                 const R rx0 = oa[0] - R(dx) * G.delta[0];
                 const int hc = (tx + dx) + row;
-                visit_range<R, DIM>(H.hstart[hc], H.hstart[hc + 1], H.data, rx0, ry0, rz0, fn);
+                visit_range<R, DIM, false>(H.hstart[hc], H.hstart[hc + 1], H.data, rx0, ry0, rz0, fn);
             }
         }
     }
@@ -261,7 +261,9 @@ __global__ void __launch_bounds__(NT) k_density_brick(Geom<R> G, Phys<R> Ph, Sor
         const int hc = lx + B.hx * (ly + B.hy * lz);
         const int a = H.gstart[hc] + (t - sm.tstart[k]);     // global sorted index
         if (H.total < 0) {
-            density_store<R, DIM>(G, Ph, S, a, want_frc);
+            Sorted<R> Sw = S;
+            Sw.nmask = nullptr;       // bricks never use neighbour masks
+            density_store<R, DIM>(G, Ph, Sw, a, want_frc);
             continue;
         }
         const R4<R> me = sm.data[H.hstart[hc] + (t - sm.tstart[k])];
@@ -269,8 +271,9 @@ __global__ void __launch_bounds__(NT) k_density_brick(Geom<R> G, Phys<R> Ph, Sor
         R acc = R(0);
         for_window_halo<R, DIM>(G, B, H, lx, ly, lz, oa, [&](int, const R4<R> &q, R rx, R ry, R rz, bool ok) {
             const R r2 = rx * rx + ry * ry + rz * rz;
+            const R qq = fsqrt(r2) * G.inv_h;
             const R m = ok ? q.w : R(0);
-            acc += m * spline_f(fsqrt(r2) * G.inv_h);
+            acc += m * spline_f(qq);
         });
         const R rho = acc * G.wnorm;
         S.rho[a] = rho;
@@ -311,7 +314,9 @@ __global__ void __launch_bounds__(NT) k_update_brick(Geom<R> G, Phys<R> Ph, Sort
         const int hc = lx + B.hx * (ly + B.hy * lz);
         const int a = H.gstart[hc] + (t - sm.tstart[k]);
         if (H.total < 0) {
-            gas_predict<R, DIM>(G, Ph, Sg, Pg, a);
+            Sorted<R> Sw = Sg;
+            Sw.nmask = nullptr;
+            gas_predict<R, DIM>(G, Ph, Sw, Pg, a);
             continue;
         }
         const R4<R> me = sm.data[H.hstart[hc] + (t - sm.tstart[k])];
@@ -321,8 +326,9 @@ __global__ void __launch_bounds__(NT) k_update_brick(Geom<R> G, Phys<R> Ph, Sort
         R ax = R(0), ay = R(0), az = R(0);
         for_window_halo<R, DIM>(G, B, H, lx, ly, lz, oa, [&](int, const R4<R> &q, R rx, R ry, R rz, bool ok) {
             const R r2 = rx * rx + ry * ry + rz * rz;
-            const R ir = (ok && r2 > R(0)) ? frsq(r2) : R(0);
-            const R fac = mu_m * (Pa + q.w) * spline_df(r2 * ir * G.inv_h) * ir;
+            const R r = fsqrt(r2);
+            const R ir = (ok && r2 > R(0)) ? frcp(r) : R(0);
+            const R fac = mu_m * (Pa + q.w) * spline_df(r * G.inv_h) * ir;
             ax -= fac * rx;
             ay -= fac * ry;
             az -= fac * rz;

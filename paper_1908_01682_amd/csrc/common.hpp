@@ -23,22 +23,31 @@ constexpr int kMaxWindow = 8;        // largest neighbour window half-width (cel
 // expand to the first polynomial), so f, f' and f'' vanish beyond the support
 // and a pair loop needs no range test.
 // --------------------------------------------------------------------------
+// saturate to [0, 1]
+__device__ __forceinline__ float sat(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+__device__ __forceinline__ double sat(double x) { return fmin(fmax(x, 0.0), 1.0); }
+
+// For q >= 0: t1 = max(1-q, 0) = sat(1 - q) and s = max(2-q, 0) / 2 =
+// sat(1 - q/2), so f = 0.25 (2s)^3 - t1^3 = 2 s^3 - t1^3.
 template <typename R>
 __device__ __forceinline__ R spline_f(R q)
 {
-    const R t2 = fmax(R(2) - q, R(0));
-    const R t1 = fmax(R(1) - q, R(0));
-    return R(0.25) * t2 * t2 * t2 - t1 * t1 * t1;
+    const R s = sat(R(1) - R(0.5) * q);
+    const R t1 = sat(R(1) - q);
+    return R(2) * (s * s * s) - t1 * t1 * t1;
 }
 
-// f'(q) = 3 max(1-q, 0)^2 - 0.75 max(2-q, 0)^2
+// f'(q) = 3 max(1-q, 0)^2 - 0.75 max(2-q, 0)^2 = 3 (t1^2 - s^2)
 template <typename R>
 __device__ __forceinline__ R spline_df(R q)
 {
-    const R t2 = fmax(R(2) - q, R(0));
-    const R t1 = fmax(R(1) - q, R(0));
-    return R(3) * t1 * t1 - R(0.75) * t2 * t2;
+    const R s = sat(R(1) - R(0.5) * q);
+    const R t1 = sat(R(1) - q);
+    return R(3) * (t1 * t1 - s * s);
 }
+
+constexpr int kChunk = 4;      // candidates loaded together before any is used
+constexpr int kPad = kChunk;   // records past the end of a sorted pos / frc array that may be read
 
 // Grid + kernel geometry of one problem (uniform periodic cells, Section 2.3).
 template <typename R>
@@ -133,6 +142,7 @@ struct Sorted {
     int *tmp_idx;        // [n] unsorted-within-cell scatter of source indices
     int *tmp_id;         // [n] ids in the same layout
     int *src;            // nullable [n]: index in the unsorted arrays of sorted particle dst
+    unsigned long long *nmask;   // nullable [rows][n]: neighbour bits per window row (gas)
 };
 
 struct Flags {

@@ -13,6 +13,8 @@ namespace tfsph_host {
 inline int ntiles_of(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
 
 inline int default_cells_per_block(int dim) { return dim == 1 ? 128 : (dim == 2 ? 64 : 32); }
+// upper bound of tfsph_set_cells_per_block: the block's cell solves sit in LDS
+constexpr int kMaxCellsPerBlock = 512;
 
 // zero + count + scan + scatter + rank/gather of both phases into the workspace
 template <typename R>
@@ -69,7 +71,8 @@ inline BrickGrid brick_grid(const Geom<R> &G)
     return B;
 }
 
-// kernel variant: 0 (auto) and 1 = global-memory pair loops; 2 = LDS bricks where eligible
+// kernel variant: 0 (auto) and 1 = global-memory pair loops (neighbour masks
+// when S.nmask is set); 2 = LDS bricks where eligible
 template <typename R, int DIM>
 inline tfsph_status enqueue_density(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &S, int want_frc,
                                     hipStream_t st, int variant = 0)
@@ -89,14 +92,46 @@ inline tfsph_status enqueue_density(const Geom<R> &G, const Phys<R> &Ph, const S
     return TFSPH_OK;
 }
 
+// whether enqueue_update() runs the LDS-brick form, which evaluates the gas
+// force itself (else enqueue_force() must run first)
+template <typename R, int DIM>
+inline bool update_uses_bricks(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg, int variant)
+{
+    if constexpr (DIM >= 2)
+        return variant == 2 && brick_grid<R, DIM>(G).nbricks > 0 && Ph.eos == 0 && !Ph.av && !Sg.has_mass;
+    return false;
+}
+
+// Explicit gas terms and predictor v~, one thread per gas particle.  The
+// pair loop has a launch of its own: a block that owns whole cells holds a
+// varying number of particles, and the few past a multiple of the block size
+// would take a whole extra round of the pair loop.
+template <typename R, int DIM>
+inline tfsph_status enqueue_force(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg, const Phase<R> &Pg,
+                                  hipStream_t st)
+{
+    if (Sg.n == 0) return TFSPH_OK;
+    const dim3 grid(blocks_for(Sg.n)), block(kBlock);
+    if (Ph.av || Ph.eos != 0)
+        hipLaunchKernelGGL((k_gas_predict<R, DIM, kForceGeneral>), grid, block, 0, st, G, Ph, Sg, Pg);
+    else if (Sg.has_mass)
+        hipLaunchKernelGGL((k_gas_predict<R, DIM, kForceIsoMass>), grid, block, 0, st, G, Ph, Sg, Pg);
+    else
+        hipLaunchKernelGGL((k_gas_predict<R, DIM, kForceIsoUniform>), grid, block, 0, st, G, Ph, Sg, Pg);
+    LAUNCH_CHECK("gas_predict");
+    return TFSPH_OK;
+}
+
+// Cell sums, implicit solve, particle update, move and carry; the LDS-brick
+// form (variant 2, when eligible) also evaluates the gas force.
 template <typename R, int DIM>
 inline tfsph_status enqueue_update(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg, const Sorted<R> &Sd,
                                    const Phase<R> &Pg, const Phase<R> &Pd, const Flags &F, int cpb, hipStream_t st,
                                    int variant = 0)
 {
     if constexpr (DIM >= 2) {
-        const BrickGrid B = brick_grid<R, DIM>(G);
-        if (variant == 2 && B.nbricks > 0 && Ph.eos == 0 && !Ph.av && !Sg.has_mass) {
+        if (update_uses_bricks<R, DIM>(G, Ph, Sg, variant)) {
+            const BrickGrid B = brick_grid<R, DIM>(G);
             hipLaunchKernelGGL((k_update_brick<R, DIM, 512>), dim3(B.nbricks), dim3(512), 0, st, G, Ph, Sg, Sd,
                                Pg, Pd, F, B);
             LAUNCH_CHECK("update_brick");

@@ -45,6 +45,17 @@ inline int window_of(const tfsph_params *p, int d)
     return (int)std::ceil(2.0 * p->h / D - 1e-12);
 }
 
+// Rows of the neighbour window that carry a 64-bit neighbour mask per gas
+// particle: (2 wy + 1)(2 wz + 1) when the window spans at most 5 cells along x,
+// else 0 (no masks; the force pass scans the window).
+inline int mask_rows_of(const tfsph_params *p)
+{
+    if (window_of(p, 0) > 2) return 0;
+    int r = 1;
+    for (int d = 1; d < p->dim; ++d) r *= 2 * window_of(p, d) + 1;
+    return r;
+}
+
 struct Carver {
     size_t off = 0;
     char *base = nullptr;
@@ -62,6 +73,7 @@ struct PhaseFlags {
     bool mass;      // per-particle mass array present
     bool energy;    // energy array present
     bool prs;       // gas: force record and predictor scratch
+    int mask_rows = 0;   // gas: rows of neighbour bits per particle (0: no masks)
 };
 
 template <typename R>
@@ -72,8 +84,8 @@ Sorted<R> carve_phase(Carver &cv, int n, int dim, int ncell, PhaseFlags f)
     S.has_mass = f.mass ? 1 : 0;
     S.cell = cv.take<int>(n);
     S.id = cv.take<int>(n);
-    S.pos = cv.take<R4<R>>(n);
-    S.frc = f.prs ? cv.take<R4<R>>(n) : nullptr;
+    S.pos = cv.take<R4<R>>(size_t(n) + kPad);
+    S.frc = f.prs ? cv.take<R4<R>>(size_t(n) + kPad) : nullptr;
     for (int d = 0; d < 3; ++d) {
         S.vel[d] = d < dim ? cv.take<R>(n) : nullptr;
         S.vt[d] = (f.prs && d < dim) ? cv.take<R>(n) : nullptr;
@@ -85,6 +97,7 @@ Sorted<R> carve_phase(Carver &cv, int n, int dim, int ncell, PhaseFlags f)
     S.slot = cv.take<int>(n);
     S.tmp_idx = cv.take<int>(n);
     S.tmp_id = cv.take<int>(n);
+    S.nmask = f.mask_rows > 0 ? cv.take<unsigned long long>(size_t(f.mask_rows) * n) : nullptr;
     return S;
 }
 

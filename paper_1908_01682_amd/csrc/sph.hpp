@@ -2,33 +2,47 @@
 //
 // k_density  : rho_a = sum_b m_b W(|r_ab|, h) over the cell window, self
 //              included; also stores p_a / rho_a^2 for the force pass.
+// k_gas_predict : explicit gas terms of eq. (19) and the predictor v~, one
+//              thread per gas particle.
 // k_update   : one block owns a contiguous run of cells (both phases).  It
-//              evaluates the explicit gas terms of eq. (19) for its gas
-//              particles, forms the predictor v~, sums mass and momentum of
-//              each cell serially in (cell, id) order (no float atomics),
-//              solves the 2x2 implicit system of each cell in closed form,
-//              updates every particle of its cells, moves it and carries its
-//              offset back into [0, Delta).
+//              sums mass and momentum of each cell serially in (cell, id)
+//              order (no float atomics), solves the 2x2 implicit system of
+//              each cell in closed form, updates every particle of its cells,
+//              moves it and carries its offset back into [0, Delta).
 #pragma once
 
 #include "common.hpp"
 
 namespace tfsph {
 
-constexpr int kChunk = 4;      // candidates loaded together before any is used
+// Load the chunk of kChunk records starting at b of a range ending at b1.
+// Padded arrays (sorted pos / frc in global memory, kPad spare records at
+// the end) are read straight past b1 from one address; otherwise (LDS) the
+// indices are clamped to the range.
+template <bool Padded, typename V>
+__device__ __forceinline__ void load_chunk(const V *__restrict__ data, int b, int b1, V q[kChunk])
+{
+    if (Padded) {
+        const V *p = data + b;
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) q[k] = p[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) q[k] = data[min(b + k, b1 - 1)];
+    }
+}
 
 // Visit candidates [b0, b1) of one cell: records are loaded kChunk at a time
-// (indices clamped to the range) so one memory wait serves several candidates;
-// fn(b, q, rx, ry, rz, valid) gets the record, r = x_a - x_b and whether b is a
-// real candidate (false for the clamped padding of the last chunk).
-template <typename R, int DIM, typename Fn>
+// so one memory wait serves several candidates; fn(b, q, rx, ry, rz, valid)
+// gets the record, r = x_a - x_b and whether b is a real candidate (false
+// past b1 in the last chunk; such records are finite but belong elsewhere).
+template <typename R, int DIM, bool Padded = true, typename Fn>
 __device__ __forceinline__ void visit_range(int b0, int b1, const R4<R> *__restrict__ data, R rx0, R ry0, R rz0,
                                             Fn &fn)
 {
     for (int b = b0; b < b1; b += kChunk) {
         R4<R> q[kChunk];
-#pragma unroll
-        for (int k = 0; k < kChunk; ++k) q[k] = data[min(b + k, b1 - 1)];
+        load_chunk<Padded>(data, b, b1, q);
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             const R rx = rx0 - q[k].x;
@@ -39,17 +53,86 @@ __device__ __forceinline__ void visit_range(int b0, int b1, const R4<R> *__restr
     }
 }
 
+// Cell ranges [bs[k], be[k]) of one row of the window: cells cx - WX + k,
+// k = 0..2 WX (wrapped), of the row starting at linear index `row`.
+template <int WX, typename R>
+__device__ __forceinline__ void row_ranges(const Geom<R> &G, int cx, int row, const int *__restrict__ start,
+                                           int bs[2 * WX + 1], int be[2 * WX + 1])
+{
+#pragma unroll
+    for (int k = 0; k <= 2 * WX; ++k) {
+        const int lin = wrap_index(cx - WX + k, G.nc[0]) + row;
+        bs[k] = start[lin];
+        be[k] = start[lin + 1];
+    }
+}
+
+// Walk the rows of the neighbour window of cell (cx, cy, cz) for a window of
+// WX = G.win[0] cells on each side along x: window z, then y offsets
+// ascending; row_fn(r, bs, be, ry0, rz0) gets the row number, its cell ranges
+// (row_ranges) and the y / z parts of x_a - x_b before the candidate's own
+// offset is subtracted.
+template <typename R, int DIM, int WX, typename RowFn>
+__device__ __forceinline__ void for_window_rows(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
+                                                const int *__restrict__ start, RowFn &&row_fn)
+{
+    const int wz = DIM > 2 ? G.win[2] : 0;
+    const int wy = DIM > 1 ? G.win[1] : 0;
+    int r = 0;
+    for (int dz = -wz; dz <= wz; ++dz) {
+        const int z = DIM > 2 ? wrap_index(cz + dz, G.nc[2]) : 0;
+        const R rz0 = DIM > 2 ? oa[2] - R(dz) * G.delta[2] : R(0);
+        for (int dy = -wy; dy <= wy; ++dy) {
+            const int y = DIM > 1 ? wrap_index(cy + dy, G.nc[1]) : 0;
+            const R ry0 = DIM > 1 ? oa[1] - R(dy) * G.delta[1] : R(0);
+            int bs[2 * WX + 1], be[2 * WX + 1];
+            row_ranges<WX>(G, cx, G.nc[0] * (y + G.nc[1] * z), start, bs, be);
+            row_fn(r, bs, be, ry0, rz0);
+            ++r;
+        }
+    }
+}
+
+template <int V> struct IntC { static constexpr int value = V; };
+
+// Call f(IntC<wx>) for a window of wx = 1 or 2 cells along x; false (f not
+// called) for wider windows.
+template <typename F>
+__device__ __forceinline__ bool with_row_width(int wx, F &&f)
+{
+    if (wx == 1) {
+        f(IntC<1>{});
+        return true;
+    }
+    if (wx == 2) {
+        f(IntC<2>{});
+        return true;
+    }
+    return false;
+}
+
 // Visit every particle of a phase in the neighbour window of a point with
 // offsets oa[] in cell (cx, cy, cz).  Order: window z, y, x offsets
-// ascending, then cell order.  The cell ranges of a row of the window (up to
-// 5 cells) are loaded together before the row is walked.
+// ascending, then cell order.  The cell ranges of a row of the window are
+// loaded together before the row is walked.
 template <typename R, int DIM, typename Fn>
 __device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
                                            const int *__restrict__ start, const R4<R> *__restrict__ data, Fn &&fn)
 {
+    const bool rows = with_row_width(G.win[0], [&](auto W) {
+        constexpr int WX = decltype(W)::value;
+        for_window_rows<R, DIM, WX>(G, cx, cy, cz, oa, start, [&](int, const int *bs, const int *be, R ry0, R rz0) {
+#pragma unroll
+            for (int k = 0; k <= 2 * WX; ++k) {
+                const R rx0 = oa[0] - R(k - WX) * G.delta[0];
+                visit_range<R, DIM>(bs[k], be[k], data, rx0, ry0, rz0, fn);
+            }
+        });
+    });
+    if (rows) return;
+    const int wx = G.win[0];
     const int wz = DIM > 2 ? G.win[2] : 0;
     const int wy = DIM > 1 ? G.win[1] : 0;
-    const int wx = G.win[0];
     for (int dz = -wz; dz <= wz; ++dz) {
         const int z = DIM > 2 ? wrap_index(cz + dz, G.nc[2]) : 0;
         const R rz0 = DIM > 2 ? oa[2] - R(dz) * G.delta[2] : R(0);
@@ -57,32 +140,142 @@ __device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int
             const int y = DIM > 1 ? wrap_index(cy + dy, G.nc[1]) : 0;
             const R ry0 = DIM > 1 ? oa[1] - R(dy) * G.delta[1] : R(0);
             const int row = G.nc[0] * (y + G.nc[1] * z);
-            if (wx <= 2) {
-                int bs[5], be[5];
-#pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    if (k <= 2 * wx) {
-                        const int lin = wrap_index(cx - wx + k, G.nc[0]) + row;
-                        bs[k] = start[lin];
-                        be[k] = start[lin + 1];
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    if (k <= 2 * wx) {
-                        const R rx0 = oa[0] - R(k - wx) * G.delta[0];
-                        visit_range<R, DIM>(bs[k], be[k], data, rx0, ry0, rz0, fn);
-                    }
-                }
-            } else {
-                for (int dx = -wx; dx <= wx; ++dx) {
-                    const int lin = wrap_index(cx + dx, G.nc[0]) + row;
-                    const R rx0 = oa[0] - R(dx) * G.delta[0];
-                    visit_range<R, DIM>(start[lin], start[lin + 1], data, rx0, ry0, rz0, fn);
-                }
+            for (int dx = -wx; dx <= wx; ++dx) {
+                const int lin = wrap_index(cx + dx, G.nc[0]) + row;
+                const R rx0 = oa[0] - R(dx) * G.delta[0];
+                visit_range<R, DIM>(start[lin], start[lin + 1], data, rx0, ry0, rz0, fn);
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour masks.  Positions do not change between the density pass and the
+// force pass, so the density pass records, for every gas particle and every
+// row of its window, which candidates lie inside the support: bit p of row r
+// is the p-th candidate of the row in walking order (cells dx = -wx..wx, each
+// in cell order).  A row with more than 64 candidates is not recorded; the
+// force pass scans such a row.  The support test is q = sqrt(r^2) / h < 2,
+// the same q the force terms use, and those terms vanish exactly for q >= 2
+// (f'(q) = 0), so walking the set bits gives bitwise the sums of the scan.
+// Masks exist only for windows of at most 2 cells on each side along x.
+// ---------------------------------------------------------------------------
+constexpr int kMaskBits = 64;
+
+// As visit_range(), for the density pass: fn(...) returns whether the
+// candidate is a neighbour; returns those answers as bits p0 + (b - b0).
+template <typename R, int DIM, typename Fn>
+__device__ __forceinline__ unsigned long long visit_range_bits(int b0, int b1, const R4<R> *__restrict__ data, R rx0,
+                                                               R ry0, R rz0, int p0, Fn &fn)
+{
+    unsigned long long m = 0;
+    for (int b = b0; b < b1; b += kChunk) {
+        R4<R> q[kChunk];
+        load_chunk<true>(data, b, b1, q);
+        unsigned nib = 0;
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            const R rx = rx0 - q[k].x;
+            const R ry = DIM > 1 ? ry0 - q[k].y : R(0);
+            const R rz = DIM > 2 ? rz0 - q[k].z : R(0);
+            nib |= fn(b + k, q[k], rx, ry, rz, b + k < b1) ? (1u << k) : 0u;
+        }
+        // bits past 63 only occur in rows longer than kMaskBits, which are
+        // never read back
+        m |= (unsigned long long)nib << ((p0 + b - b0) & (kMaskBits - 1));
+    }
+    return m;
+}
+
+// Walk the window of a point like for_window() and store the neighbour mask
+// of each row at mask[r * stride] (window of at most 2 cells along x).
+template <typename R, int DIM, typename Fn>
+__device__ __forceinline__ void for_window_recording(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
+                                                     const int *__restrict__ start, const R4<R> *__restrict__ data,
+                                                     unsigned long long *mask, int stride, Fn &&fn)
+{
+    with_row_width(G.win[0], [&](auto W) {
+        constexpr int WX = decltype(W)::value;
+        for_window_rows<R, DIM, WX>(G, cx, cy, cz, oa, start, [&](int r, const int *bs, const int *be, R ry0, R rz0) {
+            unsigned long long m = 0;
+            int p0 = 0;
+#pragma unroll
+            for (int k = 0; k <= 2 * WX; ++k) {
+                const R rx0 = oa[0] - R(k - WX) * G.delta[0];
+                m |= visit_range_bits<R, DIM>(bs[k], be[k], data, rx0, ry0, rz0, p0, fn);
+                p0 += be[k] - bs[k];
+            }
+            mask[size_t(r) * stride] = m;
+        });
+    });
+}
+
+// Visit the neighbours of a point recorded in mask[r * stride] (rows of at
+// most kMaskBits candidates) or, for longer rows, every candidate of the row;
+// fn(b, q, rx, ry, rz, valid) as for for_window().  Neighbours are taken kChunk
+// at a time; a lane with fewer left repeats its last one with valid = false.
+template <typename R, int DIM, typename Fn>
+__device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
+                                               const int *__restrict__ start, const R4<R> *__restrict__ data,
+                                               const unsigned long long *__restrict__ mask, int stride, Fn &&fn)
+{
+    with_row_width(G.win[0], [&](auto W) {
+        constexpr int WX = decltype(W)::value;
+        for_window_rows<R, DIM, WX>(G, cx, cy, cz, oa, start, [&](int r, const int *bs, const int *be, R ry0, R rz0) {
+            // first walking position of each cell in the row, and the cell's
+            // index shift and x part of x_a - x_b
+            int P[2 * WX + 1], shift[2 * WX + 1];
+            R rx0[2 * WX + 1];
+            int len = 0;
+#pragma unroll
+            for (int k = 0; k <= 2 * WX; ++k) {
+                P[k] = len;
+                shift[k] = bs[k] - len;
+                rx0[k] = oa[0] - R(k - WX) * G.delta[0];
+                len += be[k] - bs[k];
+            }
+            if (len > kMaskBits) {
+#pragma unroll
+                for (int k = 0; k <= 2 * WX; ++k) visit_range<R, DIM>(bs[k], be[k], data, rx0[k], ry0, rz0, fn);
+                return;
+            }
+            unsigned long long m = mask[size_t(r) * stride];
+            int p = 0;
+            while (m) {
+                int b[kChunk];
+                R x0[kChunk];
+                bool ok[kChunk];
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    ok[j] = m != 0;
+                    // m | bit 63 keeps the count defined when m is empty
+                    const int pj = __builtin_ctzll(m | (1ull << 63));
+                    p = ok[j] ? pj : p;
+                    m &= m - 1;
+                    int sh = shift[0];
+                    R xx = rx0[0];
+#pragma unroll
+                    for (int k = 1; k <= 2 * WX; ++k) {
+                        const bool ge = p >= P[k];
+                        sh = ge ? shift[k] : sh;
+                        xx = ge ? rx0[k] : xx;
+                    }
+                    b[j] = p + sh;
+                    x0[j] = xx;
+                }
+                R4<R> q[kChunk];
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) q[j] = data[b[j]];
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    const R rx = x0[j] - q[j].x;
+                    const R ry = DIM > 1 ? ry0 - q[j].y : R(0);
+                    const R rz = DIM > 2 ? rz0 - q[j].z : R(0);
+                    fn(b[j], q[j], rx, ry, rz, ok[j]);
+                }
+            }
+        });
+    });
 }
 
 template <typename R>
@@ -98,31 +291,38 @@ __device__ __forceinline__ R sound_of(const Phys<R> &Ph, R e)
 }
 
 // --------------------------------------------------------------------------
-// Summation density of phase S at its own sorted particle a.
+// Summation density of phase S at its own sorted particle a.  With `record`
+// (gas, masks allocated) the neighbour mask rows of a are stored as well.
 // --------------------------------------------------------------------------
 template <typename R, int DIM>
-__device__ __forceinline__ R density_at(const Geom<R> &G, const Sorted<R> &S, int a)
+__device__ __forceinline__ R density_at(const Geom<R> &G, const Sorted<R> &S, int a, bool record = false)
 {
     int cx, cy, cz;
     split_cell(G, S.cell[a], cx, cy, cz);
     const R4<R> me = S.pos[a];
     const R oa[3] = {me.x, me.y, me.z};
     R acc = R(0);
-    for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.pos, [&](int, const R4<R> &q, R rx, R ry, R rz, bool ok) {
+    auto term = [&](int, const R4<R> &q, R rx, R ry, R rz, bool ok) {
         const R r2 = rx * rx + ry * ry + rz * rz;
+        const R qq = fsqrt(r2) * G.inv_h;
         const R m = ok ? q.w : R(0);
-        acc += m * spline_f(fsqrt(r2) * G.inv_h);
-    });
+        acc += m * spline_f(qq);
+        return ok && qq < R(2);
+    };
+    if (record && S.nmask)
+        for_window_recording<R, DIM>(G, cx, cy, cz, oa, S.start, S.pos, S.nmask + a, S.n, term);
+    else
+        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.pos, term);
     return acc * G.wnorm;
 }
 
 // density of particle a into S.rho[a]; with want_frc also the force-pass
-// record (ox, oy, oz, p / rho^2)
+// record (ox, oy, oz, p / rho^2) and, when allocated, the neighbour masks
 template <typename R, int DIM>
 __device__ __forceinline__ void density_store(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &S, int a,
                                               int want_frc)
 {
-    const R rho = density_at<R, DIM>(G, S, a);
+    const R rho = density_at<R, DIM>(G, S, a, want_frc != 0);
     S.rho[a] = rho;
     if (want_frc) {
         const R e = S.energy ? S.energy[a] : R(0);
@@ -131,10 +331,21 @@ __device__ __forceinline__ void density_store(const Geom<R> &G, const Phys<R> &P
     }
 }
 
+// Block-to-work map.  Consecutive block ids land on different XCDs
+// (round-robin dispatch over 8 XCDs); remap so that each XCD works on one
+// contiguous slab of cells and the neighbour halos stay in its own L2.
+__device__ __forceinline__ int xcd_block(int nblocks)
+{
+    const int b = blockIdx.x;
+    const int per = nblocks / 8;
+    if (per == 0 || b >= per * 8) return b;
+    return (b % 8) * per + b / 8;
+}
+
 template <typename R, int DIM>
 __global__ void __launch_bounds__(kBlock) k_density(Geom<R> G, Phys<R> Ph, Sorted<R> S, int want_frc)
 {
-    const int a = blockIdx.x * kBlock + threadIdx.x;
+    const int a = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (a >= S.n) return;
     density_store<R, DIM>(G, Ph, S, a, want_frc);
 }
@@ -147,7 +358,19 @@ __global__ void __launch_bounds__(kBlock) k_density(Geom<R> G, Phys<R> Ph, Sorte
 //   Pi_ab = (-alpha cbar mu + beta mu^2) / rhobar  if v_ab . r_ab < 0
 //   mu    = h v_ab . r_ab / (r^2 + 0.01 h^2)
 // --------------------------------------------------------------------------
-template <typename R, int DIM>
+// Kinds of gas force loop: isothermal without viscosity and with a uniform
+// mass (the common case), the same with per-particle masses, and the general
+// one (artificial viscosity and / or the adiabatic EOS with de/dt).
+enum { kForceIsoUniform = 0, kForceIsoMass = 1, kForceGeneral = 2 };
+
+template <typename R>
+__device__ __forceinline__ int force_kind(const Phys<R> &Ph, const Sorted<R> &S)
+{
+    if (Ph.av || Ph.eos != 0) return kForceGeneral;
+    return S.has_mass ? kForceIsoMass : kForceIsoUniform;
+}
+
+template <typename R, int DIM, int KIND>
 __device__ __forceinline__ void gas_force_at(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &S, int a,
                                              R acc[3], R &dedt)
 {
@@ -156,29 +379,38 @@ __device__ __forceinline__ void gas_force_at(const Geom<R> &G, const Phys<R> &Ph
     const R4<R> me = S.frc[a];
     const R oa[3] = {me.x, me.y, me.z};
     const R Pa = me.w;
-    const bool per_mass = S.has_mass != 0;
     const R4<R> *pos = S.pos;
-    const R mu_m = S.pos[a].w;        // uniform mass (only used when !per_mass)
+    const R mu_m = S.pos[a].w;        // uniform mass (kForceIsoUniform)
     R ax = R(0), ay = R(0), az = R(0), de = R(0);
-    if (!Ph.av && Ph.eos == 0) {
-        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
+    // neighbours from the masks of the density pass when present, else the window
+    auto visit = [&](auto &&fn) {
+        if (S.nmask)
+            for_neighbours<R, DIM>(G, cx, cy, cz, oa, S.start, S.frc, S.nmask + a, S.n, fn);
+        else
+            for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.frc, fn);
+    };
+    if constexpr (KIND != kForceGeneral) {
+        visit([&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
             const R r2 = rx * rx + ry * ry + rz * rz;
-            const R ir = (ok && r2 > R(0)) ? frsq(r2) : R(0);    // self pair and padding contribute 0
-            const R mb = per_mass ? pos[b].w : mu_m;
-            const R fac = mb * (Pa + q.w) * spline_df(r2 * ir * G.inv_h) * ir;
+            const R r = fsqrt(r2);
+            const R ir = (ok && r2 > R(0)) ? frcp(r) : R(0);    // self pair and padding contribute 0
+            const R mb = KIND == kForceIsoMass ? pos[b].w : mu_m;
+            const R fac = mb * (Pa + q.w) * spline_df(r * G.inv_h) * ir;
             ax -= fac * rx;
             ay -= fac * ry;
             az -= fac * rz;
         });
     } else {
+        const bool per_mass = S.has_mass != 0;
         const R va[3] = {S.vel[0][a], DIM > 1 ? S.vel[1][a] : R(0), DIM > 2 ? S.vel[2][a] : R(0)};
         const R rhoa = S.rho[a];
         const R ca = sound_of(Ph, S.energy ? S.energy[a] : R(0));
-        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
+        visit([&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
             const R r2 = rx * rx + ry * ry + rz * rz;
-            if (ok && r2 < G.support2 && r2 > R(0)) {
-                const R ir = frsq(r2);
-                const R gfac = spline_df(r2 * ir * G.inv_h) * ir;   // grad_a W = gfac * gnorm * r_vec
+            const R r = fsqrt(r2);
+            const R qq = r * G.inv_h;
+            if (ok && qq < R(2) && r2 > R(0)) {
+                const R gfac = spline_df(qq) * frcp(r);   // grad_a W = gfac * gnorm * r_vec
                 const R vx = va[0] - S.vel[0][b];
                 const R vy = DIM > 1 ? va[1] - S.vel[1][b] : R(0);
                 const R vz = DIM > 2 ? va[2] - S.vel[2][b] : R(0);
@@ -204,6 +436,18 @@ __device__ __forceinline__ void gas_force_at(const Geom<R> &G, const Phys<R> &Ph
     acc[1] = ay * G.gnorm;
     acc[2] = az * G.gnorm;
     dedt = de * G.gnorm;
+}
+
+// gas force of particle a with the loop kind picked at run time
+template <typename R, int DIM>
+__device__ __forceinline__ void gas_force_any(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &S, int a,
+                                              R acc[3], R &dedt)
+{
+    switch (force_kind(Ph, S)) {
+    case kForceIsoUniform: gas_force_at<R, DIM, kForceIsoUniform>(G, Ph, S, a, acc, dedt); break;
+    case kForceIsoMass: gas_force_at<R, DIM, kForceIsoMass>(G, Ph, S, a, acc, dedt); break;
+    default: gas_force_at<R, DIM, kForceGeneral>(G, Ph, S, a, acc, dedt); break;
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -238,17 +482,43 @@ __device__ __forceinline__ void cell_sums(const Phys<R> &Ph, const Sorted<R> &Sg
     const int d0 = Sd.start[c], d1 = Sd.start[c + 1];
     R Mg = R(0), Md = R(0);
     R Pg[3] = {R(0), R(0), R(0)}, Pd[3] = {R(0), R(0), R(0)};
-    for (int a = g0; a < g1; ++a) {
-        const R m = Sg.pos[a].w;
-        Mg += m;
+    // particles are loaded kChunk at a time (indices clamped to the cell) and
+    // then added one by one in cell order
+    for (int a = g0; a < g1; a += kChunk) {
+        R m[kChunk], v[kChunk][3];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) Pg[d] += m * Sg.vt[d][a];
+        for (int k = 0; k < kChunk; ++k) {
+            const int i = min(a + k, g1 - 1);
+            m[k] = Sg.pos[i].w;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) v[k][d] = Sg.vt[d][i];
+        }
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            if (a + k < g1) {
+                Mg += m[k];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) Pg[d] += m[k] * v[k][d];
+            }
+        }
     }
-    for (int j = d0; j < d1; ++j) {
-        const R m = Sd.pos[j].w;
-        Md += m;
+    for (int j = d0; j < d1; j += kChunk) {
+        R m[kChunk], u[kChunk][3];
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) Pd[d] += m * (Sd.vel[d][j] + Ph.tau * Ph.g[d]);
+        for (int k = 0; k < kChunk; ++k) {
+            const int i = min(j + k, d1 - 1);
+            m[k] = Sd.pos[i].w;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) u[k][d] = Sd.vel[d][i];
+        }
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            if (j + k < d1) {
+                Md += m[k];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) Pd[d] += m[k] * (u[k][d] + Ph.tau * Ph.g[d]);
+            }
+        }
     }
     S.ng = g1 - g0;
     S.nd = d1 - d0;
@@ -293,25 +563,17 @@ __device__ __forceinline__ bool solve_cell(const Phys<R> &Ph, const Sorted<R> &S
     return solve_from_sums<R, DIM>(Ph, S, out);
 }
 
-// Block-to-cell-range map.  Consecutive block ids land on different XCDs
-// (round-robin dispatch over 8 XCDs); remap so that each XCD works on one
-// contiguous slab of cell ranges and neighbour halos stay in its own L2.
-__device__ __forceinline__ int xcd_block(int nblocks)
-{
-    const int b = blockIdx.x;
-    const int per = nblocks / 8;
-    if (per == 0 || b >= per * 8) return b;
-    return (b % 8) * per + b / 8;
-}
-
 // Explicit part of eq. (19) for sorted gas particle a: v~ = v + tau (A + g)
 // into the predictor scratch, e += tau de/dt into the caller's energy array.
-template <typename R, int DIM>
+template <typename R, int DIM, int KIND = -1>
 __device__ __forceinline__ void gas_predict(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg,
                                             const Phase<R> &Pg, int a)
 {
     R acc[3], dedt;
-    gas_force_at<R, DIM>(G, Ph, Sg, a, acc, dedt);
+    if constexpr (KIND < 0)
+        gas_force_any<R, DIM>(G, Ph, Sg, a, acc, dedt);
+    else
+        gas_force_at<R, DIM, KIND>(G, Ph, Sg, a, acc, dedt);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) Sg.vt[d][a] = Sg.vel[d][a] + Ph.tau * (acc[d] + Ph.g[d]);
     if (Sg.energy) Pg.energy[a] = Sg.energy[a] + Ph.tau * dedt;
@@ -374,6 +636,18 @@ __device__ __forceinline__ bool dust_finish(const Geom<R> &G, const Phys<R> &Ph,
     return ok;
 }
 
+// Explicit gas terms and predictor, one thread per gas particle (the form
+// used when the update kernel is told the predictor already ran).
+template <typename R, int DIM, int KIND>
+__global__ void __launch_bounds__(kBlock) k_gas_predict(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Phase<R> Pg)
+{
+    const int a = xcd_block(gridDim.x) * kBlock + threadIdx.x;
+    if (a >= Sg.n) return;
+    gas_predict<R, DIM, KIND>(G, Ph, Sg, Pg, a);
+}
+
+// Cell sums, implicit solve and particle updates of a contiguous run of cells
+// per block; the predictor v~ (and e) of the gas comes from k_gas_predict.
 template <typename R, int DIM>
 __global__ void __launch_bounds__(kBlock)
 k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R> Pd, Flags F, int cells_per_block,
@@ -387,19 +661,17 @@ k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R
     const int c1 = min(c0 + cells_per_block, G.ncell);
     if (threadIdx.x == 0) { s_bad = 0; s_one = 0; }
 
-    // (1) explicit gas terms and predictor v~ (eq. 19, explicit part)
     const int ga = Sg.start[c0], gb = Sg.start[c1];
-    for (int a = ga + threadIdx.x; a < gb; a += kBlock) gas_predict<R, DIM>(G, Ph, Sg, Pg, a);
     __syncthreads();
 
-    // (2) per-cell sums in canonical order and the implicit solve
+    // (1) per-cell sums in canonical order and the implicit solve
     int one = 0;
     for (int c = c0 + threadIdx.x; c < c1; c += kBlock)
         one += solve_cell<R, DIM>(Ph, Sg, Sd, c, cs[c - c0]) ? 1 : 0;
     if (one) atomicAdd(&s_one, one);
     __syncthreads();
 
-    // (3) implicit particle update (eqs. 19-20), position update, carry
+    // (2) implicit particle update (eqs. 19-20), position update, carry
     int bad = 0;
     for (int a = ga + threadIdx.x; a < gb; a += kBlock)
         bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0]);

@@ -118,10 +118,10 @@ struct StepGraph {
 struct tfsph_ctx {
     tfsph_params p;
     bool profiling = false;
-    KernelTimer timers[3];
+    KernelTimer timers[4];
     StepGraph sg;
     hipStream_t capture_stream = nullptr;
-    int variant = 0;            // 0 (auto), 1: global-memory pair loops; 2: LDS bricks where eligible
+    int variant = 0;            // TFSPH_VARIANT_*
     int ng, nd;
     PhaseFlags fg, fd;
     double mg_uniform, md_uniform;
@@ -153,7 +153,7 @@ static tfsph_status timer_mark(tfsph_ctx *c, int k, hipStream_t st)
 
 static PhaseFlags gas_flags(const tfsph_params *p, bool mass_array)
 {
-    return PhaseFlags{mass_array, p->eos == TFSPH_ADIABATIC, true};
+    return PhaseFlags{mass_array, p->eos == TFSPH_ADIABATIC, true, mask_rows_of(p)};
 }
 
 static PhaseFlags dust_flags(bool mass_array) { return PhaseFlags{mass_array, false, false}; }
@@ -231,6 +231,7 @@ tfsph_status enqueue_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
     int *partial;
     Flags F;
     carve_all<R>(c, Sg, Sd, partial, F);
+    if (c->variant != TFSPH_VARIANT_AUTO) Sg.nmask = nullptr;    // scan the whole window in both passes
     MARK(TFSPH_KERNEL_BIN);
     tfsph_status r = enqueue_bin<R>(c->ng, c->nd, G, Pg, Pd, Sg, Sd, partial, F, st);
     if (r != TFSPH_OK) return r;
@@ -240,6 +241,12 @@ tfsph_status enqueue_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
         r = enqueue_density<R, DIM>(G, Ph, Sg, 1, st, c->variant);
         if (r != TFSPH_OK) return r;
         MARK(TFSPH_KERNEL_DENSITY);
+    }
+    if (c->ng > 0 && !update_uses_bricks<R, DIM>(G, Ph, Sg, c->variant)) {
+        MARK(TFSPH_KERNEL_FORCE);
+        r = enqueue_force<R, DIM>(G, Ph, Sg, Pg, st);
+        if (r != TFSPH_OK) return r;
+        MARK(TFSPH_KERNEL_FORCE);
     }
     MARK(TFSPH_KERNEL_UPDATE);
     r = enqueue_update<R, DIM>(G, Ph, Sg, Sd, Pg, Pd, F, c->cells_per_block, st, c->variant);
@@ -433,6 +440,16 @@ static void drop_graph(StepGraph &g)
     g = StepGraph{};
 }
 
+extern "C" tfsph_status tfsph_set_cells_per_block(tfsph_ctx *c, int32_t cells)
+{
+    if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
+    if (cells < 1 || cells > kMaxCellsPerBlock)
+        return fail(TFSPH_E_INVALID_ARG, "cells per block %d outside [1, %d]", cells, kMaxCellsPerBlock);
+    c->cells_per_block = cells;
+    drop_graph(c->sg);
+    return TFSPH_OK;
+}
+
 extern "C" tfsph_status tfsph_set_kernel_variant(tfsph_ctx *c, int32_t variant)
 {
     if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
@@ -456,7 +473,7 @@ extern "C" tfsph_status tfsph_profile(tfsph_ctx *c, int32_t enable)
 extern "C" tfsph_status tfsph_profile_read(tfsph_ctx *c, int32_t kernel, double *total_ms, int64_t *launches)
 {
     if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
-    if (kernel < 0 || kernel > 2) return fail(TFSPH_E_INVALID_ARG, "unknown kernel id %d", kernel);
+    if (kernel < 0 || kernel > 3) return fail(TFSPH_E_INVALID_ARG, "unknown kernel id %d", kernel);
     KernelTimer &T = c->timers[kernel];
     double sum = 0.0;
     for (size_t i = 0; i + 1 < T.used; i += 2) {

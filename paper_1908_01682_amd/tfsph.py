@@ -87,6 +87,7 @@ def lib():
         L.tfsph_cells_to_positions.argtypes = [P, ctypes.c_int64, vp, ctypes.c_void_p * 3, vp, vp]
         L.tfsph_profile.argtypes = [vp, ctypes.c_int32]
         L.tfsph_set_kernel_variant.argtypes = [vp, ctypes.c_int32]
+        L.tfsph_set_cells_per_block.argtypes = [vp, ctypes.c_int32]
         L.tfsph_profile_read.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]
         L.tfsph_step_graph.argtypes = [vp, ctypes.POINTER(StateC), ctypes.c_int32, ctypes.c_int32, vp]
@@ -104,7 +105,7 @@ def lib():
                                          ctypes.c_void_p * 3, vp, vp, vp, ctypes.c_size_t, vp]
         for name in ("tfsph_validate", "tfsph_workspace_size", "tfsph_init", "tfsph_step", "tfsph_density",
                      "tfsph_get_flags", "tfsph_destroy", "tfsph_positions_to_cells", "tfsph_cells_to_positions",
-                     "tfsph_profile", "tfsph_profile_read", "tfsph_set_kernel_variant", "tfsph_step_graph", "tfsph_batch_workspace_size",
+                     "tfsph_profile", "tfsph_profile_read", "tfsph_set_kernel_variant", "tfsph_set_cells_per_block", "tfsph_step_graph", "tfsph_batch_workspace_size",
                      "tfsph_batch_init", "tfsph_batch_set_tuning", "tfsph_step_batched", "tfsph_step_batched_graph",
                      "tfsph_batch_get_flags", "tfsph_batch_destroy", "tfsph_adjoint_workspace_size",
                      "tfsph_step_adjoint"):
@@ -186,7 +187,7 @@ def tfsph_get_flags(ctx):
     return int(f.value), int(n.value)
 
 
-TFSPH_KERNEL_UPDATE, TFSPH_KERNEL_DENSITY, TFSPH_KERNEL_BIN = 0, 1, 2
+TFSPH_KERNEL_UPDATE, TFSPH_KERNEL_DENSITY, TFSPH_KERNEL_BIN, TFSPH_KERNEL_FORCE = 0, 1, 2, 3
 
 
 TFSPH_VARIANT_AUTO, TFSPH_VARIANT_GLOBAL, TFSPH_VARIANT_LDS_BRICKS = 0, 1, 2
@@ -194,6 +195,10 @@ TFSPH_VARIANT_AUTO, TFSPH_VARIANT_GLOBAL, TFSPH_VARIANT_LDS_BRICKS = 0, 1, 2
 
 def tfsph_set_kernel_variant(ctx, variant: int) -> None:
     _check(lib().tfsph_set_kernel_variant(ctx, int(variant)), "tfsph_set_kernel_variant")
+
+
+def tfsph_set_cells_per_block(ctx, cells: int) -> None:
+    _check(lib().tfsph_set_cells_per_block(ctx, int(cells)), "tfsph_set_cells_per_block")
 
 
 def tfsph_profile(ctx, enable: bool) -> None:

@@ -118,3 +118,20 @@ def test_init_rejects_bad_arguments_before_any_device_work(lib):
     # NULL ctx pointer for step
     assert T.lib().tfsph_step(None, ctypes.byref(st), 1, None) == -1
     assert T.lib().tfsph_status_string(-2) == b"TFSPH_E_WORKSPACE"
+
+
+def test_tuning_calls_reject_null_context(lib):
+    """The tuning entry points validate on the host and never touch a device without a context."""
+    L = T.lib()
+    assert L.tfsph_set_kernel_variant(None, 0) == -1
+    assert L.tfsph_set_cells_per_block(None, 32) == -1
+    assert L.tfsph_profile(None, 1) == -1
+
+
+def test_workspace_holds_neighbour_masks(lib):
+    """AUTO keeps 8 bytes per gas particle and window row for the neighbour masks: 9 rows in 3D
+    with a one-cell window (h = dx, cells of 2h), so 1000 more gas particles need at least 72 kB."""
+    p = T.make_params(I.dusty_box(n_side=16, cells_per_axis=8).params)
+    a = T.tfsph_workspace_size(p, 4096, 4096)
+    b = T.tfsph_workspace_size(p, 5096, 4096)
+    assert b - a >= 1000 * 8 * 9

@@ -296,24 +296,58 @@ def test_full_size_one_step(orc, name):
     ("box3d_bricks", lambda: I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4), 0),
     ("box3d_ragged_bricks", lambda: I.dusty_box(n_side=26, cells_per_axis=13, regions_per_axis=1), 0),
     ("box3d_overflow_fallback", lambda: I.dusty_box(n_side=24, cells_per_axis=8, regions_per_axis=2), 0),
+    ("box3d_mixed_mask_rows", lambda: I.dusty_box(n_side=20, cells_per_axis=8, regions_per_axis=2), 0),
     ("box3d_bricks_f64", lambda: I.dusty_box(n_side=20, cells_per_axis=10, regions_per_axis=2), 1),
     ("wave2d_bricks", lambda: I.wave_2d(n_side=100, amp=1e-2), 0),
     ("wave2d_bricks_f64", lambda: I.wave_2d(n_side=36, amp=1e-2), 1),
+    ("shock1d_viscosity", lambda: I.dusty_shock(n=4000), 0),
+    ("wave1d_f64", lambda: I.dusty_wave(n_side=400, amp=1e-2), 1),
 ], ids=lambda v: v if isinstance(v, str) else "")
-def test_lds_bricks_bitwise_equal_global_loops(name, make, precision):
-    """LDS-staged cell bricks walk the window in the same order with the same arithmetic as the
-    global-memory loops: every step must agree bit for bit (including bricks whose halo overflows
-    the LDS and fall back, and bricks sticking out of a ragged grid)."""
+def test_pair_loop_variants_bitwise_equal(name, make, precision):
+    """Neighbour masks (default), full window scans and LDS-staged cell bricks visit neighbours in
+    the same order with the same arithmetic, and terms outside the support are exactly zero: every
+    step must agree bit for bit.  The cases cover bricks whose halo overflows the LDS, bricks
+    sticking out of a ragged grid, mask rows longer than 64 candidates (scanned instead) next to
+    short ones, viscosity with a per-particle mass and an adiabatic EOS (1D shock) and FP64."""
     prob = make()
     out = []
-    for variant in (T.TFSPH_VARIANT_LDS_BRICKS, T.TFSPH_VARIANT_GLOBAL):
+    for variant in (T.TFSPH_VARIANT_AUTO, T.TFSPH_VARIANT_GLOBAL, T.TFSPH_VARIANT_LDS_BRICKS):
         sim = _sim(prob, precision)
         T.tfsph_set_kernel_variant(sim.ctx, variant)
         sim.step(6)
         torch.cuda.synchronize()
         out.append((sim.gas.numpy(), sim.dust.numpy()))
+        flags, _ = sim.flags()
+        assert not flags & T.TFSPH_FLAG_NONFINITE
         sim.close()
-    for k in ("cell", "id", "off", "vel", "rho"):
-        assert np.array_equal(out[0][0][k], out[1][0][k]), k
-        if out[0][1][k] is not None:
-            assert np.array_equal(out[0][1][k], out[1][1][k]), k
+    for other in out[1:]:
+        for k in ("cell", "id", "off", "vel", "rho", "energy"):
+            if out[0][0].get(k) is not None:
+                assert np.array_equal(out[0][0][k], other[0][k]), k
+            if out[0][1].get(k) is not None:
+                assert np.array_equal(out[0][1][k], other[1][k]), k
+
+
+@pytest.mark.parametrize("name,make,precision", [
+    ("box3d", lambda: I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4), 0),
+    ("wave2d_f64", lambda: I.wave_2d(n_side=48, amp=1e-2), 1),
+    ("shock1d", lambda: I.dusty_shock(n=3000), 0),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_cells_per_block_bitwise_invariant(name, make, precision):
+    """Every cell is summed serially by one thread whatever the number of cells a block owns:
+    the state after several steps is bitwise the same for 1, 37 and 512 cells per block."""
+    prob = make()
+    out = []
+    for cpb in (None, 1, 37, 512):
+        sim = _sim(prob, precision)
+        if cpb is not None:
+            T.tfsph_set_cells_per_block(sim.ctx, cpb)
+        sim.step(4)
+        torch.cuda.synchronize()
+        out.append((sim.gas.numpy(), sim.dust.numpy()))
+        sim.close()
+    for other in out[1:]:
+        for k in ("cell", "id", "off", "vel", "rho"):
+            assert np.array_equal(out[0][0][k], other[0][k]), k
+            if out[0][1].get(k) is not None:
+                assert np.array_equal(out[0][1][k], other[1][k]), k
