@@ -3,10 +3,13 @@
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload box3d|shock1d|wave2d]
 
 Prints ONE JSON line: gas+dust particle-steps/s of whole IDIC steps
-(bin -> density -> force + predictor + cell solve + update) with inputs
-resident in HBM, the HBM roofline of the dominant kernel (its launches timed
-with HIP events on the stream they run on), and the FP64 CPU oracle timed on
-the host cores on a bounded sample of the same workload.
+(bin -> density -> force + predictor -> cell solve + update) with inputs
+resident in HBM; the roofline of the dominant kernel (its launches timed with
+HIP events on the stream they run on; the pair kernels are bound by vector
+ALU work, priced in algorithmic flops against the FP32 vector peak, the update
+kernel by HBM bytes); the whole step's algorithmic HBM bytes against the HBM
+peak; and the FP64 CPU oracle timed on the host cores on a bounded sample of
+the same workload.
 """
 from __future__ import annotations
 
@@ -23,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3      # MI355X vector FP32 (packed); FP64 vector 78.6
+FP64_PEAK_TFLOPS = 78.6
 METRIC = "gas+dust particle-steps/s per GPU (% HBM roofline); adjoint/forward time ratio"
 
 WORKLOADS = {
@@ -31,15 +36,50 @@ WORKLOADS = {
     "wave2d": "2D periodic dusty wave, 512^2 gas + 512^2 dust, 256^2 cells, t_stop 1e-3, FP32",
 }
 
+# floating-point operations the method needs, per unit (see the roofline notes in bench output)
+FLOPS_PER_CANDIDATE = 8       # r^2 of a window candidate: 3 sub + 3 mul + 2 add
+FLOPS_PER_DENSITY_PAIR = 13   # q = sqrt(r^2)/h (2), f(q) (9), m f accumulated (2)
+FLOPS_PER_FORCE_PAIR = 28     # r^2 (8), r and 1/r (2), q (1), f'(q) (7), m (P_a+P_b) f'/r (4), 3 fma (6)
+
+
+def window_candidates(prob) -> int:
+    """Sum over gas particles of the gas population of their neighbour-cell window (the
+    candidates a cell-list search must test), from the initial cell counts."""
+    p = prob.params
+    d = p.dim
+    nc = np.array(p.n_cells[:d])
+    lo, hi = np.array(p.lo[:d]), np.array(p.hi[:d])
+    delta = (hi - lo) / nc
+    win = np.ceil(2.0 * p.h / delta - 1e-12).astype(int)
+    cell = np.floor((np.mod(prob.gas.x - lo, hi - lo)) / delta).astype(np.int64)
+    cell = np.minimum(cell, nc - 1)
+    counts = np.zeros(tuple(nc), dtype=np.int64)
+    np.add.at(counts, tuple(cell.T), 1)
+    wsum = np.zeros_like(counts)
+    import itertools
+    for off in itertools.product(*[range(-w, w + 1) for w in win]):
+        wsum += np.roll(counts, shift=tuple(-o for o in off), axis=tuple(range(d)))
+    return int((counts * wsum).sum())
+
+
+def support_pairs(prob) -> int:
+    """Sum over gas particles of the gas particles within 2h (self included), periodic."""
+    from scipy.spatial import cKDTree
+    p = prob.params
+    d = p.dim
+    lo, hi = np.array(p.lo[:d]), np.array(p.hi[:d])
+    x = np.mod(prob.gas.x - lo, hi - lo)
+    tree = cKDTree(x, boxsize=hi - lo)
+    n = tree.query_ball_point(x, r=2.0 * p.h * (1.0 - 1e-12), return_length=True, workers=-1)
+    return int(np.sum(n))
+
 
 def update_kernel_bytes(prob) -> float:
-    """Algorithmic HBM bytes of one launch of the update kernel.
-
-    Per particle it must read its position (dim x 4 B) and velocity (dim x 4 B)
-    and write both back (16 dim B in total) and write its cell key (4 B);
-    a gas particle also reads its density across the global density -> force
-    dependency (4 B); a per-particle mass is read once (4 B).
-    """
+    """Algorithmic HBM bytes of one launch of the update kernel (cell sums, implicit solve,
+    particle update): per particle it must read its position (dim x 4 B) and velocity
+    (dim x 4 B) and write both back (16 dim B in total) and write its cell key (4 B); a gas
+    particle also reads its density across the global density -> force dependency (4 B); a
+    per-particle mass is read once (4 B)."""
     d = prob.params.dim
     g, s = prob.gas, prob.dust
     gas_b = 16 * d + 4 + 4 + (4 if g.uniform_mass() is None else 0) + (8 if g.e is not None else 0)
@@ -47,24 +87,44 @@ def update_kernel_bytes(prob) -> float:
     return float(g.n * gas_b + s.n * dust_b)
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per launch of k_update from the committed FETCH_SIZE / WRITE_SIZE summary,
-    or None when the kernel sources changed since the counters were taken."""
+def step_bytes(prob) -> float:
+    """Algorithmic HBM bytes of one whole step: every particle reads and writes its state
+    (16 dim B), writes and reads its cell key (8 B) and, when per-particle, its mass (8 B);
+    gas writes and reads its density across the density -> force dependency (8 B) and its
+    energy when adiabatic (8 B); per cell both phases write and read count and offset (32 B)."""
+    p = prob.params
+    d = p.dim
+    g, s = prob.gas, prob.dust
+    gas_b = 16 * d + 8 + 8 + (8 if g.uniform_mass() is None else 0) + (8 if g.e is not None else 0)
+    dust_b = 16 * d + 8 + (8 if s.uniform_mass() is None else 0)
+    return float(g.n * gas_b + s.n * dust_b + 32 * int(np.prod(p.n_cells[:d])))
+
+
+COUNTER_SOURCES = ("common.hpp", "sph.hpp", "binning.hpp", "enqueue.hpp", "host.hpp")
+
+
+def kernel_source_sha() -> str:
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_update_{workload}_hbm_counters.md")
-    if not os.path.exists(path):
-        return None
     h = hashlib.sha1()
-    for f in ("common.hpp", "sph.hpp", "binning.hpp", "enqueue.hpp"):
+    for f in COUNTER_SOURCES:
         with open(os.path.join(ROOT, "paper_1908_01682_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of a kernel from the committed FETCH_SIZE / WRITE_SIZE summary,
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
     rec = {}
     with open(path) as fh:
         for line in fh:
             if ":" in line and line.split(":")[0] in ("kernel_source_sha1", "traffic_bytes_per_launch"):
                 k, v = line.split(":", 1)
                 rec[k.strip()] = v.strip()
-    if rec.get("kernel_source_sha1") != h.hexdigest()[:16]:
+    if rec.get("kernel_source_sha1") != kernel_source_sha() or "traffic_bytes_per_launch" not in rec:
         return None
     return float(rec["traffic_bytes_per_launch"])
 
@@ -155,7 +215,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="box3d", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batched measurements")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -195,9 +255,17 @@ def main(argv=None):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     T.tfsph_profile(sim.ctx, False)
-    upd_ms, upd_n = T.tfsph_profile_read(sim.ctx, T.TFSPH_KERNEL_UPDATE)
-    den_ms, den_n = T.tfsph_profile_read(sim.ctx, T.TFSPH_KERNEL_DENSITY)
-    bin_ms, bin_n = T.tfsph_profile_read(sim.ctx, T.TFSPH_KERNEL_BIN)
+    kernel_ms = {}
+    for name, kind in (("k_density", T.TFSPH_KERNEL_DENSITY), ("k_gas_predict", T.TFSPH_KERNEL_FORCE),
+                       ("k_update", T.TFSPH_KERNEL_UPDATE), ("binning", T.TFSPH_KERNEL_BIN)):
+        ms, n = T.tfsph_profile_read(sim.ctx, kind)
+        kernel_ms[name] = ms / n if n else 0.0
+    # the same steps without the timing events (throughput as an application sees it)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(a.steps)
+    torch.cuda.synchronize()
+    wall_plain = time.perf_counter() - t0
     flags, _ = sim.flags()
     sim.close()
     if flags & T.TFSPH_FLAG_NONFINITE:
@@ -206,9 +274,28 @@ def main(argv=None):
 
     ms_per_step = 1e3 * wall / a.steps
     value = n_part * a.steps / wall
-    upd_avg_s = upd_ms / max(upd_n, 1) * 1e-3
-    alg = update_kernel_bytes(prob)
-    achieved = alg / upd_avg_s / 1e9
+    print("[bench] counting window candidates and support pairs", file=sys.stderr, flush=True)
+    cand = window_candidates(prob)
+    pairs = support_pairs(prob)
+    peak_tf = FP32_PEAK_TFLOPS
+    work = {
+        "k_density": ("alu", FLOPS_PER_CANDIDATE * cand + FLOPS_PER_DENSITY_PAIR * pairs, peak_tf, "TFLOP/s"),
+        "k_gas_predict": ("alu", FLOPS_PER_FORCE_PAIR * (pairs - prob.gas.n), peak_tf, "TFLOP/s"),
+        "k_update": ("hbm", update_kernel_bytes(prob), HBM_PEAK_GBS, "GB/s"),
+    }
+    per_kernel = {}
+    for k, (bound, amount, peak, unit) in work.items():
+        t = kernel_ms[k] * 1e-3
+        ach = amount / t / (1e12 if unit == "TFLOP/s" else 1e9) if t > 0 else 0.0
+        per_kernel[k] = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+                         "avg_launch_ms": kernel_ms[k],
+                         ("algorithmic_flops_per_launch" if bound == "alu" else "algorithmic_bytes_per_launch"): amount}
+    dom = max(work, key=lambda k: kernel_ms[k])
+    roof = dict(per_kernel[dom])
+    roof = {"bound": roof.pop("bound"), "achieved": roof.pop("achieved"), "peak": roof.pop("peak"),
+            "unit": roof.pop("unit"), "frac": roof.pop("frac"), "traffic": measured_traffic(dom, a.workload),
+            "kernel": dom, **roof}
+    sbytes = step_bytes(prob)
     result = {
         "metric": METRIC,
         "value": value,
@@ -224,11 +311,15 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": WORKLOADS[a.workload], "particles": n_part,
                    "cells": int(np.prod(prob.params.n_cells[:prob.params.dim])), "dim": prob.params.dim},
-        "roofline": {"bound": "hbm", "kernel": "k_update", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(a.workload),
-                     "algorithmic_bytes_per_launch": alg, "avg_launch_ms": upd_avg_s * 1e3},
-        "kernel_ms_per_step": {"update": upd_ms / max(upd_n, 1), "density": den_ms / max(den_n, 1),
-                               "bin": bin_ms / max(bin_n, 1)},
+        "roofline": roof,
+        "hbm_roofline_step": {"algorithmic_bytes_per_step": sbytes,
+                              "achieved_GBs": sbytes / (ms_per_step * 1e-3) / 1e9,
+                              "frac": sbytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "kernels": per_kernel,
+        "kernel_ms_per_step": kernel_ms,
+        "window_candidates": cand,
+        "support_pairs": pairs,
+        "uninstrumented": {"ms_per_step": 1e3 * wall_plain / a.steps, "value": n_part * a.steps / wall_plain},
         "adjoint_forward_ratio": None,
     }
     if not a.no_extras:

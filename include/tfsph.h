@@ -270,7 +270,7 @@ enum { TFSPH_VARIANT_AUTO = 0, TFSPH_VARIANT_GLOBAL = 1, TFSPH_VARIANT_LDS_BRICK
 tfsph_status tfsph_set_kernel_variant(tfsph_ctx *ctx, int32_t variant);
 
 /* Cells owned by one 256-thread block of the update kernel (cell sums,
- * implicit solve, particle update), in [1, 512]; the default depends on the
+ * implicit solve, particle update), in [1, 256]; the default depends on the
  * dimension.  Results do not depend on it (each cell is summed serially by
  * one thread).  Drops the context's cached step graph.  Returns
  * TFSPH_E_INVALID_ARG outside that range or for a null context. */

@@ -14,7 +14,8 @@ inline int ntiles_of(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
 
 inline int default_cells_per_block(int dim) { return dim == 1 ? 128 : (dim == 2 ? 64 : 32); }
 // upper bound of tfsph_set_cells_per_block: the block's cell solves sit in LDS
-constexpr int kMaxCellsPerBlock = 512;
+// next to the staged particle records (under 64 KiB in FP64)
+constexpr int kMaxCellsPerBlock = 256;
 
 // zero + count + scan + scatter + rank/gather of both phases into the workspace
 template <typename R>
@@ -139,7 +140,7 @@ inline tfsph_status enqueue_update(const Geom<R> &G, const Phys<R> &Ph, const So
         }
     }
     const int nblocks = (G.ncell + cpb - 1) / cpb;
-    const size_t lds = sizeof(CellSolve<R>) * cpb;
+    const size_t lds = update_lds_bytes<R>(cpb);
     hipLaunchKernelGGL((k_update<R, DIM>), dim3(nblocks), dim3(kBlock), lds, st, G, Ph, Sg, Sd, Pg, Pd, F, cpb, nblocks);
     LAUNCH_CHECK("update");
     return TFSPH_OK;

@@ -465,8 +465,7 @@ struct CellSolve {
     R V[3], U[3];
 };
 
-// Mass and mean predictor velocity of each phase in cell c, summed serially
-// in canonical (cell, id) order (eqs. 17, 21 with mass weights).
+// Particle count, mass and mean predictor velocity of each phase in one cell.
 template <typename R>
 struct CellSums {
     int ng, nd;
@@ -474,25 +473,20 @@ struct CellSums {
     R Vt[3], Ut[3];
 };
 
-template <typename R, int DIM>
-__device__ __forceinline__ void cell_sums(const Phys<R> &Ph, const Sorted<R> &Sg, const Sorted<R> &Sd, int c,
-                                          CellSums<R> &S)
+// Sums over gas [g0, g1) and dust [d0, d1) of one cell; gas(i, m, v) and
+// dust(i, m, u) fetch a particle's mass and velocity (v~ for gas, u before the
+// gravity kick for dust).  Particles are fetched kChunk at a time (indices
+// clamped to the cell) and then added one by one in cell order.
+template <typename R, int DIM, typename GasAt, typename DustAt>
+__device__ __forceinline__ void cell_sums_with(const Phys<R> &Ph, int g0, int g1, int d0, int d1, GasAt &&gas,
+                                               DustAt &&dust, CellSums<R> &S)
 {
-    const int g0 = Sg.start[c], g1 = Sg.start[c + 1];
-    const int d0 = Sd.start[c], d1 = Sd.start[c + 1];
     R Mg = R(0), Md = R(0);
     R Pg[3] = {R(0), R(0), R(0)}, Pd[3] = {R(0), R(0), R(0)};
-    // particles are loaded kChunk at a time (indices clamped to the cell) and
-    // then added one by one in cell order
     for (int a = g0; a < g1; a += kChunk) {
         R m[kChunk], v[kChunk][3];
 #pragma unroll
-        for (int k = 0; k < kChunk; ++k) {
-            const int i = min(a + k, g1 - 1);
-            m[k] = Sg.pos[i].w;
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) v[k][d] = Sg.vt[d][i];
-        }
+        for (int k = 0; k < kChunk; ++k) gas(min(a + k, g1 - 1), m[k], v[k]);
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             if (a + k < g1) {
@@ -505,12 +499,7 @@ __device__ __forceinline__ void cell_sums(const Phys<R> &Ph, const Sorted<R> &Sg
     for (int j = d0; j < d1; j += kChunk) {
         R m[kChunk], u[kChunk][3];
 #pragma unroll
-        for (int k = 0; k < kChunk; ++k) {
-            const int i = min(j + k, d1 - 1);
-            m[k] = Sd.pos[i].w;
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) u[k][d] = Sd.vel[d][i];
-        }
+        for (int k = 0; k < kChunk; ++k) dust(min(j + k, d1 - 1), m[k], u[k]);
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             if (j + k < d1) {
@@ -529,6 +518,27 @@ __device__ __forceinline__ void cell_sums(const Phys<R> &Ph, const Sorted<R> &Sg
         S.Vt[d] = S.ng > 0 ? Pg[d] / Mg : R(0);
         S.Ut[d] = S.nd > 0 ? Pd[d] / Md : R(0);
     }
+}
+
+// Mass and mean predictor velocity of each phase in cell c, summed serially
+// in canonical (cell, id) order (eqs. 17, 21 with mass weights).
+template <typename R, int DIM>
+__device__ __forceinline__ void cell_sums(const Phys<R> &Ph, const Sorted<R> &Sg, const Sorted<R> &Sd, int c,
+                                          CellSums<R> &S)
+{
+    cell_sums_with<R, DIM>(
+        Ph, Sg.start[c], Sg.start[c + 1], Sd.start[c], Sd.start[c + 1],
+        [&](int i, R &m, R *v) {
+            m = Sg.pos[i].w;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) v[d] = Sg.vt[d][i];
+        },
+        [&](int i, R &m, R *u) {
+            m = Sd.pos[i].w;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) u[d] = Sd.vel[d][i];
+        },
+        S);
 }
 
 // closed-form implicit solve from the cell sums; true for a one-phase cell
@@ -646,15 +656,29 @@ __global__ void __launch_bounds__(kBlock) k_gas_predict(Geom<R> G, Phys<R> Ph, S
     gas_predict<R, DIM, KIND>(G, Ph, Sg, Pg, a);
 }
 
+// Records of a block's particles staged in LDS for the cell sums: up to
+// kStage per phase (mass and velocity), else the sums read global memory.
+constexpr int kStage = 2 * kBlock;
+
+template <typename R>
+constexpr size_t update_lds_bytes(int cells_per_block)
+{
+    return sizeof(CellSolve<R>) * cells_per_block + 2 * sizeof(R4<R>) * kStage;
+}
+
 // Cell sums, implicit solve and particle updates of a contiguous run of cells
 // per block; the predictor v~ (and e) of the gas comes from k_gas_predict.
+// The block first copies mass and velocity of its particles into LDS with
+// coalesced loads, so the serial per-cell sums read LDS.
 template <typename R, int DIM>
 __global__ void __launch_bounds__(kBlock)
 k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R> Pd, Flags F, int cells_per_block,
          int nblocks)
 {
     extern __shared__ unsigned char smem_raw[];
-    CellSolve<R> *cs = reinterpret_cast<CellSolve<R> *>(smem_raw);
+    R4<R> *stg = reinterpret_cast<R4<R> *>(smem_raw);          // [kStage] gas: m, v~
+    R4<R> *std_ = stg + kStage;                                  // [kStage] dust: m, u
+    CellSolve<R> *cs = reinterpret_cast<CellSolve<R> *>(std_ + kStage);
     __shared__ int s_bad, s_one;
     const int blk = xcd_block(nblocks);
     const int c0 = blk * cells_per_block;
@@ -662,12 +686,47 @@ k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R
     if (threadIdx.x == 0) { s_bad = 0; s_one = 0; }
 
     const int ga = Sg.start[c0], gb = Sg.start[c1];
+    const int da = Sd.start[c0], db = Sd.start[c1];
+    const bool staged = gb - ga <= kStage && db - da <= kStage;
+    if (staged) {
+        for (int i = threadIdx.x; i < gb - ga; i += kBlock) {
+            const int a = ga + i;
+            stg[i] = mk4<R>(Sg.pos[a].w, Sg.vt[0][a], DIM > 1 ? Sg.vt[1][a] : R(0), DIM > 2 ? Sg.vt[2][a] : R(0));
+        }
+        for (int i = threadIdx.x; i < db - da; i += kBlock) {
+            const int j = da + i;
+            std_[i] = mk4<R>(Sd.pos[j].w, Sd.vel[0][j], DIM > 1 ? Sd.vel[1][j] : R(0), DIM > 2 ? Sd.vel[2][j] : R(0));
+        }
+    }
     __syncthreads();
 
     // (1) per-cell sums in canonical order and the implicit solve
     int one = 0;
-    for (int c = c0 + threadIdx.x; c < c1; c += kBlock)
-        one += solve_cell<R, DIM>(Ph, Sg, Sd, c, cs[c - c0]) ? 1 : 0;
+    for (int c = c0 + threadIdx.x; c < c1; c += kBlock) {
+        CellSums<R> S;
+        if (staged) {
+            cell_sums_with<R, DIM>(
+                Ph, Sg.start[c] - ga, Sg.start[c + 1] - ga, Sd.start[c] - da, Sd.start[c + 1] - da,
+                [&](int i, R &m, R *v) {
+                    const R4<R> q = stg[i];
+                    m = q.x;
+                    v[0] = q.y;
+                    v[1] = q.z;
+                    v[2] = q.w;
+                },
+                [&](int i, R &m, R *u) {
+                    const R4<R> q = std_[i];
+                    m = q.x;
+                    u[0] = q.y;
+                    u[1] = q.z;
+                    u[2] = q.w;
+                },
+                S);
+        } else {
+            cell_sums<R, DIM>(Ph, Sg, Sd, c, S);
+        }
+        one += solve_from_sums<R, DIM>(Ph, S, cs[c - c0]) ? 1 : 0;
+    }
     if (one) atomicAdd(&s_one, one);
     __syncthreads();
 
@@ -675,7 +734,6 @@ k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R
     int bad = 0;
     for (int a = ga + threadIdx.x; a < gb; a += kBlock)
         bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0]);
-    const int da = Sd.start[c0], db = Sd.start[c1];
     for (int j = da + threadIdx.x; j < db; j += kBlock)
         bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[Sd.cell[j] - c0]);
     if (bad) atomicOr(&s_bad, 1);
