@@ -54,6 +54,7 @@ typedef struct {
     double dt;
     double av_alpha;
     double av_beta;
+    double K;           /* > 0: drag coefficient K of eq. (7) held constant, t*_stop = rho*_d / K per volume */
 } orc_params;
 
 typedef struct {
@@ -379,6 +380,8 @@ int64_t orc_step(const orc_params *p, orc_phase *G, orc_phase *Dd, int32_t nstep
     const int64_t nc = orc_ncells(p);
     const int64_t ng = G->n, nd = Dd->n;
     const double tau = p->dt;
+    double vol = 1.0;   /* volume of one drag cell (length in 1D, area in 2D) */
+    for (int d = 0; d < dim; ++d) vol *= (p->hi[d] - p->lo[d]) / p->nc[d];
     int64_t *sg = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
     int64_t *sd = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
     double *acc = (double *)malloc(sizeof(double) * (dim * ng + 1));
@@ -424,11 +427,18 @@ int64_t orc_step(const orc_params *p, orc_phase *G, orc_phase *Dd, int32_t nstep
                 for (int d = 0; d < dim; ++d) C->Pd[d] += Dd->mass[j] * Dd->vel[d * nd + j];
             }
             if (C->N > 0 && C->L > 0) {
-                /* eq. (17)-(18): eps = M_d / M_g; K over the cell gas density is eps / t_stop,
-                 * K over the cell dust density is 1 / t_stop */
-                double eps = C->Md / C->Mg;
-                C->beta = tau / p->tstop;
-                C->alpha = eps * C->beta;
+                if (p->K > 0.0) {
+                    /* K* = K with the volume averages rho*_g = M_g / V, rho*_d = M_d / V:
+                     * tau K* / rho*_g and tau K* / rho*_d */
+                    C->alpha = tau * p->K * vol / C->Mg;
+                    C->beta = tau * p->K * vol / C->Md;
+                } else {
+                    /* eq. (17)-(18): eps = M_d / M_g; K over the cell gas density is eps / t_stop,
+                     * K over the cell dust density is 1 / t_stop */
+                    double eps = C->Md / C->Mg;
+                    C->beta = tau / p->tstop;
+                    C->alpha = eps * C->beta;
+                }
                 double Dt = 1.0 + C->alpha + C->beta;
                 for (int d = 0; d < dim; ++d) {
                     double Vt = C->Pg[d] / C->Mg, Ut = C->Pd[d] / C->Md;

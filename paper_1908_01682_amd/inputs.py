@@ -74,6 +74,8 @@ class Params:
     g: tuple = (0.0, 0.0, 0.0)
     av_alpha: float = 0.0
     av_beta: float = 0.0
+    K: float = 0.0            # > 0: drag coefficient K = rho_d / t_stop of eq. (7) held constant
+                              # (t_stop then varies per cell as rho*_d / K; t_stop above is unused)
 
     def cell_width(self):
         return tuple((self.hi[k] - self.lo[k]) / self.n_cells[k] for k in range(3))
@@ -170,7 +172,7 @@ def dusty_shock(n: int = 100_000, t_stop: float = 1e-3, eps: float = 1.0, gamma:
                 rho_l: float = 1.0, p_l: float = 1.0, rho_r: float = 0.125, p_r: float = 0.1,
                 jitter: float = 0.1, h_over_dx: float = 2.0, cfl: float = 0.25, steps: int = 2000,
                 seed: int = 2, av_alpha: float = 1.0, av_beta: float = 2.0,
-                cells: Optional[int] = None) -> Problem:
+                cells: Optional[int] = None, K: float = 0.0) -> Problem:
     """Sod-type shock tube in a coupled gas-dust mixture (the Dustyshock problem).
 
     Mirrored periodic tube [-0.5, 0.5): left state for x < 0, right state for
@@ -178,6 +180,9 @@ def dusty_shock(n: int = 100_000, t_stop: float = 1e-3, eps: float = 1.0, gamma:
     phases use a uniform lattice with spacing dx = 1/n, jittered by
     U(-jitter, jitter) dx, and per-particle masses m = rho(x_lattice) dx
     (dust: eps * rho).  Gas is adiabatic with gamma; velocities start at zero.
+    K > 0 holds the drag coefficient K = rho_d / t_stop fixed instead of t_stop
+    (the paper's shock test: K = 500, so t_stop is 0.002 on the left and
+    0.00025 on the right of the tube).
     """
     rng = np.random.default_rng(seed)
     dx = 1.0 / n
@@ -199,9 +204,10 @@ def dusty_shock(n: int = 100_000, t_stop: float = 1e-3, eps: float = 1.0, gamma:
     dt = cfl * h / c_max
     params = Params(dim=1, n_cells=(cells, 1, 1), lo=(-0.5, 0.0, 0.0), hi=(0.5, 1.0, 1.0), h=h,
                     c_s=c_max, t_stop=t_stop, dt=dt, eos=ADIABATIC, gamma=gamma,
-                    av_alpha=av_alpha, av_beta=av_beta)
+                    av_alpha=av_alpha, av_beta=av_beta, K=K)
     extra = dict(rho_l=rho_l, p_l=p_l, rho_r=rho_r, p_r=p_r, eps=eps, gamma=gamma)
-    return Problem(f"dusty_shock_tstop{t_stop:g}", params, gas, dust, steps, extra)
+    name = f"dusty_shock_K{K:g}" if K > 0 else f"dusty_shock_tstop{t_stop:g}"
+    return Problem(name, params, gas, dust, steps, extra)
 
 
 # ----------------------------------------------------------------------------

@@ -245,6 +245,76 @@ def test_drag_decay_is_exact(orc, eps):
         assert np.max(np.abs((gi.vel[0] + eps * di.vel[0]) / (1 + eps) - bary)) < 1e-15
 
 
+@pytest.mark.parametrize("eps", [1.0, 0.3, 7.0])
+def test_k_mode_drag_decay_is_exact(orc, eps):
+    """Drag coefficient K held constant (eq. 7 with the volume averages of Section 2.3): in a
+    uniform mixture of densities rho_g, rho_d, v - u shrinks by exactly
+    1 / (1 + tau K (1/rho_g + 1/rho_d)) per step and the barycentric velocity is unchanged."""
+    K = 500.0
+    prob = _uniform_mixture(eps, 1e-3, 0.3, -0.1)
+    p = prob.params.replace(K=K, t_stop=float("nan"))       # t_stop is not used in K mode
+    g, d = orc.from_problem(prob)
+    rho_g, rho_d = 1.0, eps
+    D = 1.0 + p.dt * K * (1.0 / rho_g + 1.0 / rho_d)
+    bary = (0.3 + eps * -0.1) / (1 + eps)
+    for s in range(1, 6):
+        orc.step(p, g, d, 1)
+        gi, di = g.by_id(), d.by_id()
+        rel = gi.vel[0] - di.vel[0]
+        assert np.max(np.abs(rel - 0.4 / D ** s)) < 2e-15
+        assert np.max(np.abs((gi.vel[0] + eps * di.vel[0]) / (1 + eps) - bary)) < 1e-15
+
+
+def test_k_mode_equals_tstop_mode_when_dust_density_is_uniform(orc):
+    """With every drag volume holding the same dust density rho_d, K = rho_d / t_stop gives the
+    same step as the constant-t_stop form (eq. 7), up to rounding."""
+    prob = I.dusty_wave(n_side=200, amp=1e-2, eps=0.5, t_stop=1e-3, h_over_dx=2.0, cells_per_axis=100)
+    # an amplitude-free copy keeps every cell's dust mass equal
+    flat = I.dusty_wave(n_side=200, amp=0.0, eps=0.5, t_stop=1e-3, h_over_dx=2.0, cells_per_axis=100)
+    flat.gas.v[:] = prob.gas.v
+    flat.dust.v[:] = -0.5 * prob.dust.v
+    p_t = flat.params
+    p_k = flat.params.replace(K=0.5 / 1e-3)
+    g1, d1 = orc.from_problem(flat)
+    g2, d2 = orc.from_problem(flat)
+    orc.step(p_t, g1, d1, 3)
+    orc.step(p_k, g2, d2, 3)
+    for a, b in ((g1, g2), (d1, d2)):
+        assert np.max(np.abs(a.by_id().vel - b.by_id().vel)) < 1e-13
+        assert np.max(np.abs(a.by_id().off - b.by_id().off)) < 1e-15
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_k_mode_per_cell_relaxation_and_momentum(orc, dim):
+    """Uneven masses, no pressure (c_s ~ 0): in every drag volume of size V with masses M_g, M_d
+    the mass-weighted mean velocities satisfy V* - U* = (V~ - U~) / (1 + tau K V (1/M_g + 1/M_d))
+    (Appendix A.1 with K* / rho*_g = K V / M_g) and M_g V* + M_d U* = M_g V~ + M_d U~."""
+    prob = _random_mixture(dim, 1500, 60 + dim, tstop=1e-3)
+    K = 300.0
+    p = prob.params.replace(K=K, c_s=1e-12, t_stop=float("nan"))
+    ncell = int(np.prod(p.n_cells[:dim]))
+    D = orc.cell_width(p)
+    vol = float(np.prod(D[:dim]))
+    g, d = orc.from_problem(prob)
+    g0, d0 = g.by_id(), d.by_id()
+    Mg, Pg = _cell_sums(g0, ncell, g0.vel)
+    Md, Pd = _cell_sums(d0, ncell, d0.vel)
+    orc.step(p, g, d, 1)
+    g1, d1 = g.by_id(), d.by_id()
+    _, Pg1 = _cell_sums(g0, ncell, g1.vel)       # cells of step n, velocities of step n+1
+    _, Pd1 = _cell_sums(d0, ncell, d1.vel)
+    both = (Mg > 0) & (Md > 0)
+    assert both.sum() > ncell // 2
+    Dc = 1.0 + p.dt * K * vol * (1.0 / Mg[both] + 1.0 / Md[both])
+    rel0 = Pg[:, both] / Mg[both] - Pd[:, both] / Md[both]
+    rel1 = Pg1[:, both] / Mg[both] - Pd1[:, both] / Md[both]
+    scale = np.max(np.abs(rel0))
+    assert np.max(np.abs(rel1 - rel0 / Dc)) < 1e-12 * scale
+    tot0 = Pg[:, both] + Pd[:, both]
+    tot1 = Pg1[:, both] + Pd1[:, both]
+    assert np.max(np.abs(tot1 - tot0)) < 1e-13 * np.max(np.abs(tot0))
+
+
 def test_drag_decay_continuum_limit(orc):
     """As tau -> 0 the discrete decay approaches exp(-(1 + eps) t / t_stop) with O(tau) error."""
     eps, ts, T = 1.0, 1e-3, 2e-3
