@@ -77,6 +77,11 @@ typedef struct {
     double av_alpha;        /* artificial viscosity alpha, beta (0, 0 = off) */
     double av_beta;
     int32_t precision;      /* TFSPH_F32 or TFSPH_F64 for every real array */
+    double K;               /* 0: t_stop is held constant.  > 0: the drag coefficient K of eq. (7)
+                               is held constant and t_stop is unused: per drag volume of size V
+                               (length in 1D, area in 2D) with masses M_g, M_d the volume averages
+                               are rho*_g = M_g / V, rho*_d = M_d / V, so t*_stop = rho*_d / K
+                               (Section 2.3) */
 } tfsph_params;
 
 /* One particle phase (gas: indices a, b; dust: j, k in the paper's notation).
@@ -111,7 +116,8 @@ const char *tfsph_last_error(void);
  * TFSPH_E_INVALID_ARG when: dim not in 1..3; a cell count < 1 or, on an
  * axis >= dim, != 1; box_hi <= box_lo; h <= 0; an axis with fewer than
  * 2W+1 cells where W = ceil(2h / Delta) is the neighbour window; W > 8;
- * t_stop <= 0 or dt <= 0 or non-finite; isothermal with c_s <= 0; adiabatic
+ * K < 0 or non-finite; K == 0 with t_stop <= 0 or non-finite; dt <= 0 or
+ * non-finite; isothermal with c_s <= 0; adiabatic
  * with gamma <= 1; negative viscosity coefficients; unknown eos/precision;
  * more than 2^31-1 cells. */
 tfsph_status tfsph_validate(const tfsph_params *p);
@@ -141,7 +147,8 @@ tfsph_status tfsph_init(tfsph_ctx **out, const tfsph_params *p, tfsph_state *s, 
  *       adiabatic EOS; u~_j = u_j + tau g (eq. 20);
  *   (d) per cell: M_g, M_d and the momenta of v~, u~ (eqs. 17, 21), the
  *       implicit solve of eqs. (19)-(21) for the new cell means
- *       (eps = M_d/M_g, alpha = eps tau/t_stop, beta = tau/t_stop),
+ *       (eps = M_d/M_g, alpha = eps tau/t_stop, beta = tau/t_stop; with
+ *       K > 0: alpha = tau K V/M_g, beta = tau K V/M_d for the volume V),
  *       then v_a = (v~_a + alpha U*)/(1+alpha), u_j = (u~_j + beta V*)/(1+beta);
  *       cells with one phase only get no drag;
  *   (e) x += tau v_new, offsets carried back into [0, Delta).
@@ -227,7 +234,10 @@ tfsph_status tfsph_batch_destroy(tfsph_batch *b);
  *     L = (1/N_d) sum_j (rho_d,j(T) - target[id_j])^2,
  *     rho_d,j = sum_k m_k W(|x_j - x_k|, h)   (dust only, at the final state),
  * with respect to log t_stop and the initial velocities v0 (gas) and u0
- * (dust).  Cells and neighbour sets are held at their forward values (they
+ * (dust).  With the drag coefficient K held constant (p->K > 0) the scalar is
+ * the derivative with respect to log(1/K) (= -dL/dlog K): alpha and beta
+ * scale like 1/t_stop in one form and like K in the other.  Cells and
+ * neighbour sets are held at their forward values (they
  * are piecewise constant in the inputs).  Memory is bounded by checkpointing:
  * the state is saved every ckpt_every steps in a forward sweep; then for each
  * segment, last first, the segment is replayed from its checkpoint with every

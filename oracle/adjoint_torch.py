@@ -15,7 +15,9 @@ Step (Section 2.3, eqs. 17-21; same readings as the C oracle):
   rho_a = sum_b m_b W(r_ab)                    summation density, gas only
   A_a   = -sum_b m_b (P_a + P_b) grad_a W_ab    P = c_s^2 / rho  (isothermal)
   v~ = v + tau (A + g),  u~ = u + tau g
-  per cell: eps = M_d / M_g, beta = tau / t_stop, alpha = eps beta,
+  per cell: eps = M_d / M_g, beta = tau / t_stop, alpha = eps beta
+            (drag coefficient K held constant: alpha = tau K V / M_g, beta = tau K V / M_d
+            for the cell volume V, and the scalar parameter is log(1/K)),
             V* = ((1+beta) V~ + alpha U~) / D,  U* = (beta V~ + (1+alpha) U~) / D,  D = 1 + alpha + beta
   v = (v~ + alpha U*) / (1 + alpha),  u = (u~ + beta V*) / (1 + beta)   (alpha = beta = 0 in one-phase cells)
   x += tau v
@@ -79,7 +81,8 @@ def forward_loss(p, xg0, xd0, mg, md, v0g, v0d, log_tstop, target, steps):
 
     xg0, xd0: absolute FP64 positions (n, dim), numpy; mg, md: masses (numpy);
     v0g, v0d: torch (n, dim) float64 tensors (may require grad); log_tstop: 0-d
-    tensor; target: numpy (n_dust,) in the same order as xd0.
+    tensor, log t_stop, or log(1/K) when p.K > 0 (K held constant); target: numpy
+    (n_dust,) in the same order as xd0.
     Returns (loss, final gas velocity, final dust velocity, final positions).
     """
     dim = p.dim
@@ -93,7 +96,10 @@ def forward_loss(p, xg0, xd0, mg, md, v0g, v0d, log_tstop, target, steps):
     xd = torch.as_tensor(xd0, dtype=torch.float64)
     v, u = v0g, v0d
     ts = torch.exp(log_tstop)
+    kmode = float(getattr(p, "K", 0.0)) > 0.0
+    vol = float(np.prod([(p.hi[k] - p.lo[k]) / p.n_cells[k] for k in range(dim)]))
     beta = tau / ts
+    tkv = tau * vol / ts            # tau K V with K = 1 / exp(log_tstop)
     for _ in range(steps):
         xgn, xdn = xg.detach().numpy(), xd.detach().numpy()
         cg = torch.as_tensor(_cells(p, xgn))
@@ -119,9 +125,13 @@ def forward_loss(p, xg0, xd0, mg, md, v0g, v0d, log_tstop, target, steps):
         both = (Mg > 0) & (Md > 0)
         Mg_s = torch.where(both, Mg, torch.ones_like(Mg))
         Md_s = torch.where(both, Md, torch.ones_like(Md))
-        eps = Md_s / Mg_s
-        al = torch.where(both, eps * beta, torch.zeros_like(eps))
-        be = torch.where(both, beta * torch.ones_like(eps), torch.zeros_like(eps))
+        if kmode:
+            al = torch.where(both, tkv / Mg_s, torch.zeros_like(Mg_s))
+            be = torch.where(both, tkv / Md_s, torch.zeros_like(Md_s))
+        else:
+            eps = Md_s / Mg_s
+            al = torch.where(both, eps * beta, torch.zeros_like(eps))
+            be = torch.where(both, beta * torch.ones_like(eps), torch.zeros_like(eps))
         Dd = 1.0 + al + be
         Vt, Ut = Pg / Mg_s[:, None], Pd / Md_s[:, None]
         Vs = ((1.0 + be)[:, None] * Vt + al[:, None] * Ut) / Dd[:, None]
@@ -143,7 +153,8 @@ def forward_loss(p, xg0, xd0, mg, md, v0g, v0d, log_tstop, target, steps):
 
 
 def gradients(p, xg0, xd0, mg, md, v0g, v0d, t_stop, target, steps):
-    """(loss, dL/dlog t_stop, dL/dv0 (n_g, d), dL/du0 (n_d, d)) by autograd, all FP64 numpy."""
+    """(loss, dL/dlog t_stop, dL/dv0 (n_g, d), dL/du0 (n_d, d)) by autograd, all FP64 numpy.
+    With p.K > 0, ``t_stop`` is 1/K and the scalar derivative is dL/dlog(1/K)."""
     vg = torch.tensor(v0g, dtype=torch.float64, requires_grad=True)
     vd = torch.tensor(v0d, dtype=torch.float64, requires_grad=True)
     s = torch.tensor(math.log(t_stop), dtype=torch.float64, requires_grad=True)

@@ -11,7 +11,8 @@
 //   V~bar = (Vbar (1+beta) + Ubar beta) / D,   U~bar = (Vbar alpha + Ubar (1+alpha)) / D
 //   alphabar += (Vbar.(U~ - V*) + Ubar.(U~ - U*)) / D
 //   betabar  += (Vbar.(V~ - V*) + Ubar.(V~ - U*)) / D
-//   d/d log t_stop += -alpha alphabar - beta betabar      (alpha, beta proportional to 1/t_stop)
+//   d/d log t_stop += -alpha alphabar - beta betabar      (alpha, beta proportional to 1/t_stop;
+//                                                          with K held constant, d/d log(1/K))
 //   v~bar_a = w_a/(1+alpha) + (m_a/M_g) V~bar,   ubar_j = z_j/(1+beta) + (m_j/M_d) U~bar
 // then through the explicit SPH terms (A = tau v~bar):
 //   Pbar_a = -sum_b (m_b Abar_a - m_a Abar_b) . G_ab

@@ -73,7 +73,9 @@ struct Phys {
     R gm1;               // gamma - 1
     R ggm1;              // gamma (gamma - 1): c^2 = ggm1 * e
     R tau;               // time step
-    R beta;              // tau / t_stop
+    R beta;              // tau / t_stop (t_stop held constant)
+    int kmode;           // drag coefficient K held constant instead
+    R tauKV;             // tau K V for a drag volume V (K mode)
     R g[3];
     R av_alpha, av_beta;
     R eta2;              // 0.01 h^2 in the viscosity denominator

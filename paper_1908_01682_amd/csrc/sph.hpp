@@ -453,7 +453,8 @@ __device__ __forceinline__ void gas_force_any(const Geom<R> &G, const Phys<R> &P
 // --------------------------------------------------------------------------
 // Per-cell closed-form implicit solve (eqs. 17-21 with first-order time
 // differences).  With eps = M_d / M_g, alpha = eps tau / t_stop and
-// beta = tau / t_stop the new cell means solve
+// beta = tau / t_stop (or, K held constant, alpha = tau K V / M_g and
+// beta = tau K V / M_d for the cell volume V) the new cell means solve
 //   (1 + alpha) V - alpha U = V~,   -beta V + (1 + beta) U = U~,
 // so with D = 1 + alpha + beta:
 //   V = ((1 + beta) V~ + alpha U~) / D,   U = (beta V~ + (1 + alpha) U~) / D.
@@ -547,9 +548,15 @@ __device__ __forceinline__ bool solve_from_sums(const Phys<R> &Ph, const CellSum
 {
     const bool both = S.ng > 0 && S.nd > 0;
     if (both) {
-        const R eps = S.Md / S.Mg;
-        out.beta = Ph.beta;
-        out.alpha = eps * Ph.beta;
+        if (Ph.kmode) {
+            // K* = K, rho*_g = M_g / V, rho*_d = M_d / V
+            out.alpha = Ph.tauKV / S.Mg;
+            out.beta = Ph.tauKV / S.Md;
+        } else {
+            const R eps = S.Md / S.Mg;
+            out.beta = Ph.beta;
+            out.alpha = eps * Ph.beta;
+        }
         const R D = R(1) + out.alpha + out.beta;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {

@@ -69,7 +69,9 @@ extern "C" tfsph_status tfsph_validate(const tfsph_params *p)
         ncell *= p->n_cells[d];
         if (ncell > 0x7fffffffLL - 1) return fail(TFSPH_E_INVALID_ARG, "too many cells");
     }
-    if (!finite_pos(p->t_stop)) return fail(TFSPH_E_INVALID_ARG, "t_stop must be positive");
+    if (!(std::isfinite(p->K) && p->K >= 0.0)) return fail(TFSPH_E_INVALID_ARG, "K must be >= 0 and finite");
+    if (p->K == 0.0 && !finite_pos(p->t_stop))
+        return fail(TFSPH_E_INVALID_ARG, "t_stop must be positive (or K > 0)");
     if (!finite_pos(p->dt)) return fail(TFSPH_E_INVALID_ARG, "dt must be positive");
     if (p->eos == TFSPH_ISOTHERMAL && !finite_pos(p->c_s)) return fail(TFSPH_E_INVALID_ARG, "c_s must be positive");
     if (p->eos == TFSPH_ADIABATIC && !(std::isfinite(p->gamma) && p->gamma > 1.0))

@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
                 ("box_hi", ctypes.c_double * 3), ("h", ctypes.c_double), ("eos", ctypes.c_int32),
                 ("c_s", ctypes.c_double), ("gamma", ctypes.c_double), ("t_stop", ctypes.c_double),
                 ("g", ctypes.c_double * 3), ("dt", ctypes.c_double), ("av_alpha", ctypes.c_double),
-                ("av_beta", ctypes.c_double), ("precision", ctypes.c_int32)]
+                ("av_beta", ctypes.c_double), ("precision", ctypes.c_int32), ("K", ctypes.c_double)]
 
 
 class PhaseC(ctypes.Structure):
@@ -146,6 +146,7 @@ def make_params(p, precision: int = TFSPH_F32) -> Params:
     c.t_stop, c.dt = float(p.t_stop), float(p.dt)
     c.av_alpha, c.av_beta = float(p.av_alpha), float(p.av_beta)
     c.precision = int(precision)
+    c.K = float(getattr(p, "K", 0.0))
     return c
 
 
@@ -515,7 +516,8 @@ class AdjointRunner:
     """Initial state of a problem on the device plus the adjoint workspace.
 
     ``run(target)`` returns (loss, dL/dlog t_stop, dL/dv0, dL/du0) with the
-    velocity gradients as (n, dim) tensors indexed by particle id.  The initial
+    velocity gradients as (n, dim) tensors indexed by particle id (with the
+    drag coefficient K held constant the scalar is dL/dlog(1/K)).  The initial
     arrays stay in id order, so ``set_velocities`` takes (n, dim) by id.
     """
 
@@ -557,7 +559,12 @@ class AdjointRunner:
         self.out = torch.zeros(2, dtype=torch.float64, device=self.device)
 
     def set_t_stop(self, t_stop: float) -> None:
-        self.params.t_stop = float(t_stop)
+        """Relaxation-time parameter: t_stop, or 1/K when the drag coefficient K is held
+        constant (the scalar gradient of ``run`` is then dL/dlog(1/K))."""
+        if self.params.K > 0:
+            self.params.K = 1.0 / float(t_stop)
+        else:
+            self.params.t_stop = float(t_stop)
 
     def set_velocities(self, v0g=None, v0d=None) -> None:
         for ph, v in ((self.gas, v0g), (self.dust, v0d)):

@@ -135,3 +135,16 @@ def test_workspace_holds_neighbour_masks(lib):
     a = T.tfsph_workspace_size(p, 4096, 4096)
     b = T.tfsph_workspace_size(p, 5096, 4096)
     assert b - a >= 1000 * 8 * 9
+
+
+def test_validate_drag_coefficient_mode(lib):
+    """K > 0 holds the drag coefficient constant and leaves t_stop unused; K must be finite and
+    non-negative, and with K = 0 t_stop must be positive."""
+    p = _good()
+    p.K, p.t_stop = 500.0, 0.0
+    assert _status(p) == 0, T.lib().tfsph_last_error()
+    for bad in (-1.0, float("nan"), float("inf")):
+        p.K = bad
+        assert _status(p) == -1
+    p.K, p.t_stop = 0.0, 0.0
+    assert _status(p) == -1

@@ -25,6 +25,15 @@ def _batch_1d(seed=11, n_inst=6):
     return probs
 
 
+def _batch_1d_kmode(seed=21):
+    """Instances with the drag coefficient K held constant next to constant-t_stop ones."""
+    probs = I.batched_waves(n_inst=4, n_min=600, n_max=2500, seed=seed, amp=1e-2)
+    for i, p in enumerate(probs):
+        if i % 2 == 0:
+            p.params = p.params.replace(K=float(200.0 * (i + 1)))
+    return probs
+
+
 def _batch_2d():
     rng = np.random.default_rng(3)
     out = []
@@ -42,9 +51,9 @@ def _same(a, b):
         assert np.array_equal(A[k], B[k]), k
 
 
-@pytest.mark.parametrize("dim,precision", [(1, 0), (1, 1), (2, 0)])
-def test_batched_equals_plain_bitwise(dim, precision):
-    probs = _batch_1d() if dim == 1 else _batch_2d()
+@pytest.mark.parametrize("dim,precision,kmode", [(1, 0, False), (1, 1, False), (2, 0, False), (1, 0, True)])
+def test_batched_equals_plain_bitwise(dim, precision, kmode):
+    probs = _batch_1d_kmode() if kmode else (_batch_1d() if dim == 1 else _batch_2d())
     banner(f"batched dim={dim} precision={precision} n_inst={len(probs)}")
     bs = T.BatchedSimulation(probs, precision=precision)
     bs.step(7)

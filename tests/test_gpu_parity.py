@@ -57,8 +57,19 @@ def _cases():
         ("box3d_small_f64", lambda: I.dusty_box(n_side=24, cells_per_axis=12, regions_per_axis=4), 1),
         ("wave2d_small", lambda: I.wave_2d(n_side=64), 0),
         ("batched_instance", lambda: I.batched_waves(n_inst=3, n_min=900, n_max=1200, seed=int(rng.integers(1 << 30)))[2], 0),
+        # drag coefficient K held constant (t*_stop = rho*_d / K per drag volume); K = 500 is the
+        # paper's value for its shock test
+        ("shock_K500", lambda: I.dusty_shock(n=4000, K=500.0), 0),
+        ("shock_K500_f64", lambda: I.dusty_shock(n=4000, K=500.0), 1),
+        ("box3d_small_K", lambda: _with_k(I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4), 3000.0), 0),
+        ("wave2d_small_K_f64", lambda: _with_k(I.wave_2d(n_side=40, eps=0.5), 800.0), 1),
     ]
     return out
+
+
+def _with_k(prob, K):
+    prob.params = prob.params.replace(K=K)
+    return prob
 
 
 CASES = _cases()
@@ -73,8 +84,8 @@ def test_one_step_parity(orc, name, make, precision):
     assert not (flags & T.TFSPH_FLAG_NONFINITE)
 
 
-@pytest.mark.parametrize("name,make,precision", [CASES[0], CASES[3], CASES[8], CASES[10]],
-                         ids=["wave1d", "shock", "box3d", "wave2d"])
+@pytest.mark.parametrize("name,make,precision", [CASES[0], CASES[3], CASES[8], CASES[10], CASES[12], CASES[14]],
+                         ids=["wave1d", "shock", "box3d", "wave2d", "shock_K500", "box3d_K"])
 def test_five_step_parity(orc, name, make, precision):
     """Several steps: binning of moved particles, re-sorting and reuse of the workspace."""
     prob = make()

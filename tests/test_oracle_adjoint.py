@@ -3,6 +3,7 @@
 Its forward pass must reproduce the C oracle's step to rounding, and its
 autograd gradients must equal central finite differences of the C oracle's
 loss: d/d log t_stop directly, and d/dv0, d/du0 along random directions.
+With the drag coefficient K held constant the scalar is log(1/K) instead.
 """
 import math
 
@@ -13,7 +14,7 @@ import torch
 from paper_1908_01682_amd import inputs as I
 
 
-def _problem(dim, seed, per_particle_dust_mass=False):
+def _problem(dim, seed, per_particle_dust_mass=False, kmode=False):
     if dim == 1:
         prob = I.dusty_wave(n_side=120, amp=1e-2, t_stop=1e-3, eps=0.7, cells_per_axis=60)
     else:
@@ -23,11 +24,22 @@ def _problem(dim, seed, per_particle_dust_mass=False):
     prob.dust.v = prob.dust.v + 0.02 * rng.standard_normal(prob.dust.v.shape)
     if per_particle_dust_mass:
         prob.dust.m = prob.dust.m * rng.uniform(0.5, 1.5, prob.dust.n)
+    if kmode:
+        prob.params = prob.params.replace(K=800.0)
     return prob
 
 
+def _relax(p):
+    """The relaxation-time parameter: t_stop, or 1/K when K is held constant."""
+    return 1.0 / p.K if p.K > 0 else p.t_stop
+
+
+def _with_relax(p, t):
+    return p.replace(K=1.0 / t) if p.K > 0 else p.replace(t_stop=t)
+
+
 def c_oracle_loss(orc, prob, v0g, v0d, t_stop, target, steps):
-    p = prob.params.replace(t_stop=t_stop)
+    p = _with_relax(prob.params, t_stop)
     g = orc.from_positions(p, prob.gas.x, v0g, prob.gas.m, prob.gas.id)
     d = orc.from_positions(p, prob.dust.x, v0d, prob.dust.m, prob.dust.id)
     orc.step(p, g, d, steps)
@@ -36,24 +48,25 @@ def c_oracle_loss(orc, prob, v0g, v0d, t_stop, target, steps):
 
 
 def _target(orc, prob, steps):
-    _, _, d = c_oracle_loss(orc, prob, prob.gas.v, prob.dust.v, 2.0 * prob.params.t_stop, np.zeros(prob.dust.n), steps)
+    _, _, d = c_oracle_loss(orc, prob, prob.gas.v, prob.dust.v, 2.0 * _relax(prob.params), np.zeros(prob.dust.n),
+                            steps)
     rho = orc.density(prob.params, d)
     t = np.zeros(prob.dust.n)
     t[d.id] = rho
     return t
 
 
-@pytest.mark.parametrize("dim", [1, 2])
-def test_torch_forward_equals_c_oracle(orc, dim):
+@pytest.mark.parametrize("dim,kmode", [(1, False), (2, False), (1, True), (2, True)])
+def test_torch_forward_equals_c_oracle(orc, dim, kmode):
     from oracle import adjoint_torch as AT
-    prob = _problem(dim, 1, per_particle_dust_mass=True)
+    prob = _problem(dim, 1, per_particle_dust_mass=True, kmode=kmode)
     steps = 8
     target = _target(orc, prob, steps)
     p = prob.params
-    loss_c, g, d = c_oracle_loss(orc, prob, prob.gas.v, prob.dust.v, p.t_stop, target, steps)
+    loss_c, g, d = c_oracle_loss(orc, prob, prob.gas.v, prob.dust.v, _relax(p), target, steps)
     vg = torch.tensor(prob.gas.v)
     vd = torch.tensor(prob.dust.v)
-    s = torch.tensor(math.log(p.t_stop), dtype=torch.float64)
+    s = torch.tensor(math.log(_relax(p)), dtype=torch.float64)
     loss_t, v, u, (xg, xd), _ = AT.forward_loss(p, prob.gas.x, prob.dust.x, prob.gas.m, prob.dust.m, vg, vd, s,
                                                target, steps)
     gi, di = g.by_id(), d.by_id()
@@ -66,19 +79,21 @@ def test_torch_forward_equals_c_oracle(orc, dim):
     assert abs(float(loss_t) - loss_c) <= 1e-10 * loss_c
 
 
-@pytest.mark.parametrize("dim,mass", [(1, False), (2, False), (2, True)])
-def test_gradients_match_central_differences(orc, dim, mass):
+@pytest.mark.parametrize("dim,mass,kmode", [(1, False, False), (2, False, False), (2, True, False),
+                                            (1, False, True), (2, True, True)])
+def test_gradients_match_central_differences(orc, dim, mass, kmode):
     from oracle import adjoint_torch as AT
-    prob = _problem(dim, 2 + dim, per_particle_dust_mass=mass)
+    prob = _problem(dim, 2 + dim, per_particle_dust_mass=mass, kmode=kmode)
     steps = 6
     p = prob.params
+    t0 = _relax(p)
     target = _target(orc, prob, steps)
     loss, dls, dvg, dvd = AT.gradients(p, prob.gas.x, prob.dust.x, prob.gas.m, prob.dust.m, prob.gas.v,
-                                       prob.dust.v, p.t_stop, target, steps)
-    # d/d log t_stop
+                                       prob.dust.v, t0, target, steps)
+    # d/d log t_stop (d/d log(1/K) with K held constant)
     e = 1e-5
-    lp, _, _ = c_oracle_loss(orc, prob, prob.gas.v, prob.dust.v, p.t_stop * math.exp(e), target, steps)
-    lm, _, _ = c_oracle_loss(orc, prob, prob.gas.v, prob.dust.v, p.t_stop * math.exp(-e), target, steps)
+    lp, _, _ = c_oracle_loss(orc, prob, prob.gas.v, prob.dust.v, t0 * math.exp(e), target, steps)
+    lm, _, _ = c_oracle_loss(orc, prob, prob.gas.v, prob.dust.v, t0 * math.exp(-e), target, steps)
     fd = (lp - lm) / (2 * e)
     assert abs(dls - fd) <= 1e-6 * abs(fd) + 1e-12 * loss, (dls, fd)
     assert abs(fd) > 1e-3 * loss / 1.0       # the derivative is not trivially zero
@@ -97,7 +112,7 @@ def test_gradients_match_central_differences(orc, dim, mass):
             vd_p += h * dirn
             vd_m -= h * dirn
             ana = float(np.sum(dvd * dirn))
-        lp, _, _ = c_oracle_loss(orc, prob, vg_p, vd_p, p.t_stop, target, steps)
-        lm, _, _ = c_oracle_loss(orc, prob, vg_m, vd_m, p.t_stop, target, steps)
+        lp, _, _ = c_oracle_loss(orc, prob, vg_p, vd_p, t0, target, steps)
+        lm, _, _ = c_oracle_loss(orc, prob, vg_m, vd_m, t0, target, steps)
         fd = (lp - lm) / (2 * h)
         assert abs(ana - fd) <= 1e-5 * abs(fd) + 1e-9 * loss, (which, ana, fd)
