@@ -112,6 +112,26 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
+def measured_valu_share(workload: str):
+    """Share of the chip's non-packed VALU issue slots each kernel used, from the committed
+    SQ-counter summary, or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"pair_kernels_{workload}_valu_counters.md")
+    if not os.path.exists(path):
+        return None
+    out, sha = {}, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("kernel_source_sha1:"):
+                sha = line.split(":", 1)[1].strip()
+            cols = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cols) == 7 and cols[0].startswith("k_"):
+                try:
+                    out[cols[0]] = float(cols[6])
+                except ValueError:
+                    pass
+    return out if sha == kernel_source_sha() and out else None
+
+
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of a kernel from the committed FETCH_SIZE / WRITE_SIZE summary,
     or None when the kernel sources changed since the counters were taken."""
@@ -196,17 +216,26 @@ def batched_throughput(I, T, torch, steps=500, plain_steps=20):
             "plain_path_value": plain, "vs_plain": value / plain, "nonfinite": bool(flags & 1)}
 
 
-def cpu_baseline(prob, steps: int):
+def cpu_baseline(prob, steps: int, steps_1t: int = 1):
+    """The FP64 oracle on the host cores (all threads, then one thread) on a bounded sample."""
     from oracle import oracle as O
     O.build()
+    n = prob.gas.n + prob.dust.n
+    cores = O.num_threads()
     g, d = O.from_problem(prob)
     t0 = time.perf_counter()
     O.step(prob.params, g, d, steps)
     dt = time.perf_counter() - t0
-    n = prob.gas.n + prob.dust.n
-    return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{steps} steps of the full {prob.name} workload ({n} particles), FP64, "
-                      f"{dt:.2f} s wall"}
+    O.set_num_threads(1)
+    g, d = O.from_problem(prob)
+    t0 = time.perf_counter()
+    O.step(prob.params, g, d, steps_1t)
+    dt1 = time.perf_counter() - t0
+    O.set_num_threads(cores)
+    return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} steps of the full {prob.name} workload ({n} particles), FP64, {dt:.2f} s wall "
+                      f"on {cores} threads; {steps_1t} step on 1 thread, {dt1:.2f} s",
+            "value_1_thread": n * steps_1t / dt1}
 
 
 def main(argv=None):
@@ -317,6 +346,7 @@ def main(argv=None):
                               "frac": sbytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "kernels": per_kernel,
         "kernel_ms_per_step": kernel_ms,
+        "valu_issue_share": measured_valu_share(a.workload),
         "window_candidates": cand,
         "support_pairs": pairs,
         "uninstrumented": {"ms_per_step": 1e3 * wall_plain / a.steps, "value": n_part * a.steps / wall_plain},

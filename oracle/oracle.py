@@ -67,6 +67,7 @@ def lib():
         L.orc_kernel_dw.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
         L.orc_kernel_dw.restype = ctypes.c_double
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -212,6 +213,10 @@ def kernel_dw(dim, h, r):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().orc_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------------------

@@ -520,3 +520,14 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the following calls (results do not depend on it: every
+ * per-particle and per-cell sum is serial in canonical order). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -2,7 +2,7 @@
 // into disjoint volumes at each time instant) as a deterministic counting sort.
 //
 //   count    : slot_i = atomicAdd(count[cell_i], 1)       (integer, any order)
-//   scan     : start = exclusive prefix sum of count        (3 launches, integer)
+//   scan     : start = exclusive prefix sum of count        (2 or 3 launches, integer)
 //   scatter  : tmp[start[c] + slot_i] = (i, id_i)          (unordered inside a cell)
 //   rank     : final position = start[c] + #{k in cell c : id_k < id_i}
 //              and every field of particle i is gathered to it
@@ -148,10 +148,17 @@ k_scan_top(int *partial, int ntiles, int *start_g, int *start_d, int ncell)
     if (threadIdx.x == 0) (blockIdx.y == 0 ? start_g : start_d)[ncell] = carry_in;
 }
 
-// per-tile exclusive scan plus tile prefix -> start[]
+// at most this many tiles: k_scan_down sums the preceding tile totals itself
+// and k_scan_top is not launched
+constexpr int kScanInlineTiles = 4 * kBlock;
+
+// per-tile exclusive scan plus tile prefix -> start[].  With `inline_prefix`
+// the prefix is the sum of the raw tile totals of the tiles before this one
+// (and the last tile writes start[ncell]); otherwise k_scan_top has turned
+// partial[] into exclusive prefixes.
 static __global__ void __launch_bounds__(kBlock)
-k_scan_down(const int *count_g, const int *count_d, int ncell, const int *partial, int ntiles,
-            int *start_g, int *start_d)
+k_scan_down(const int *count_g, const int *count_d, int ncell, const int *partial, int ntiles, int *start_g,
+            int *start_d, int inline_prefix)
 {
     const int *count = blockIdx.y == 0 ? count_g : count_d;
     int *start = blockIdx.y == 0 ? start_g : start_d;
@@ -163,6 +170,16 @@ k_scan_down(const int *count_g, const int *count_d, int ncell, const int *partia
         const int i = base + k * kBlock + threadIdx.x;
         tile[k * kBlock + threadIdx.x] = i < ncell ? count[i] : 0;
     }
+    int prefix = 0;
+    if (inline_prefix) {
+        int s = 0;
+        for (int t = threadIdx.x; t < (int)blockIdx.x; t += kBlock) s += partial[blockIdx.y * ntiles + t];
+        int total;
+        block_exclusive_scan(s, lds, total);
+        prefix = total;
+    } else {
+        prefix = partial[blockIdx.y * ntiles + blockIdx.x];
+    }
     __syncthreads();
     int loc[kScanItems];
     int s = 0;
@@ -172,7 +189,7 @@ k_scan_down(const int *count_g, const int *count_d, int ncell, const int *partia
         s += tile[threadIdx.x * kScanItems + k];
     }
     int total;
-    const int ex = block_exclusive_scan(s, lds, total) + partial[blockIdx.y * ntiles + blockIdx.x];
+    const int ex = block_exclusive_scan(s, lds, total) + prefix;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) tile[threadIdx.x * kScanItems + k] = ex + loc[k];
     __syncthreads();
@@ -181,6 +198,7 @@ k_scan_down(const int *count_g, const int *count_d, int ncell, const int *partia
         const int i = base + k * kBlock + threadIdx.x;
         if (i < ncell) start[i] = tile[k * kBlock + threadIdx.x];
     }
+    if (inline_prefix && blockIdx.x == (unsigned)ntiles - 1 && threadIdx.x == 0) start[ncell] = prefix + total;
 }
 
 // --- scatter (index, id) into cell ranges ----------------------------------------

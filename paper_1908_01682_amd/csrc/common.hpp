@@ -46,7 +46,22 @@ __device__ __forceinline__ R spline_df(R q)
     return R(3) * (t1 * t1 - s * s);
 }
 
-constexpr int kChunk = 4;      // candidates loaded together before any is used
+// Tuning knobs, fixed at compile time: candidates loaded together before any
+// is used (window scans), neighbours taken together by the mask walk, and an
+// optional waves-per-SIMD floor for the pair kernels.
+#ifndef TFSPH_CHUNK
+#define TFSPH_CHUNK 4
+#endif
+#ifndef TFSPH_WALK
+#define TFSPH_WALK 4
+#endif
+#ifdef TFSPH_PAIR_WAVES_PER_EU
+#define TFSPH_PAIR_OCCUPANCY __attribute__((amdgpu_waves_per_eu(TFSPH_PAIR_WAVES_PER_EU)))
+#else
+#define TFSPH_PAIR_OCCUPANCY
+#endif
+constexpr int kChunk = TFSPH_CHUNK;
+constexpr int kWalk = TFSPH_WALK;
 constexpr int kPad = kChunk;   // records past the end of a sorted pos / frc array that may be read
 
 // Grid + kernel geometry of one problem (uniform periodic cells, Section 2.3).

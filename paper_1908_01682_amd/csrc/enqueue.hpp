@@ -18,9 +18,10 @@ inline int default_cells_per_block(int dim) { return dim == 1 ? 128 : (dim == 2 
 constexpr int kMaxCellsPerBlock = 256;
 
 // zero + count + scan + scatter + rank/gather of both phases into the workspace
+// Counting sort of both phases into (cell, id) order.
 template <typename R>
 inline tfsph_status enqueue_bin(int ng, int nd, const Geom<R> &G, const Phase<R> &Pg, const Phase<R> &Pd,
-                         Sorted<R> &Sg, Sorted<R> &Sd, int *partial, const Flags &F, hipStream_t st)
+                                Sorted<R> &Sg, Sorted<R> &Sd, int *partial, const Flags &F, hipStream_t st)
 {
     const int ncell = G.ncell;
     const int ntiles = ntiles_of(ncell);
@@ -34,10 +35,13 @@ inline tfsph_status enqueue_bin(int ng, int nd, const Geom<R> &G, const Phase<R>
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3(ntiles, 2), dim3(kBlock), 0, st, Sg.count, Sd.count, ncell, partial, ntiles);
     LAUNCH_CHECK("scan_reduce");
-    hipLaunchKernelGGL(k_scan_top, dim3(1, 2), dim3(kBlock), 0, st, partial, ntiles, Sg.start, Sd.start, ncell);
-    LAUNCH_CHECK("scan_top");
+    const int inline_prefix = ntiles <= kScanInlineTiles ? 1 : 0;
+    if (!inline_prefix) {
+        hipLaunchKernelGGL(k_scan_top, dim3(1, 2), dim3(kBlock), 0, st, partial, ntiles, Sg.start, Sd.start, ncell);
+        LAUNCH_CHECK("scan_top");
+    }
     hipLaunchKernelGGL(k_scan_down, dim3(ntiles, 2), dim3(kBlock), 0, st, Sg.count, Sd.count, ncell, partial, ntiles,
-                       Sg.start, Sd.start);
+                       Sg.start, Sd.start, inline_prefix);
     LAUNCH_CHECK("scan_down");
     if (bg + bd > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(bg + bd), dim3(kBlock), 0, st, Pg.cell, Pg.id, Sg.slot, Sg.start, ng,

@@ -212,7 +212,7 @@ __device__ __forceinline__ void for_window_recording(const Geom<R> &G, int cx, i
 
 // Visit the neighbours of a point recorded in mask[r * stride] (rows of at
 // most kMaskBits candidates) or, for longer rows, every candidate of the row;
-// fn(b, q, rx, ry, rz, valid) as for for_window().  Neighbours are taken kChunk
+// fn(b, q, rx, ry, rz, valid) as for for_window().  Neighbours are taken kWalk
 // at a time; a lane with fewer left repeats its last one with valid = false.
 template <typename R, int DIM, typename Fn>
 __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
@@ -242,11 +242,11 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
             unsigned long long m = mask[size_t(r) * stride];
             int p = 0;
             while (m) {
-                int b[kChunk];
-                R x0[kChunk];
-                bool ok[kChunk];
+                int b[kWalk];
+                R x0[kWalk];
+                bool ok[kWalk];
 #pragma unroll
-                for (int j = 0; j < kChunk; ++j) {
+                for (int j = 0; j < kWalk; ++j) {
                     ok[j] = m != 0;
                     // m | bit 63 keeps the count defined when m is empty
                     const int pj = __builtin_ctzll(m | (1ull << 63));
@@ -263,11 +263,11 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
                     b[j] = p + sh;
                     x0[j] = xx;
                 }
-                R4<R> q[kChunk];
+                R4<R> q[kWalk];
 #pragma unroll
-                for (int j = 0; j < kChunk; ++j) q[j] = data[b[j]];
+                for (int j = 0; j < kWalk; ++j) q[j] = data[b[j]];
 #pragma unroll
-                for (int j = 0; j < kChunk; ++j) {
+                for (int j = 0; j < kWalk; ++j) {
                     const R rx = x0[j] - q[j].x;
                     const R ry = DIM > 1 ? ry0 - q[j].y : R(0);
                     const R rz = DIM > 2 ? rz0 - q[j].z : R(0);
@@ -343,7 +343,8 @@ __device__ __forceinline__ int xcd_block(int nblocks)
 }
 
 template <typename R, int DIM>
-__global__ void __launch_bounds__(kBlock) k_density(Geom<R> G, Phys<R> Ph, Sorted<R> S, int want_frc)
+__global__ void TFSPH_PAIR_OCCUPANCY __launch_bounds__(kBlock) k_density(Geom<R> G, Phys<R> Ph, Sorted<R> S,
+                                                                         int want_frc)
 {
     const int a = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (a >= S.n) return;
@@ -653,10 +654,11 @@ __device__ __forceinline__ bool dust_finish(const Geom<R> &G, const Phys<R> &Ph,
     return ok;
 }
 
-// Explicit gas terms and predictor, one thread per gas particle (the form
-// used when the update kernel is told the predictor already ran).
+// Explicit gas terms and predictor, one thread per gas particle, specialised
+// on the kind of force loop.
 template <typename R, int DIM, int KIND>
-__global__ void __launch_bounds__(kBlock) k_gas_predict(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Phase<R> Pg)
+__global__ void TFSPH_PAIR_OCCUPANCY __launch_bounds__(kBlock) k_gas_predict(Geom<R> G, Phys<R> Ph, Sorted<R> Sg,
+                                                                             Phase<R> Pg)
 {
     const int a = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (a >= Sg.n) return;
