@@ -149,3 +149,50 @@ def test_adjoint_rejects_unsupported():
     params = T.make_params(prob.params, T.TFSPH_F32)
     with pytest.raises(T.TfsphError):
         T.tfsph_adjoint_workspace_size(params, 400, 400, 10, 5)       # adiabatic + viscosity
+
+
+def test_full_size_adjoint_against_oracle_differences(orc):
+    """The full adjoint workload (2D wave, 512^2 + 512^2 particles, 256^2 cells, 200 steps,
+    checkpoint every 20) as the benchmark runs it, against the FP64 C oracle: its loss, and the
+    central difference of its loss in log t_stop.  The difference step (1e-5) must leave every
+    particle's drag cell unchanged at every step (cells are held fixed by the adjoint; a crossing
+    would put a jump into the difference): that is checked.  FP64 device run: loss to 1e-10,
+    gradient to 1e-6.  FP32 device run (the benchmark's): loss to 1e-4, gradient to 2.5e-3
+    (measured 1.6e-3: the scalar sums -alpha abar - beta betabar over 65536 cells with
+    cancellation)."""
+    prob = I.workload("wave2d", steps=200)
+    ex = prob.extra
+    k = np.asarray(ex["kvec"])
+    target = ex["rho_d0"] * (1.0 + ex["amp"] * np.sin(prob.dust.x @ k))
+    steps, ckpt = 200, 20
+    ts = prob.params.t_stop
+    e = 1e-5
+    runs = []
+    for t in (ts, ts * math.exp(e), ts * math.exp(-e)):
+        p = prob.params.replace(t_stop=t)
+        g = orc.from_positions(p, prob.gas.x, prob.gas.v, prob.gas.m, prob.gas.id)
+        d = orc.from_positions(p, prob.dust.x, prob.dust.v, prob.dust.m, prob.dust.id)
+        runs.append((p, g, d))
+    for s in range(steps):
+        for p, g, d in runs:
+            orc.step(p, g, d, 1)
+        # the oracle keeps each step's canonical order: equal cell histories give equal arrays
+        g0, d0 = runs[0][1], runs[0][2]
+        for _, g, d in runs[1:]:
+            same = all(np.array_equal(a, b) for a, b in ((g.cell, g0.cell), (g.id, g0.id), (d.cell, d0.cell),
+                                                         (d.id, d0.id)))
+            assert same, f"a drag cell differs at step {s}"
+    losses = []
+    for p, g, d in runs:
+        rho = orc.density(p, d)
+        losses.append(float(np.mean((rho - target[d.id]) ** 2)))
+    l0, fd = losses[0], (losses[1] - losses[2]) / (2 * e)
+    for prec, tl, tg in ((T.TFSPH_F64, 1e-10, 1e-6), (T.TFSPH_F32, 1e-4, 2.5e-3)):
+        banner(f"adjoint full size: {prob.gas.n}+{prob.dust.n} particles, {steps} steps, ckpt {ckpt}, prec {prec}")
+        runner = T.AdjointRunner(prob, steps, ckpt, precision=prec)
+        loss, dlogt, _, _ = runner.run(target if prec == T.TFSPH_F64 else target.astype(np.float32))
+        torch.cuda.synchronize()
+        banner(f"loss {float(loss):.9e} vs {l0:.9e}; dL/dlog t_stop {float(dlogt):.9e} vs {fd:.9e}")
+        assert abs(float(loss) - l0) <= tl * l0
+        assert abs(float(dlogt) - fd) <= tg * abs(fd)
+        del runner

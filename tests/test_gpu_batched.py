@@ -168,3 +168,31 @@ def test_autotuner_picks_a_shape_and_caches(tmp_path):
     r2 = A.tune(bs, steps=4, blocks=(256, 512, 1024), path=path)
     assert r2["cached"] and r2["block"] == r1["block"]
     bs.close()
+
+
+def test_full_size_batched_equals_plain_on_sampled_instances(tmp_path):
+    """The full batched workload (256 uneven 1D waves, 5.4M particles, 500 steps) in the launch
+    configuration the benchmark times (autotuned workgroup size, hipGraph replay): sampled
+    instances, the largest and the smallest among them, are bitwise what tfsph_step gives alone."""
+    from paper_1908_01682_amd import autotune as A
+    probs = I.batched_waves()
+    steps = probs[0].steps
+    sizes = [p.gas.n + p.dust.n for p in probs]
+    rng = np.random.default_rng(17)
+    sample = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), *rng.integers(0, len(probs), 2).tolist()})
+    banner(f"batched full size: {len(probs)} instances, {sum(sizes)} particles, {steps} steps, sample {sample}")
+    bs = T.BatchedSimulation(probs, precision=T.TFSPH_F32)
+    A.tune(bs, steps=4, path=str(tmp_path / "tune.json"))
+    bs.step_graph(steps)
+    torch.cuda.synchronize()
+    flags, _ = bs.flags()
+    assert not (flags & T.TFSPH_FLAG_NONFINITE)
+    for i in sample:
+        sim = T.Simulation(probs[i], precision=T.TFSPH_F32)
+        sim.step(steps)
+        torch.cuda.synchronize()
+        g, d = bs.instance(i)
+        _same(g, sim.gas.numpy())
+        _same(d, sim.dust.numpy())
+        sim.close()
+    bs.close()
