@@ -121,6 +121,39 @@ def test_long_run_wave1d(orc, precision, amp):
     assert all(v <= bound for v in errs.values()), errs
 
 
+def test_long_run_wave2d_fp32(orc):
+    """1000 steps of the 2D dusty wave (64^2 + 64^2 particles, 32^2 cells, amplitude 1e-2), FP32
+    against the FP64 oracle, relative L2 of each field's deviation from its mean: gas velocity and
+    density within 1e-3, dust velocity within 2e-3 (measured 7.8e-4, 7.6e-5 and 1.6e-3; the dust
+    velocity error comes from FP32 rounding of the pair sums: no particle changes cell, and
+    accumulating the pair sums in FP64 brings it to 1.0e-3)."""
+    prob = I.wave_2d(n_side=64, amp=1e-2)
+    p = prob.params
+    sim = _sim(prob, 0)
+    og, od = oracle_phase(orc, sim.gas.numpy(), 2), oracle_phase(orc, sim.dust.numpy(), 2)
+    orc.step(p, og, od, 1000)
+    sim.step(1000)
+    torch.cuda.synchronize()
+    G, D = by_id(sim.gas.numpy()), by_id(sim.dust.numpy())
+    og, od = og.by_id(), od.by_id()
+    errs = {"v": _rel_l2(G["vel"], og.vel), "u": _rel_l2(D["vel"], od.vel), "rho": _rel_l2(G["rho"], og.rho)}
+    flags, _ = sim.flags()
+    sim.close()
+    banner(f"wave2d 1000 steps fp32 rel L2 {errs}")
+    assert not flags & T.TFSPH_FLAG_NONFINITE
+    assert errs["v"] <= 1e-3 and errs["rho"] <= 1e-3 and errs["u"] <= 2e-3, errs
+
+
+def test_long_run_box3d_fp64(orc):
+    """200 steps of a small 3D dusty box (24^3 + 24^3 particles, 12^3 cells, uneven dust masses,
+    random velocities) in FP64 against the FP64 oracle: normalised max errors within 1e-9
+    (the two differ only in rounding order)."""
+    prob = I.dusty_box(n_side=24, cells_per_axis=12, regions_per_axis=4)
+    err, flags = _step_parity(orc, prob, 1, nsteps=200)
+    assert not flags & T.TFSPH_FLAG_NONFINITE
+    assert all(v <= 1e-9 for v in err.values()), err
+
+
 def _low_level_init(prob, precision, cell, off, vel, ids):
     """tfsph_init on host-supplied (cell, off) arrays (possibly non-canonical)."""
     p = prob.params
