@@ -63,6 +63,9 @@ def _cases():
         ("shock_K500_f64", lambda: I.dusty_shock(n=4000, K=500.0), 1),
         ("box3d_small_K", lambda: _with_k(I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4), 3000.0), 0),
         ("wave2d_small_K_f64", lambda: _with_k(I.wave_2d(n_side=40, eps=0.5), 800.0), 1),
+        # drag cells narrower than 2h: a window of two cells on each side (25 rows in 3D)
+        ("box3d_window2", lambda: I.dusty_box(n_side=24, cells_per_axis=16, regions_per_axis=2), 0),
+        ("wave2d_window2_f64", lambda: I.dusty_wave(n_side=48, dim=2, amp=1e-2, h_over_dx=1.0, cells_per_axis=32), 1),
     ]
     return out
 
@@ -346,6 +349,8 @@ def test_full_size_one_step(orc, name):
     ("wave2d_bricks_f64", lambda: I.wave_2d(n_side=36, amp=1e-2), 1),
     ("shock1d_viscosity", lambda: I.dusty_shock(n=4000), 0),
     ("wave1d_f64", lambda: I.dusty_wave(n_side=400, amp=1e-2), 1),
+    ("box3d_window2", lambda: I.dusty_box(n_side=24, cells_per_axis=16, regions_per_axis=2), 0),
+    ("wave2d_window2", lambda: I.dusty_wave(n_side=48, dim=2, amp=1e-2, h_over_dx=1.0, cells_per_axis=32), 0),
 ], ids=lambda v: v if isinstance(v, str) else "")
 def test_pair_loop_variants_bitwise_equal(name, make, precision):
     """Neighbour masks (default), full window scans and LDS-staged cell bricks visit neighbours in
