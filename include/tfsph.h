@@ -82,6 +82,10 @@ typedef struct {
                                (length in 1D, area in 2D) with masses M_g, M_d the volume averages
                                are rho*_g = M_g / V, rho*_d = M_d / V, so t*_stop = rho*_d / K
                                (Section 2.3) */
+    double t_stop_epstein;  /* 0: unused.  > 0 (with K == 0): t*_stop = t_stop_epstein / rho*_g per
+                               drag volume, the Epstein regime at fixed grain size and sound speed
+                               (t_stop_epstein is the stopping time at unit gas density); t_stop
+                               is unused */
 } tfsph_params;
 
 /* One particle phase (gas: indices a, b; dust: j, k in the paper's notation).
@@ -116,8 +120,8 @@ const char *tfsph_last_error(void);
  * TFSPH_E_INVALID_ARG when: dim not in 1..3; a cell count < 1 or, on an
  * axis >= dim, != 1; box_hi <= box_lo; h <= 0; an axis with fewer than
  * 2W+1 cells where W = ceil(2h / Delta) is the neighbour window; W > 8;
- * K < 0 or non-finite; K == 0 with t_stop <= 0 or non-finite; dt <= 0 or
- * non-finite; isothermal with c_s <= 0; adiabatic
+ * K or t_stop_epstein < 0 or non-finite, or both > 0; both 0 with t_stop <= 0
+ * or non-finite; dt <= 0 or non-finite; isothermal with c_s <= 0; adiabatic
  * with gamma <= 1; negative viscosity coefficients; unknown eos/precision;
  * more than 2^31-1 cells. */
 tfsph_status tfsph_validate(const tfsph_params *p);
@@ -148,7 +152,9 @@ tfsph_status tfsph_init(tfsph_ctx **out, const tfsph_params *p, tfsph_state *s, 
  *   (d) per cell: M_g, M_d and the momenta of v~, u~ (eqs. 17, 21), the
  *       implicit solve of eqs. (19)-(21) for the new cell means
  *       (eps = M_d/M_g, alpha = eps tau/t_stop, beta = tau/t_stop; with
- *       K > 0: alpha = tau K V/M_g, beta = tau K V/M_d for the volume V),
+ *       K > 0: alpha = tau K V/M_g, beta = tau K V/M_d for the volume V;
+ *       with t_stop_epstein = T_E > 0: alpha = tau M_d/(V T_E),
+ *       beta = tau M_g/(V T_E)),
  *       then v_a = (v~_a + alpha U*)/(1+alpha), u_j = (u~_j + beta V*)/(1+beta);
  *       cells with one phase only get no drag;
  *   (e) x += tau v_new, offsets carried back into [0, Delta).
@@ -235,8 +241,9 @@ tfsph_status tfsph_batch_destroy(tfsph_batch *b);
  *     rho_d,j = sum_k m_k W(|x_j - x_k|, h)   (dust only, at the final state),
  * with respect to log t_stop and the initial velocities v0 (gas) and u0
  * (dust).  With the drag coefficient K held constant (p->K > 0) the scalar is
- * the derivative with respect to log(1/K) (= -dL/dlog K): alpha and beta
- * scale like 1/t_stop in one form and like K in the other.  Cells and
+ * the derivative with respect to log(1/K) (= -dL/dlog K), with the Epstein
+ * law (p->t_stop_epstein > 0) with respect to log t_stop_epstein: alpha and
+ * beta scale like 1/t_stop, K and 1/t_stop_epstein in the three forms.  Cells and
  * neighbour sets are held at their forward values (they
  * are piecewise constant in the inputs).  Memory is bounded by checkpointing:
  * the state is saved every ckpt_every steps in a forward sweep; then for each

@@ -17,7 +17,9 @@ Step (Section 2.3, eqs. 17-21; same readings as the C oracle):
   v~ = v + tau (A + g),  u~ = u + tau g
   per cell: eps = M_d / M_g, beta = tau / t_stop, alpha = eps beta
             (drag coefficient K held constant: alpha = tau K V / M_g, beta = tau K V / M_d
-            for the cell volume V, and the scalar parameter is log(1/K)),
+            for the cell volume V, and the scalar parameter is log(1/K); Epstein law
+            t*_stop = T_E / rho*_g: alpha = tau M_d / (V T_E), beta = tau M_g / (V T_E), the
+            scalar parameter being log T_E),
             V* = ((1+beta) V~ + alpha U~) / D,  U* = (beta V~ + (1+alpha) U~) / D,  D = 1 + alpha + beta
   v = (v~ + alpha U*) / (1 + alpha),  u = (u~ + beta V*) / (1 + beta)   (alpha = beta = 0 in one-phase cells)
   x += tau v
@@ -97,6 +99,7 @@ def forward_loss(p, xg0, xd0, mg, md, v0g, v0d, log_tstop, target, steps):
     v, u = v0g, v0d
     ts = torch.exp(log_tstop)
     kmode = float(getattr(p, "K", 0.0)) > 0.0
+    epstein = float(getattr(p, "t_stop_epstein", 0.0)) > 0.0
     vol = float(np.prod([(p.hi[k] - p.lo[k]) / p.n_cells[k] for k in range(dim)]))
     beta = tau / ts
     tkv = tau * vol / ts            # tau K V with K = 1 / exp(log_tstop)
@@ -128,6 +131,9 @@ def forward_loss(p, xg0, xd0, mg, md, v0g, v0d, log_tstop, target, steps):
         if kmode:
             al = torch.where(both, tkv / Mg_s, torch.zeros_like(Mg_s))
             be = torch.where(both, tkv / Md_s, torch.zeros_like(Md_s))
+        elif epstein:      # t*_stop = T_E / rho*_g with T_E = exp(log_tstop)
+            al = torch.where(both, tau * (Md_s / vol) / ts, torch.zeros_like(Md_s))
+            be = torch.where(both, tau * (Mg_s / vol) / ts, torch.zeros_like(Mg_s))
         else:
             eps = Md_s / Mg_s
             al = torch.where(both, eps * beta, torch.zeros_like(eps))

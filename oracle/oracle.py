@@ -41,7 +41,7 @@ class _Params(ctypes.Structure):
                 ("hi", ctypes.c_double * 3), ("h", ctypes.c_double), ("eos", ctypes.c_int32),
                 ("cs", ctypes.c_double), ("gamma", ctypes.c_double), ("tstop", ctypes.c_double),
                 ("g", ctypes.c_double * 3), ("dt", ctypes.c_double), ("av_alpha", ctypes.c_double),
-                ("av_beta", ctypes.c_double), ("K", ctypes.c_double)]
+                ("av_beta", ctypes.c_double), ("K", ctypes.c_double), ("tse", ctypes.c_double)]
 
 
 class _Phase(ctypes.Structure):
@@ -84,6 +84,7 @@ def params_struct(p) -> _Params:
     s.h, s.eos, s.cs, s.gamma = float(p.h), int(p.eos), float(p.c_s), float(p.gamma)
     s.tstop, s.dt, s.av_alpha, s.av_beta = float(p.t_stop), float(p.dt), float(p.av_alpha), float(p.av_beta)
     s.K = float(getattr(p, "K", 0.0))
+    s.tse = float(getattr(p, "t_stop_epstein", 0.0))
     return s
 
 

@@ -55,6 +55,8 @@ typedef struct {
     double av_alpha;
     double av_beta;
     double K;           /* > 0: drag coefficient K of eq. (7) held constant, t*_stop = rho*_d / K per volume */
+    double tse;         /* > 0: Epstein-like law t*_stop = tse / rho*_g per volume (tse: t_stop at unit
+                           gas density) */
 } orc_params;
 
 typedef struct {
@@ -432,6 +434,11 @@ int64_t orc_step(const orc_params *p, orc_phase *G, orc_phase *Dd, int32_t nstep
                      * tau K* / rho*_g and tau K* / rho*_d */
                     C->alpha = tau * p->K * vol / C->Mg;
                     C->beta = tau * p->K * vol / C->Md;
+                } else if (p->tse > 0.0) {
+                    /* t*_stop = tse / rho*_g, K* = rho*_d / t*_stop = rho*_d rho*_g / tse:
+                     * tau K* / rho*_g = tau rho*_d / tse, tau K* / rho*_d = tau rho*_g / tse */
+                    C->alpha = tau * (C->Md / vol) / p->tse;
+                    C->beta = tau * (C->Mg / vol) / p->tse;
                 } else {
                     /* eq. (17)-(18): eps = M_d / M_g; K over the cell gas density is eps / t_stop,
                      * K over the cell dust density is 1 / t_stop */

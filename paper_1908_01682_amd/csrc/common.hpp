@@ -89,8 +89,9 @@ struct Phys {
     R ggm1;              // gamma (gamma - 1): c^2 = ggm1 * e
     R tau;               // time step
     R beta;              // tau / t_stop (t_stop held constant)
-    int kmode;           // drag coefficient K held constant instead
-    R tauKV;             // tau K V for a drag volume V (K mode)
+    int drag_law;        // 0: t_stop held constant; 1: K held constant; 2: t*_stop = T_E / rho*_g
+    R tauKV;             // law 1: tau K V for a drag volume V
+    R tau_VTE;           // law 2: tau / (V T_E)
     R g[3];
     R av_alpha, av_beta;
     R eta2;              // 0.01 h^2 in the viscosity denominator

@@ -141,11 +141,12 @@ Phys<R> make_phys(const tfsph_params *p)
     P.gm1 = R(p->gamma - 1.0);
     P.ggm1 = R(p->gamma * (p->gamma - 1.0));
     P.tau = R(p->dt);
-    P.kmode = p->K > 0.0 ? 1 : 0;
-    P.beta = P.kmode ? R(0) : R(p->dt / p->t_stop);
+    P.drag_law = p->K > 0.0 ? 1 : (p->t_stop_epstein > 0.0 ? 2 : 0);
+    P.beta = P.drag_law == 0 ? R(p->dt / p->t_stop) : R(0);
     double vol = 1.0;
     for (int d = 0; d < p->dim; ++d) vol *= (p->box_hi[d] - p->box_lo[d]) / p->n_cells[d];
     P.tauKV = R(p->dt * p->K * vol);
+    P.tau_VTE = P.drag_law == 2 ? R(p->dt / (vol * p->t_stop_epstein)) : R(0);
     for (int d = 0; d < 3; ++d) P.g[d] = d < p->dim ? R(p->g[d]) : R(0);
     P.av_alpha = R(p->av_alpha);
     P.av_beta = R(p->av_beta);

@@ -455,7 +455,8 @@ __device__ __forceinline__ void gas_force_any(const Geom<R> &G, const Phys<R> &P
 // Per-cell closed-form implicit solve (eqs. 17-21 with first-order time
 // differences).  With eps = M_d / M_g, alpha = eps tau / t_stop and
 // beta = tau / t_stop (or, K held constant, alpha = tau K V / M_g and
-// beta = tau K V / M_d for the cell volume V) the new cell means solve
+// beta = tau K V / M_d for the cell volume V; or, with t*_stop = T_E / rho*_g,
+// alpha = tau M_d / (V T_E) and beta = tau M_g / (V T_E)) the new cell means solve
 //   (1 + alpha) V - alpha U = V~,   -beta V + (1 + beta) U = U~,
 // so with D = 1 + alpha + beta:
 //   V = ((1 + beta) V~ + alpha U~) / D,   U = (beta V~ + (1 + alpha) U~) / D.
@@ -549,10 +550,14 @@ __device__ __forceinline__ bool solve_from_sums(const Phys<R> &Ph, const CellSum
 {
     const bool both = S.ng > 0 && S.nd > 0;
     if (both) {
-        if (Ph.kmode) {
+        if (Ph.drag_law == 1) {
             // K* = K, rho*_g = M_g / V, rho*_d = M_d / V
             out.alpha = Ph.tauKV / S.Mg;
             out.beta = Ph.tauKV / S.Md;
+        } else if (Ph.drag_law == 2) {
+            // t*_stop = T_E / rho*_g: tau K* / rho*_g = tau rho*_d / T_E, tau K* / rho*_d = tau rho*_g / T_E
+            out.alpha = Ph.tau_VTE * S.Md;
+            out.beta = Ph.tau_VTE * S.Mg;
         } else {
             const R eps = S.Md / S.Mg;
             out.beta = Ph.beta;

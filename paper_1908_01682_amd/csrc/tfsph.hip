@@ -70,8 +70,12 @@ extern "C" tfsph_status tfsph_validate(const tfsph_params *p)
         if (ncell > 0x7fffffffLL - 1) return fail(TFSPH_E_INVALID_ARG, "too many cells");
     }
     if (!(std::isfinite(p->K) && p->K >= 0.0)) return fail(TFSPH_E_INVALID_ARG, "K must be >= 0 and finite");
-    if (p->K == 0.0 && !finite_pos(p->t_stop))
-        return fail(TFSPH_E_INVALID_ARG, "t_stop must be positive (or K > 0)");
+    if (!(std::isfinite(p->t_stop_epstein) && p->t_stop_epstein >= 0.0))
+        return fail(TFSPH_E_INVALID_ARG, "t_stop_epstein must be >= 0 and finite");
+    if (p->K > 0.0 && p->t_stop_epstein > 0.0)
+        return fail(TFSPH_E_INVALID_ARG, "K and t_stop_epstein select different drag laws: set at most one");
+    if (p->K == 0.0 && p->t_stop_epstein == 0.0 && !finite_pos(p->t_stop))
+        return fail(TFSPH_E_INVALID_ARG, "t_stop must be positive (or K or t_stop_epstein > 0)");
     if (!finite_pos(p->dt)) return fail(TFSPH_E_INVALID_ARG, "dt must be positive");
     if (p->eos == TFSPH_ISOTHERMAL && !finite_pos(p->c_s)) return fail(TFSPH_E_INVALID_ARG, "c_s must be positive");
     if (p->eos == TFSPH_ADIABATIC && !(std::isfinite(p->gamma) && p->gamma > 1.0))

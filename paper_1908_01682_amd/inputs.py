@@ -76,6 +76,8 @@ class Params:
     av_beta: float = 0.0
     K: float = 0.0            # > 0: drag coefficient K = rho_d / t_stop of eq. (7) held constant
                               # (t_stop then varies per cell as rho*_d / K; t_stop above is unused)
+    t_stop_epstein: float = 0.0   # > 0: t*_stop = t_stop_epstein / rho*_g per cell (Epstein drag with
+                                  # fixed grain size and sound speed); t_stop and K unused
 
     def cell_width(self):
         return tuple((self.hi[k] - self.lo[k]) / self.n_cells[k] for k in range(3))

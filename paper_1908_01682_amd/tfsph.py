@@ -39,7 +39,8 @@ class Params(ctypes.Structure):
                 ("box_hi", ctypes.c_double * 3), ("h", ctypes.c_double), ("eos", ctypes.c_int32),
                 ("c_s", ctypes.c_double), ("gamma", ctypes.c_double), ("t_stop", ctypes.c_double),
                 ("g", ctypes.c_double * 3), ("dt", ctypes.c_double), ("av_alpha", ctypes.c_double),
-                ("av_beta", ctypes.c_double), ("precision", ctypes.c_int32), ("K", ctypes.c_double)]
+                ("av_beta", ctypes.c_double), ("precision", ctypes.c_int32), ("K", ctypes.c_double),
+                ("t_stop_epstein", ctypes.c_double)]
 
 
 class PhaseC(ctypes.Structure):
@@ -147,6 +148,7 @@ def make_params(p, precision: int = TFSPH_F32) -> Params:
     c.av_alpha, c.av_beta = float(p.av_alpha), float(p.av_beta)
     c.precision = int(precision)
     c.K = float(getattr(p, "K", 0.0))
+    c.t_stop_epstein = float(getattr(p, "t_stop_epstein", 0.0))
     return c
 
 
@@ -560,9 +562,11 @@ class AdjointRunner:
 
     def set_t_stop(self, t_stop: float) -> None:
         """Relaxation-time parameter: t_stop, or 1/K when the drag coefficient K is held
-        constant (the scalar gradient of ``run`` is then dL/dlog(1/K))."""
+        constant (the scalar gradient of ``run`` is then dL/dlog(1/K)), or t_stop_epstein."""
         if self.params.K > 0:
             self.params.K = 1.0 / float(t_stop)
+        elif self.params.t_stop_epstein > 0:
+            self.params.t_stop_epstein = float(t_stop)
         else:
             self.params.t_stop = float(t_stop)
 

@@ -148,3 +148,9 @@ def test_validate_drag_coefficient_mode(lib):
         assert _status(p) == -1
     p.K, p.t_stop = 0.0, 0.0
     assert _status(p) == -1
+    p.t_stop_epstein = 2e-3                     # Epstein law: t_stop unused
+    assert _status(p) == 0, T.lib().tfsph_last_error()
+    p.K = 500.0                                 # two drag laws at once
+    assert _status(p) == -1
+    p.K, p.t_stop_epstein = 0.0, -1.0
+    assert _status(p) == -1

@@ -33,14 +33,21 @@ def _prob(dim, n, seed=0, t_stop=1e-3, mass_jitter=False):
 
 
 def _relax(p):
-    """The relaxation-time parameter: t_stop, or 1/K when K is held constant."""
-    return 1.0 / p.K if p.K > 0 else p.t_stop
+    """The relaxation-time parameter: t_stop, 1/K when K is held constant, or t_stop_epstein."""
+    if p.K > 0:
+        return 1.0 / p.K
+    return p.t_stop_epstein if p.t_stop_epstein > 0 else p.t_stop
 
 
 def _target(orc, prob, steps):
     """Dust density by id after a twin run with the relaxation time doubled (FP64 oracle)."""
     p = prob.params
-    p = p.replace(K=0.5 * p.K) if p.K > 0 else p.replace(t_stop=2.0 * p.t_stop)
+    if p.K > 0:
+        p = p.replace(K=0.5 * p.K)
+    elif p.t_stop_epstein > 0:
+        p = p.replace(t_stop_epstein=2.0 * p.t_stop_epstein)
+    else:
+        p = p.replace(t_stop=2.0 * p.t_stop)
     g, d = orc.from_problem(prob)
     orc.step(p, g, d, steps)
     rho = orc.density(p, d)
@@ -77,14 +84,19 @@ def _rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("dim,n,steps,ckpt,mass,K", [(2, 24, 12, 5, False, 0.0), (1, 160, 15, 4, True, 0.0),
-                                                     (2, 20, 7, 7, True, 0.0), (1, 160, 12, 5, True, 800.0),
-                                                     (2, 24, 9, 4, True, 1000.0)])
-def test_adjoint_fp64_matches_reference(orc, dim, n, steps, ckpt, mass, K):
-    """K > 0 holds the drag coefficient constant; the scalar is then dL/dlog(1/K)."""
+@pytest.mark.parametrize("dim,n,steps,ckpt,mass,K,TE", [(2, 24, 12, 5, False, 0.0, 0.0), (1, 160, 15, 4, True, 0.0, 0.0),
+                                                        (2, 20, 7, 7, True, 0.0, 0.0), (1, 160, 12, 5, True, 800.0, 0.0),
+                                                        (2, 24, 9, 4, True, 1000.0, 0.0),
+                                                        (1, 160, 12, 5, True, 0.0, 1.5e-3),
+                                                        (2, 24, 9, 4, True, 0.0, 1e-3)])
+def test_adjoint_fp64_matches_reference(orc, dim, n, steps, ckpt, mass, K, TE):
+    """K > 0 holds the drag coefficient constant (the scalar is then dL/dlog(1/K)); TE > 0 selects
+    the Epstein law (scalar dL/dlog T_E)."""
     prob = _prob(dim, n, seed=dim, mass_jitter=mass)
     if K > 0:
         prob.params = prob.params.replace(K=K)
+    if TE > 0:
+        prob.params = prob.params.replace(t_stop_epstein=TE)
     target = _target(orc, prob, steps)
     banner(f"adjoint fp64 dim={dim} n={n} steps={steps} ckpt={ckpt}")
     runner = T.AdjointRunner(prob, steps, ckpt, precision=T.TFSPH_F64)

@@ -26,11 +26,14 @@ def _batch_1d(seed=11, n_inst=6):
 
 
 def _batch_1d_kmode(seed=21):
-    """Instances with the drag coefficient K held constant next to constant-t_stop ones."""
-    probs = I.batched_waves(n_inst=4, n_min=600, n_max=2500, seed=seed, amp=1e-2)
+    """Instances with the drag coefficient K held constant and with the Epstein law next to
+    constant-t_stop ones."""
+    probs = I.batched_waves(n_inst=6, n_min=600, n_max=2500, seed=seed, amp=1e-2)
     for i, p in enumerate(probs):
-        if i % 2 == 0:
+        if i % 3 == 0:
             p.params = p.params.replace(K=float(200.0 * (i + 1)))
+        elif i % 3 == 1:
+            p.params = p.params.replace(t_stop_epstein=float(1e-3 * (i + 1)))
     return probs
 
 

@@ -66,8 +66,22 @@ def _cases():
         # drag cells narrower than 2h: a window of two cells on each side (25 rows in 3D)
         ("box3d_window2", lambda: I.dusty_box(n_side=24, cells_per_axis=16, regions_per_axis=2), 0),
         ("wave2d_window2_f64", lambda: I.dusty_wave(n_side=48, dim=2, amp=1e-2, h_over_dx=1.0, cells_per_axis=32), 1),
+        # gravity on both phases (eqs. 1-2)
+        ("box3d_gravity", lambda: _with(I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4),
+                                        g=(0.3, -0.5, 0.2)), 0),
+        ("shock_gravity_f64", lambda: _with(I.dusty_shock(n=4000), g=(-0.4, 0.0, 0.0)), 1),
+        # Epstein law t*_stop = T_E / rho*_g per drag volume
+        ("shock_epstein", lambda: _with(I.dusty_shock(n=4000), t_stop_epstein=2e-3), 0),
+        ("box3d_epstein", lambda: _with(I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4),
+                                        t_stop_epstein=3e-4), 0),
+        ("wave2d_epstein_f64", lambda: _with(I.wave_2d(n_side=40, eps=0.5), t_stop_epstein=1e-3), 1),
     ]
     return out
+
+
+def _with(prob, **kw):
+    prob.params = prob.params.replace(**kw)
+    return prob
 
 
 def _with_k(prob, K):

@@ -14,7 +14,7 @@ import torch
 from paper_1908_01682_amd import inputs as I
 
 
-def _problem(dim, seed, per_particle_dust_mass=False, kmode=False):
+def _problem(dim, seed, per_particle_dust_mass=False, kmode=False, epstein=False):
     if dim == 1:
         prob = I.dusty_wave(n_side=120, amp=1e-2, t_stop=1e-3, eps=0.7, cells_per_axis=60)
     else:
@@ -26,16 +26,22 @@ def _problem(dim, seed, per_particle_dust_mass=False, kmode=False):
         prob.dust.m = prob.dust.m * rng.uniform(0.5, 1.5, prob.dust.n)
     if kmode:
         prob.params = prob.params.replace(K=800.0)
+    if epstein:
+        prob.params = prob.params.replace(t_stop_epstein=1.5e-3)
     return prob
 
 
 def _relax(p):
-    """The relaxation-time parameter: t_stop, or 1/K when K is held constant."""
-    return 1.0 / p.K if p.K > 0 else p.t_stop
+    """The relaxation-time parameter: t_stop, 1/K when K is held constant, or t_stop_epstein."""
+    if p.K > 0:
+        return 1.0 / p.K
+    return p.t_stop_epstein if p.t_stop_epstein > 0 else p.t_stop
 
 
 def _with_relax(p, t):
-    return p.replace(K=1.0 / t) if p.K > 0 else p.replace(t_stop=t)
+    if p.K > 0:
+        return p.replace(K=1.0 / t)
+    return p.replace(t_stop_epstein=t) if p.t_stop_epstein > 0 else p.replace(t_stop=t)
 
 
 def c_oracle_loss(orc, prob, v0g, v0d, t_stop, target, steps):
@@ -56,10 +62,10 @@ def _target(orc, prob, steps):
     return t
 
 
-@pytest.mark.parametrize("dim,kmode", [(1, False), (2, False), (1, True), (2, True)])
-def test_torch_forward_equals_c_oracle(orc, dim, kmode):
+@pytest.mark.parametrize("dim,law", [(1, "t"), (2, "t"), (1, "K"), (2, "K"), (1, "E"), (2, "E")])
+def test_torch_forward_equals_c_oracle(orc, dim, law):
     from oracle import adjoint_torch as AT
-    prob = _problem(dim, 1, per_particle_dust_mass=True, kmode=kmode)
+    prob = _problem(dim, 1, per_particle_dust_mass=True, kmode=law == "K", epstein=law == "E")
     steps = 8
     target = _target(orc, prob, steps)
     p = prob.params
@@ -79,11 +85,11 @@ def test_torch_forward_equals_c_oracle(orc, dim, kmode):
     assert abs(float(loss_t) - loss_c) <= 1e-10 * loss_c
 
 
-@pytest.mark.parametrize("dim,mass,kmode", [(1, False, False), (2, False, False), (2, True, False),
-                                            (1, False, True), (2, True, True)])
-def test_gradients_match_central_differences(orc, dim, mass, kmode):
+@pytest.mark.parametrize("dim,mass,law", [(1, False, "t"), (2, False, "t"), (2, True, "t"),
+                                          (1, False, "K"), (2, True, "K"), (1, True, "E"), (2, True, "E")])
+def test_gradients_match_central_differences(orc, dim, mass, law):
     from oracle import adjoint_torch as AT
-    prob = _problem(dim, 2 + dim, per_particle_dust_mass=mass, kmode=kmode)
+    prob = _problem(dim, 2 + dim, per_particle_dust_mass=mass, kmode=law == "K", epstein=law == "E")
     steps = 6
     p = prob.params
     t0 = _relax(p)

@@ -315,6 +315,87 @@ def test_k_mode_per_cell_relaxation_and_momentum(orc, dim):
     assert np.max(np.abs(tot1 - tot0)) < 1e-13 * np.max(np.abs(tot0))
 
 
+@pytest.mark.parametrize("eps", [1.0, 0.3, 7.0])
+def test_epstein_drag_decay_is_exact(orc, eps):
+    """t*_stop = T_E / rho*_g per volume (Epstein drag at fixed grain size and sound speed):
+    K* / rho*_g = rho*_d / T_E and K* / rho*_d = rho*_g / T_E, so in a uniform mixture v - u
+    shrinks by exactly 1 / (1 + tau (rho_g + rho_d) / T_E) per step."""
+    TE = 2e-3
+    prob = _uniform_mixture(eps, 1e-3, 0.3, -0.1)
+    p = prob.params.replace(t_stop_epstein=TE, t_stop=float("nan"))
+    g, d = orc.from_problem(prob)
+    D = 1.0 + p.dt * (1.0 + eps) / TE             # rho_g = 1, rho_d = eps
+    bary = (0.3 + eps * -0.1) / (1 + eps)
+    for s in range(1, 6):
+        orc.step(p, g, d, 1)
+        gi, di = g.by_id(), d.by_id()
+        assert np.max(np.abs((gi.vel[0] - di.vel[0]) - 0.4 / D ** s)) < 2e-15
+        assert np.max(np.abs((gi.vel[0] + eps * di.vel[0]) / (1 + eps) - bary)) < 1e-15
+
+
+def test_epstein_equals_tstop_mode_when_gas_density_is_uniform(orc):
+    """With the same gas density rho_g in every volume, T_E = t_stop rho_g gives the constant-t_stop
+    step, up to rounding."""
+    flat = I.dusty_wave(n_side=200, amp=0.0, eps=0.5, t_stop=1e-3, h_over_dx=2.0, cells_per_axis=100)
+    wave = I.dusty_wave(n_side=200, amp=1e-2, eps=0.5, t_stop=1e-3, h_over_dx=2.0, cells_per_axis=100)
+    flat.gas.v[:] = wave.gas.v
+    flat.dust.v[:] = -0.5 * wave.dust.v
+    p_t = flat.params
+    p_e = flat.params.replace(t_stop_epstein=1e-3 * 1.0)
+    g1, d1 = orc.from_problem(flat)
+    g2, d2 = orc.from_problem(flat)
+    orc.step(p_t, g1, d1, 3)
+    orc.step(p_e, g2, d2, 3)
+    for a, b in ((g1, g2), (d1, d2)):
+        assert np.max(np.abs(a.by_id().vel - b.by_id().vel)) < 1e-13
+        assert np.max(np.abs(a.by_id().off - b.by_id().off)) < 1e-15
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_epstein_per_cell_relaxation_and_momentum(orc, dim):
+    """Uneven masses, no pressure: per drag volume V* - U* = (V~ - U~) / (1 + tau (M_g + M_d) / (V T_E))
+    and M_g V* + M_d U* = M_g V~ + M_d U~."""
+    prob = _random_mixture(dim, 1500, 70 + dim, tstop=1e-3)
+    TE = 3e-3
+    p = prob.params.replace(t_stop_epstein=TE, c_s=1e-12, t_stop=float("nan"))
+    ncell = int(np.prod(p.n_cells[:dim]))
+    vol = float(np.prod(orc.cell_width(p)[:dim]))
+    g, d = orc.from_problem(prob)
+    g0, d0 = g.by_id(), d.by_id()
+    Mg, Pg = _cell_sums(g0, ncell, g0.vel)
+    Md, Pd = _cell_sums(d0, ncell, d0.vel)
+    orc.step(p, g, d, 1)
+    g1, d1 = g.by_id(), d.by_id()
+    _, Pg1 = _cell_sums(g0, ncell, g1.vel)
+    _, Pd1 = _cell_sums(d0, ncell, d1.vel)
+    both = (Mg > 0) & (Md > 0)
+    assert both.sum() > ncell // 2
+    Dc = 1.0 + p.dt * (Mg[both] + Md[both]) / (vol * TE)
+    rel0 = Pg[:, both] / Mg[both] - Pd[:, both] / Md[both]
+    rel1 = Pg1[:, both] / Mg[both] - Pd1[:, both] / Md[both]
+    assert np.max(np.abs(rel1 - rel0 / Dc)) < 1e-12 * np.max(np.abs(rel0))
+    tot0, tot1 = Pg[:, both] + Pd[:, both], Pg1[:, both] + Pd1[:, both]
+    assert np.max(np.abs(tot1 - tot0)) < 1e-13 * np.max(np.abs(tot0))
+
+
+@pytest.mark.parametrize("eps", [1.0, 4.0])
+def test_gravity_in_a_uniform_mixture(orc, eps):
+    """Eqs. (1)-(2) with g: gravity acts on both phases alike, so in a uniform mixture the
+    barycentric velocity gains exactly tau g per step while v - u decays as without gravity."""
+    g0 = 0.7
+    prob = _uniform_mixture(eps, 1e-3, 0.3, -0.1)
+    p = prob.params.replace(g=(g0, 0.0, 0.0))
+    g, d = orc.from_problem(prob)
+    D = 1.0 + p.dt * (1.0 + eps) / p.t_stop
+    bary0 = (0.3 + eps * -0.1) / (1 + eps)
+    for s in range(1, 6):
+        orc.step(p, g, d, 1)
+        gi, di = g.by_id(), d.by_id()
+        assert np.max(np.abs((gi.vel[0] - di.vel[0]) - 0.4 / D ** s)) < 1e-14
+        bary = (gi.vel[0] + eps * di.vel[0]) / (1 + eps)
+        assert np.max(np.abs(bary - (bary0 + s * p.dt * g0))) < 1e-14
+
+
 def test_drag_decay_continuum_limit(orc):
     """As tau -> 0 the discrete decay approaches exp(-(1 + eps) t / t_stop) with O(tau) error."""
     eps, ts, T = 1.0, 1e-3, 2e-3
