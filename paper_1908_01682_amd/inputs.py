@@ -229,7 +229,7 @@ def _random_velocity_field(x, rng, n_modes=64, kmax=4, rms=0.1):
     amps = rng.standard_normal((n_modes, 3))
     phases = rng.uniform(0.0, 2.0 * math.pi, n_modes)
     v = np.zeros_like(x)
-    chunk = 1 << 18
+    chunk = 1 << 13   # small enough that the (chunk, n_modes) temporaries are reused, not re-faulted
     for s in range(0, x.shape[0], chunk):
         arg = x[s:s + chunk] @ kv.T + phases[None, :]
         v[s:s + chunk] = np.cos(arg) @ amps

@@ -23,6 +23,8 @@ TFSPH_OK = 0
 TFSPH_F32, TFSPH_F64 = 0, 1
 TFSPH_FLAG_NONFINITE = 1
 TFSPH_FLAG_EMPTY_PHASE_CELL = 2
+TFSPH_FLAG_BAD_CELL = 4
+TFSPH_FLAG_CELL_OVERFLOW = 8
 
 STATUS = {0: "TFSPH_OK", -1: "TFSPH_E_INVALID_ARG", -2: "TFSPH_E_WORKSPACE", -3: "TFSPH_E_HIP",
           -4: "TFSPH_E_UNSUPPORTED", -5: "TFSPH_E_STATE"}

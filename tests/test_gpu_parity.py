@@ -75,6 +75,9 @@ def _cases():
         ("box3d_epstein", lambda: _with(I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4),
                                         t_stop_epstein=3e-4), 0),
         ("wave2d_epstein_f64", lambda: _with(I.wave_2d(n_side=40, eps=0.5), t_stop_epstein=1e-3), 1),
+        # windows wider than two cells along x (no neighbour masks: the window is scanned)
+        ("wave1d_window4", lambda: I.dusty_wave(n_side=300, amp=1e-2, cells_per_axis=300), 0),
+        ("wave2d_window3_f64", lambda: I.dusty_wave(n_side=60, dim=2, amp=1e-2, h_over_dx=1.5, cells_per_axis=60), 1),
     ]
     return out
 
@@ -365,6 +368,7 @@ def test_full_size_one_step(orc, name):
     ("wave1d_f64", lambda: I.dusty_wave(n_side=400, amp=1e-2), 1),
     ("box3d_window2", lambda: I.dusty_box(n_side=24, cells_per_axis=16, regions_per_axis=2), 0),
     ("wave2d_window2", lambda: I.dusty_wave(n_side=48, dim=2, amp=1e-2, h_over_dx=1.0, cells_per_axis=32), 0),
+    ("wave2d_window3", lambda: I.dusty_wave(n_side=60, dim=2, amp=1e-2, h_over_dx=1.5, cells_per_axis=60), 0),
 ], ids=lambda v: v if isinstance(v, str) else "")
 def test_pair_loop_variants_bitwise_equal(name, make, precision):
     """Neighbour masks (default), full window scans and LDS-staged cell bricks visit neighbours in
@@ -415,3 +419,50 @@ def test_cells_per_block_bitwise_invariant(name, make, precision):
             assert np.array_equal(out[0][0][k], other[0][k]), k
             if out[0][1].get(k) is not None:
                 assert np.array_equal(out[0][1][k], other[1][k]), k
+
+
+def test_cell_over_the_rank_limit(orc):
+    """A drag cell holding more than 4096 particles of a phase: flagged TFSPH_FLAG_CELL_OVERFLOW
+    (the order inside that cell then follows the slot claims), and the step still matches the
+    oracle (sums over the crowded cell in another order: rounding only)."""
+    prob = I.dusty_wave(n_side=6000, amp=0.0, cells_per_axis=200)
+    rng = np.random.default_rng(5)
+    D = 1.0 / 200
+    for ph in (prob.gas, prob.dust):
+        pick = rng.choice(ph.n, 4200, replace=False)
+        ph.x[pick, 0] = 7 * D + rng.uniform(0.05, 0.95, 4200) * D
+        ph.v[:, 0] = 1e-2 * rng.standard_normal(ph.n)
+    p = prob.params
+    sim = _sim(prob, 0)
+    og, od = oracle_phase(orc, sim.gas.numpy(), 1), oracle_phase(orc, sim.dust.numpy(), 1)
+    orc.step(p, og, od, 1)
+    sim.step(1)
+    torch.cuda.synchronize()
+    err = compare_states(p, sim.gas.numpy(), sim.dust.numpy(), og, od, p.c_s)
+    flags, _ = sim.flags()
+    sim.close()
+    assert flags & T.TFSPH_FLAG_CELL_OVERFLOW
+    assert not flags & T.TFSPH_FLAG_NONFINITE
+    assert all(v <= TOL32 for v in err.values()), err
+
+
+def test_both_phases_empty():
+    """No particles at all: init and steps succeed and raise no flag."""
+    prob = I.dusty_wave(n_side=100, amp=1e-2, cells_per_axis=50)
+    empty = I.Phase(np.zeros((0, 1)), np.zeros((0, 1)), np.zeros(0), np.zeros(0, dtype=np.int32))
+    prob.gas, prob.dust = empty, empty.copy()
+    sim = _sim(prob, 0)
+    sim.step(3)
+    torch.cuda.synchronize()
+    flags, one = sim.flags()
+    sim.close()
+    assert flags == 0 and one == 0
+
+
+def test_large_box_one_step(orc):
+    """A 3D box eight times the benchmark's: 256^3 + 256^3 particles (33.5M), 128^3 cells, the
+    default kernels; one step against the oracle."""
+    prob = I.dusty_box(n_side=256, cells_per_axis=128, regions_per_axis=16)
+    err, flags = _step_parity(orc, prob, 0, 1)
+    assert not flags & T.TFSPH_FLAG_NONFINITE
+    assert all(v <= TOL32 for v in err.values()), err

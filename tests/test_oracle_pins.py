@@ -7,6 +7,7 @@ decay of the drag relaxation, its stiff and drag-free limits, the linear
 dusty-wave solution and the stiff-limit shock tube.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -282,6 +283,35 @@ def test_k_mode_equals_tstop_mode_when_dust_density_is_uniform(orc):
     for a, b in ((g1, g2), (d1, d2)):
         assert np.max(np.abs(a.by_id().vel - b.by_id().vel)) < 1e-13
         assert np.max(np.abs(a.by_id().off - b.by_id().off)) < 1e-15
+
+
+def _golden_rows(name):
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    return [tuple(float(t) for t in line.split()) for line in open(path)
+            if line.strip() and not line.startswith("#")]
+
+
+@pytest.mark.parametrize("K,rho_g,rho_d,t_stop", _golden_rows("k500_stopping_times.txt"))
+def test_k500_gives_the_papers_stopping_times(orc, K, rho_g, rho_d, t_stop):
+    """The paper's K = 500 at dust/gas ratio 1 corresponds to t_stop = 0.002 (Dustywave, unit
+    densities) and 0.00025 (Dustyshock, density 0.125): the oracle's K form at those densities
+    takes the same step as its t_stop form with the printed stopping time, and v - u decays by
+    1 / (1 + tau (1 + rho_d / rho_g) / t_stop)."""
+    prob = I.dusty_wave(n_side=64, dim=1, amp=0.0, rho_g0=rho_g, eps=rho_d / rho_g, t_stop=t_stop,
+                        h_over_dx=2.0, cells_per_axis=32)
+    prob.gas.v[:] = 0.3
+    prob.dust.v[:] = -0.1
+    p_t = prob.params
+    p_k = prob.params.replace(K=K, t_stop=float("nan"))
+    g1, d1 = orc.from_problem(prob)
+    g2, d2 = orc.from_problem(prob)
+    orc.step(p_t, g1, d1, 3)
+    orc.step(p_k, g2, d2, 3)
+    for a, b in ((g1, g2), (d1, d2)):
+        assert np.max(np.abs(a.by_id().vel - b.by_id().vel)) < 1e-14
+    D = 1.0 + p_t.dt * (1.0 + rho_d / rho_g) / t_stop
+    rel = g2.by_id().vel[0] - d2.by_id().vel[0]
+    assert np.max(np.abs(rel - 0.4 / D ** 3)) < 1e-14
 
 
 @pytest.mark.parametrize("dim", [1, 2, 3])
