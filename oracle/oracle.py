@@ -58,6 +58,8 @@ def lib():
         P, PH = ctypes.POINTER(_Params), ctypes.POINTER(_Phase)
         L.orc_step.argtypes = [P, PH, PH, ctypes.c_int32, ctypes.c_void_p]
         L.orc_step.restype = ctypes.c_int64
+        L.orc_step_imex.argtypes = [P, PH, PH, ctypes.c_int32]
+        L.orc_step_imex.restype = ctypes.c_int64
         L.orc_phase_density.argtypes = [P, PH, ctypes.c_void_p]
         L.orc_phase_forces.argtypes = [P, PH, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_canonicalize.argtypes = [P, PH]
@@ -181,8 +183,15 @@ def positions(p, ph: OPhase) -> np.ndarray:
 
 
 def step(p, gas: OPhase, dust: OPhase, nsteps: int = 1, cell_diag: Optional[np.ndarray] = None) -> int:
-    """Advance both phases ``nsteps`` IDIC steps in place; returns the one-phase-cell count."""
+    """Advance both phases ``nsteps`` steps in place; returns the one-phase-cell count (summed over
+    the drag solves).  ``p.scheme`` 0: the first-order IDIC step; 1: the second-order IMEX step
+    (ARS(2,2,2) with the drag in cell as its implicit part; ``cell_diag`` is not filled)."""
     sg, sd = gas._struct(), dust._struct()
+    if getattr(p, "scheme", 0) == 1:
+        if cell_diag is not None:
+            raise ValueError("cell_diag is only filled by the first-order step")
+        r = lib().orc_step_imex(ctypes.byref(params_struct(p)), ctypes.byref(sg), ctypes.byref(sd), int(nsteps))
+        return int(r)
     ptr = cell_diag.ctypes.data if cell_diag is not None else None
     r = lib().orc_step(ctypes.byref(params_struct(p)), ctypes.byref(sg), ctypes.byref(sd), int(nsteps), ptr)
     return int(r)

@@ -191,9 +191,10 @@ static void orc_permute_i(int32_t *x, const int64_t *perm, int64_t n, int32_t *t
     memcpy(x, tmp, sizeof(int32_t) * n);
 }
 
-/* Reorder all arrays of a phase into (cell, id) order.  Not thread safe
- * (qsort comparator uses a file-scope pointer); called from serial code. */
-void orc_sort(const orc_params *p, orc_phase *ph)
+/* Reorder all arrays of a phase into (cell, id) order; with perm_out, the
+ * particle now at k was at perm_out[k] before.  Not thread safe (qsort
+ * comparator uses a file-scope pointer); called from serial code. */
+static void orc_sort_perm(const orc_params *p, orc_phase *ph, int64_t *perm_out)
 {
     const int64_t n = ph->n;
     if (n == 0) return;
@@ -213,8 +214,11 @@ void orc_sort(const orc_params *p, orc_phase *ph)
     if (ph->energy) orc_permute_d(ph->energy, perm, n, tmp);
     orc_permute_i(ph->cell, perm, n, tmpi);
     orc_permute_i(ph->id, perm, n, tmpi);
+    if (perm_out) memcpy(perm_out, perm, sizeof(int64_t) * n);
     free(perm); free(tmp); free(tmpi);
 }
+
+void orc_sort(const orc_params *p, orc_phase *ph) { orc_sort_perm(p, ph, NULL); }
 
 /* start[c] = first sorted index of cell c, start[ncells] = n */
 void orc_cell_start(const orc_params *p, const orc_phase *ph, int64_t *start)
@@ -375,6 +379,80 @@ typedef struct {
     int64_t N, L;
 } orc_cell;
 
+/* ------------------------------------------------------------------------ */
+/* Drag in cell (Section 2.3, eqs. 17-21) with first-order time differences  */
+/* over a step tau_eff: the current velocities of both phases are the        */
+/* predictors v~, u~; per volume the mass-weighted means solve the 2x2       */
+/* system, then every particle relaxes toward the other phase's new mean.    */
+/* Both phases sorted with matching starts.  Returns the number of volumes   */
+/* that hold one phase only (no drag there).                                 */
+/* ------------------------------------------------------------------------ */
+static int64_t orc_drag_cells(const orc_params *p, orc_phase *G, orc_phase *Dd, const int64_t *sg,
+                              const int64_t *sd, double tau, double vol, orc_cell *cells)
+{
+    const int dim = p->dim;
+    const int64_t nc = orc_ncells(p);
+    const int64_t ng = G->n, nd = Dd->n;
+    /* eq. (17), (21): per-volume masses and momenta, canonical order */
+    int64_t empty = 0;
+#pragma omp parallel for schedule(static) reduction(+ : empty)
+    for (int64_t c = 0; c < nc; ++c) {
+        orc_cell *C = &cells[c];
+        memset(C, 0, sizeof(*C));
+        C->N = sg[c + 1] - sg[c];
+        C->L = sd[c + 1] - sd[c];
+        for (int64_t a = sg[c]; a < sg[c + 1]; ++a) {
+            C->Mg += G->mass[a];
+            for (int d = 0; d < dim; ++d) C->Pg[d] += G->mass[a] * G->vel[d * ng + a];
+        }
+        for (int64_t j = sd[c]; j < sd[c + 1]; ++j) {
+            C->Md += Dd->mass[j];
+            for (int d = 0; d < dim; ++d) C->Pd[d] += Dd->mass[j] * Dd->vel[d * nd + j];
+        }
+        if (C->N > 0 && C->L > 0) {
+            if (p->K > 0.0) {
+                /* K* = K with the volume averages rho*_g = M_g / V, rho*_d = M_d / V:
+                 * tau K* / rho*_g and tau K* / rho*_d */
+                C->alpha = tau * p->K * vol / C->Mg;
+                C->beta = tau * p->K * vol / C->Md;
+            } else if (p->tse > 0.0) {
+                /* t*_stop = tse / rho*_g, K* = rho*_d / t*_stop = rho*_d rho*_g / tse:
+                 * tau K* / rho*_g = tau rho*_d / tse, tau K* / rho*_d = tau rho*_g / tse */
+                C->alpha = tau * (C->Md / vol) / p->tse;
+                C->beta = tau * (C->Mg / vol) / p->tse;
+            } else {
+                /* eq. (17)-(18): eps = M_d / M_g; K over the cell gas density is eps / t_stop,
+                 * K over the cell dust density is 1 / t_stop */
+                double eps = C->Md / C->Mg;
+                C->beta = tau / p->tstop;
+                C->alpha = eps * C->beta;
+            }
+            double Dt = 1.0 + C->alpha + C->beta;
+            for (int d = 0; d < dim; ++d) {
+                double Vt = C->Pg[d] / C->Mg, Ut = C->Pd[d] / C->Md;
+                /* cell means at n+1 solve (1+alpha)V - alpha U = V~, -beta V + (1+beta) U = U~ */
+                C->V[d] = ((1.0 + C->beta) * Vt + C->alpha * Ut) / Dt;
+                C->U[d] = (C->beta * Vt + (1.0 + C->alpha) * Ut) / Dt;
+            }
+        } else {
+            C->alpha = C->beta = 0.0;
+            if (C->N > 0 || C->L > 0) empty += 1;
+        }
+    }
+
+    /* eq. (19)-(20) with the other phase's velocity uniform over the volume */
+    for (int64_t c = 0; c < nc; ++c) {
+        const orc_cell *C = &cells[c];
+        for (int64_t a = sg[c]; a < sg[c + 1]; ++a)
+            for (int d = 0; d < dim; ++d)
+                G->vel[d * ng + a] = (G->vel[d * ng + a] + C->alpha * C->U[d]) / (1.0 + C->alpha);
+        for (int64_t j = sd[c]; j < sd[c + 1]; ++j)
+            for (int d = 0; d < dim; ++d)
+                Dd->vel[d * nd + j] = (Dd->vel[d * nd + j] + C->beta * C->V[d]) / (1.0 + C->beta);
+    }
+    return empty;
+}
+
 int64_t orc_step(const orc_params *p, orc_phase *G, orc_phase *Dd, int32_t nsteps,
                  double *cell_diag /* optional [ncells][2+2*dim]: alpha, beta, V*, U* of the last step */)
 {
@@ -412,64 +490,7 @@ int64_t orc_step(const orc_params *p, orc_phase *G, orc_phase *Dd, int32_t nstep
         if (G->energy)
             for (int64_t a = 0; a < ng; ++a) G->energy[a] += tau * dedt[a];
 
-        /* eq. (17), (21): per-volume masses and momenta, canonical order */
-        int64_t empty = 0;
-#pragma omp parallel for schedule(static) reduction(+ : empty)
-        for (int64_t c = 0; c < nc; ++c) {
-            orc_cell *C = &cells[c];
-            memset(C, 0, sizeof(*C));
-            C->N = sg[c + 1] - sg[c];
-            C->L = sd[c + 1] - sd[c];
-            for (int64_t a = sg[c]; a < sg[c + 1]; ++a) {
-                C->Mg += G->mass[a];
-                for (int d = 0; d < dim; ++d) C->Pg[d] += G->mass[a] * G->vel[d * ng + a];
-            }
-            for (int64_t j = sd[c]; j < sd[c + 1]; ++j) {
-                C->Md += Dd->mass[j];
-                for (int d = 0; d < dim; ++d) C->Pd[d] += Dd->mass[j] * Dd->vel[d * nd + j];
-            }
-            if (C->N > 0 && C->L > 0) {
-                if (p->K > 0.0) {
-                    /* K* = K with the volume averages rho*_g = M_g / V, rho*_d = M_d / V:
-                     * tau K* / rho*_g and tau K* / rho*_d */
-                    C->alpha = tau * p->K * vol / C->Mg;
-                    C->beta = tau * p->K * vol / C->Md;
-                } else if (p->tse > 0.0) {
-                    /* t*_stop = tse / rho*_g, K* = rho*_d / t*_stop = rho*_d rho*_g / tse:
-                     * tau K* / rho*_g = tau rho*_d / tse, tau K* / rho*_d = tau rho*_g / tse */
-                    C->alpha = tau * (C->Md / vol) / p->tse;
-                    C->beta = tau * (C->Mg / vol) / p->tse;
-                } else {
-                    /* eq. (17)-(18): eps = M_d / M_g; K over the cell gas density is eps / t_stop,
-                     * K over the cell dust density is 1 / t_stop */
-                    double eps = C->Md / C->Mg;
-                    C->beta = tau / p->tstop;
-                    C->alpha = eps * C->beta;
-                }
-                double Dt = 1.0 + C->alpha + C->beta;
-                for (int d = 0; d < dim; ++d) {
-                    double Vt = C->Pg[d] / C->Mg, Ut = C->Pd[d] / C->Md;
-                    /* cell means at n+1 solve (1+alpha)V - alpha U = V~, -beta V + (1+beta) U = U~ */
-                    C->V[d] = ((1.0 + C->beta) * Vt + C->alpha * Ut) / Dt;
-                    C->U[d] = (C->beta * Vt + (1.0 + C->alpha) * Ut) / Dt;
-                }
-            } else {
-                C->alpha = C->beta = 0.0;
-                if (C->N > 0 || C->L > 0) empty += 1;
-            }
-        }
-        empty_total += empty;
-
-        /* eq. (19)-(20) with the other phase's velocity uniform over the volume */
-        for (int64_t c = 0; c < nc; ++c) {
-            const orc_cell *C = &cells[c];
-            for (int64_t a = sg[c]; a < sg[c + 1]; ++a)
-                for (int d = 0; d < dim; ++d)
-                    G->vel[d * ng + a] = (G->vel[d * ng + a] + C->alpha * C->U[d]) / (1.0 + C->alpha);
-            for (int64_t j = sd[c]; j < sd[c + 1]; ++j)
-                for (int d = 0; d < dim; ++d)
-                    Dd->vel[d * nd + j] = (Dd->vel[d * nd + j] + C->beta * C->V[d]) / (1.0 + C->beta);
-        }
+        empty_total += orc_drag_cells(p, G, Dd, sg, sd, tau, vol, cells);
         if (cell_diag && s == nsteps - 1) {
             int w = 2 + 2 * dim;
             for (int64_t c = 0; c < nc; ++c) {
@@ -491,6 +512,178 @@ int64_t orc_step(const orc_params *p, orc_phase *G, orc_phase *Dd, int32_t nstep
         orc_canonicalize(p, Dd);
     }
     free(sg); free(sd); free(acc); free(dedt); free(cells);
+    return empty_total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Second-order IMEX step: the ARS(2,2,2) pair of Ascher, Ruuth & Spiteri   */
+/* (Appl. Numer. Math. 25, 1997), with gamma = 1 - 1/sqrt(2) and             */
+/* delta = 1 - 1/(2 gamma).  Split of the two-fluid system (eqs. 1-2):       */
+/*   explicit part f: dx/dt = v (u), the SPH pressure and viscosity terms    */
+/*                    and g of eq. (19), de/dt of the gas;                   */
+/*   implicit part g: the drag in cell of eqs. (19)-(21), i.e. each gas       */
+/*                    particle relaxes toward the dust mean of its volume at  */
+/*                    rate K* / rho*_g and each dust particle toward the gas */
+/*                    mean at rate K* / rho*_d, volumes and rates frozen at   */
+/*                    the stage's positions.                                  */
+/* Stages (Y1 = y^n):                                                        */
+/*   Y2 = y^n + gamma tau f(Y1) + gamma tau g(Y2)                             */
+/*   Y3 = y^n + tau (delta f(Y1) + (1 - delta) f(Y2))                         */
+/*            + tau (1 - gamma) g(Y2) + gamma tau g(Y3),    y^{n+1} = Y3.     */
+/* Each implicit stage is the paper's first-order drag solve with time step   */
+/* gamma tau on the predictor formed from the explicit terms.  The stage-2    */
+/* drag rate comes from its own equation, g(Y2) = (Y2 - Y2~) / (gamma tau),   */
+/* so tau (1 - gamma) g(Y2) = ((1 - gamma) / gamma) (Y2 - Y2~).  rho on exit  */
+/* is the summation density at level n, as for the first-order step.         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    orc_phase ph;
+    int32_t *cell, *id;
+    double *off, *vel, *mass, *rho, *energy;
+} orc_stage_copy;
+
+static void orc_stage_alloc(orc_stage_copy *q, const orc_phase *src, int dim)
+{
+    const int64_t n = src->n, m = n ? n : 1;
+    q->cell = (int32_t *)malloc(sizeof(int32_t) * m);
+    q->id = (int32_t *)malloc(sizeof(int32_t) * m);
+    q->off = (double *)malloc(sizeof(double) * dim * m);
+    q->vel = (double *)malloc(sizeof(double) * dim * m);
+    q->mass = (double *)malloc(sizeof(double) * m);
+    q->rho = (double *)malloc(sizeof(double) * m);
+    q->energy = src->energy ? (double *)malloc(sizeof(double) * m) : NULL;
+    q->ph.n = n;
+    q->ph.cell = q->cell; q->ph.id = q->id; q->ph.off = q->off; q->ph.vel = q->vel;
+    q->ph.mass = q->mass; q->ph.rho = q->rho; q->ph.energy = q->energy;
+}
+
+static void orc_stage_free(orc_stage_copy *q)
+{
+    free(q->cell); free(q->id); free(q->off); free(q->vel); free(q->mass); free(q->rho); free(q->energy);
+}
+
+int64_t orc_step_imex(const orc_params *p, orc_phase *G, orc_phase *Dd, int32_t nsteps)
+{
+    const int dim = p->dim;
+    const int64_t nc = orc_ncells(p);
+    const int64_t ng = G->n, nd = Dd->n;
+    const double tau = p->dt;
+    const double gam = 1.0 - 1.0 / sqrt(2.0);
+    const double del = 1.0 - 1.0 / (2.0 * gam);
+    const double gtau = gam * tau;
+    const double rg = (1.0 - gam) / gam;
+    double vol = 1.0;
+    for (int d = 0; d < dim; ++d) vol *= (p->hi[d] - p->lo[d]) / p->nc[d];
+    const int64_t mg = ng ? ng : 1, md = nd ? nd : 1;
+    int64_t *sg = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+    int64_t *sd = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+    int64_t *sq = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+    int64_t *sr = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+    int64_t *pg = (int64_t *)malloc(sizeof(int64_t) * mg);
+    int64_t *pd = (int64_t *)malloc(sizeof(int64_t) * md);
+    /* per particle, in the order of level n (gas: A1, A2 include g) */
+    double *A1 = (double *)malloc(sizeof(double) * dim * mg), *A2 = (double *)malloc(sizeof(double) * dim * mg);
+    double *E1 = (double *)malloc(sizeof(double) * mg), *E2 = (double *)malloc(sizeof(double) * mg);
+    double *V2 = (double *)malloc(sizeof(double) * dim * mg), *D2 = (double *)malloc(sizeof(double) * dim * mg);
+    double *U2 = (double *)malloc(sizeof(double) * dim * md), *F2 = (double *)malloc(sizeof(double) * dim * md);
+    double *At = (double *)malloc(sizeof(double) * dim * mg), *Et = (double *)malloc(sizeof(double) * mg);
+    double *Pq = (double *)malloc(sizeof(double) * dim * mg), *Pr = (double *)malloc(sizeof(double) * dim * md);
+    orc_cell *cells = (orc_cell *)malloc(sizeof(orc_cell) * nc);
+    orc_stage_copy Q, Rr;
+    orc_stage_alloc(&Q, G, dim);
+    orc_stage_alloc(&Rr, Dd, dim);
+    int64_t empty_total = 0;
+
+    for (int32_t s = 0; s < nsteps; ++s) {
+        /* stage 1: volumes and explicit terms at level n */
+        orc_canonicalize(p, G);
+        orc_canonicalize(p, Dd);
+        orc_sort(p, G);
+        orc_sort(p, Dd);
+        orc_cell_start(p, G, sg);
+        orc_cell_start(p, Dd, sd);
+        orc_density(p, G, sg, G->rho);
+        orc_gas_forces(p, G, sg, A1, G->energy ? E1 : NULL);
+
+        /* stage 2 predictor: Y2~ = y^n + gamma tau f(Y1) */
+        for (int64_t a = 0; a < ng; ++a) {
+            Q.cell[a] = G->cell[a];
+            Q.id[a] = G->id[a];
+            Q.mass[a] = G->mass[a];
+            for (int d = 0; d < dim; ++d) {
+                Q.off[d * ng + a] = G->off[d * ng + a] + gtau * G->vel[d * ng + a];
+                Q.vel[d * ng + a] = G->vel[d * ng + a] + gtau * A1[d * ng + a];
+            }
+            if (G->energy) Q.energy[a] = G->energy[a] + gtau * E1[a];
+        }
+        for (int64_t j = 0; j < nd; ++j) {
+            Rr.cell[j] = Dd->cell[j];
+            Rr.id[j] = Dd->id[j];
+            Rr.mass[j] = Dd->mass[j];
+            for (int d = 0; d < dim; ++d) {
+                Rr.off[d * nd + j] = Dd->off[d * nd + j] + gtau * Dd->vel[d * nd + j];
+                Rr.vel[d * nd + j] = Dd->vel[d * nd + j] + gtau * p->g[d];
+            }
+        }
+        /* volumes at the stage-2 positions, implicit drag over gamma tau */
+        orc_canonicalize(p, &Q.ph);
+        orc_canonicalize(p, &Rr.ph);
+        orc_sort_perm(p, &Q.ph, pg);
+        orc_sort_perm(p, &Rr.ph, pd);
+        orc_cell_start(p, &Q.ph, sq);
+        orc_cell_start(p, &Rr.ph, sr);
+        memcpy(Pq, Q.vel, sizeof(double) * dim * ng);
+        memcpy(Pr, Rr.vel, sizeof(double) * dim * nd);
+        empty_total += orc_drag_cells(p, &Q.ph, &Rr.ph, sq, sr, gtau, vol, cells);
+        for (int64_t k = 0; k < ng; ++k)
+            for (int d = 0; d < dim; ++d) {
+                V2[d * ng + pg[k]] = Q.vel[d * ng + k];
+                D2[d * ng + pg[k]] = Q.vel[d * ng + k] - Pq[d * ng + k];
+            }
+        for (int64_t k = 0; k < nd; ++k)
+            for (int d = 0; d < dim; ++d) {
+                U2[d * nd + pd[k]] = Rr.vel[d * nd + k];
+                F2[d * nd + pd[k]] = Rr.vel[d * nd + k] - Pr[d * nd + k];
+            }
+        /* explicit terms at Y2 */
+        orc_density(p, &Q.ph, sq, Q.rho);
+        orc_gas_forces(p, &Q.ph, sq, At, Q.energy ? Et : NULL);
+        for (int64_t k = 0; k < ng; ++k) {
+            for (int d = 0; d < dim; ++d) A2[d * ng + pg[k]] = At[d * ng + k];
+            if (Q.energy) E2[pg[k]] = Et[k];
+        }
+
+        /* stage 3 predictor, in the order of level n:
+         * Y3~ = y^n + tau (delta f(Y1) + (1 - delta) f(Y2)) + tau (1 - gamma) g(Y2) */
+        for (int64_t a = 0; a < ng; ++a) {
+            for (int d = 0; d < dim; ++d) {
+                const double v0 = G->vel[d * ng + a];
+                G->off[d * ng + a] += tau * (del * v0 + (1.0 - del) * V2[d * ng + a]);
+                G->vel[d * ng + a] = v0 + tau * (del * A1[d * ng + a] + (1.0 - del) * A2[d * ng + a])
+                                     + rg * D2[d * ng + a];
+            }
+            if (G->energy) G->energy[a] += tau * (del * E1[a] + (1.0 - del) * E2[a]);
+        }
+        for (int64_t j = 0; j < nd; ++j)
+            for (int d = 0; d < dim; ++d) {
+                const double u0 = Dd->vel[d * nd + j];
+                Dd->off[d * nd + j] += tau * (del * u0 + (1.0 - del) * U2[d * nd + j]);
+                Dd->vel[d * nd + j] = u0 + tau * p->g[d] + rg * F2[d * nd + j];
+            }
+        /* volumes at the stage-3 positions, implicit drag over gamma tau: y^{n+1} = Y3 */
+        orc_canonicalize(p, G);
+        orc_canonicalize(p, Dd);
+        orc_sort(p, G);
+        orc_sort(p, Dd);
+        orc_cell_start(p, G, sg);
+        orc_cell_start(p, Dd, sd);
+        empty_total += orc_drag_cells(p, G, Dd, sg, sd, gtau, vol, cells);
+    }
+    orc_stage_free(&Q);
+    orc_stage_free(&Rr);
+    free(sg); free(sd); free(sq); free(sr); free(pg); free(pd);
+    free(A1); free(A2); free(E1); free(E2); free(V2); free(D2); free(U2); free(F2);
+    free(At); free(Et); free(Pq); free(Pr); free(cells);
     return empty_total;
 }
 

@@ -78,6 +78,8 @@ class Params:
                               # (t_stop then varies per cell as rho*_d / K; t_stop above is unused)
     t_stop_epstein: float = 0.0   # > 0: t*_stop = t_stop_epstein / rho*_g per cell (Epstein drag with
                                   # fixed grain size and sound speed); t_stop and K unused
+    scheme: int = 0           # 0: first-order IDIC step; 1: second-order IMEX step, ARS(2,2,2) with
+                              # the drag in cell as its implicit part
 
     def cell_width(self):
         return tuple((self.hi[k] - self.lo[k]) / self.n_cells[k] for k in range(3))
