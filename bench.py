@@ -216,6 +216,25 @@ def batched_throughput(I, T, torch, steps=500, plain_steps=20):
             "plain_path_value": plain, "vs_plain": value / plain, "nonfinite": bool(flags & 1)}
 
 
+def imex_throughput(prob, T, torch, steps=50, warmup=3):
+    """The same workload with the second-order IMEX step (three binnings, two density and force
+    passes, two drag solves per step)."""
+    q = prob.copy()
+    q.params = q.params.replace(scheme=T.TFSPH_SCHEME_IMEX2)
+    sim = T.Simulation(q, precision=T.TFSPH_F32)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    flags, _ = sim.flags()
+    sim.close()
+    n = q.gas.n + q.dust.n
+    return {"ms_per_step": 1e3 * wall / steps, "value": n * steps / wall, "unit": "particle-steps/s",
+            "steps": steps, "nonfinite": bool(flags & T.TFSPH_FLAG_NONFINITE)}
+
+
 def cpu_baseline(prob, steps: int, steps_1t: int = 1):
     """The FP64 oracle on the host cores (all threads, then one thread) on a bounded sample."""
     from oracle import oracle as O
@@ -246,7 +265,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="box3d", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint and batched measurements")
+    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint, batched and IMEX measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times (reference for HBM byte counters)")
     a = ap.parse_args(argv)
@@ -359,6 +378,10 @@ def main(argv=None):
         result["adjoint"] = adj
         print("[bench] batched 1D waves", file=sys.stderr, flush=True)
         result["batched"] = batched_throughput(I, T, torch)
+        print("[bench] second-order IMEX step on the same workload", file=sys.stderr, flush=True)
+        imex = imex_throughput(prob, T, torch)
+        imex["cost_vs_first_order"] = imex["ms_per_step"] / result["uninstrumented"]["ms_per_step"]
+        result["imex"] = imex
     if not a.no_cpu_baseline:
         print(f"[bench] oracle on host cores, {a.cpu_steps} steps", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(prob, a.cpu_steps)

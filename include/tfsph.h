@@ -60,6 +60,7 @@ enum {
 
 enum { TFSPH_F32 = 0, TFSPH_F64 = 1 };
 enum { TFSPH_ISOTHERMAL = 0, TFSPH_ADIABATIC = 1 };
+enum { TFSPH_SCHEME_IDIC = 0, TFSPH_SCHEME_IMEX2 = 1 };
 
 /* Run parameters; symbols follow the paper. */
 typedef struct {
@@ -86,6 +87,18 @@ typedef struct {
                                drag volume, the Epstein regime at fixed grain size and sound speed
                                (t_stop_epstein is the stopping time at unit gas density); t_stop
                                is unused */
+    int32_t scheme;         /* time discretisation of tfsph_step:
+                               TFSPH_SCHEME_IDIC: the paper's step, eqs. (19)-(21) with first-order
+                               time differences (Section 2.3);
+                               TFSPH_SCHEME_IMEX2: second order, the ARS(2,2,2) IMEX pair of Ascher,
+                               Ruuth & Spiteri (1997) with the drag in cell as its implicit part and
+                               the drift, pressure, viscosity, gravity and energy terms as its
+                               explicit part; each implicit stage is the first-order drag solve over
+                               gamma tau (gamma = 1 - 1/sqrt(2)) on that stage's volumes.  Per step:
+                               three binnings, two density and force passes, two drag solves; rho
+                               on exit is the density at the start of the step and the one-phase
+                               count covers both solves.  The batched and adjoint entry points
+                               accept TFSPH_SCHEME_IDIC only (TFSPH_E_UNSUPPORTED otherwise). */
 } tfsph_params;
 
 /* One particle phase (gas: indices a, b; dust: j, k in the paper's notation).

@@ -276,6 +276,8 @@ tfsph_status check_adjoint_args(const tfsph_params *p, int64_t ng, int64_t nd, i
 {
     tfsph_status r = tfsph_validate(p);
     if (r != TFSPH_OK) return r;
+    if (p->scheme != TFSPH_SCHEME_IDIC)
+        return fail(TFSPH_E_UNSUPPORTED, "the adjoint differentiates the first-order step only");
     if (p->eos != TFSPH_ISOTHERMAL || p->av_alpha != 0.0 || p->av_beta != 0.0)
         return fail(TFSPH_E_UNSUPPORTED, "the adjoint covers the isothermal EOS without artificial viscosity");
     if (n_steps < 1) return fail(TFSPH_E_INVALID_ARG, "n_steps must be >= 1");

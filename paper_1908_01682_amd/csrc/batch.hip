@@ -96,6 +96,8 @@ tfsph_status check_desc(const tfsph_batch_desc *desc, std::vector<InstLayout> &L
         const tfsph_params *p = &desc->params[i];
         tfsph_status r = tfsph_validate(p);
         if (r != TFSPH_OK) return fail(r, "instance %d: %s", i, tfsph_last_error());
+        if (p->scheme != TFSPH_SCHEME_IDIC)
+            return fail(TFSPH_E_UNSUPPORTED, "instance %d: the batched form runs the first-order step only", i);
         if (p->dim != dim || p->precision != prec)
             return fail(TFSPH_E_INVALID_ARG, "instance %d: dim/precision differ from instance 0", i);
         if (p->eos != TFSPH_ISOTHERMAL) return fail(TFSPH_E_UNSUPPORTED, "instance %d: batched form is isothermal", i);

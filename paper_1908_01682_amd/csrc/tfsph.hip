@@ -16,6 +16,7 @@
 #include "host.hpp"
 #include "sph.hpp"
 #include "enqueue.hpp"
+#include "imex.hpp"
 
 using namespace tfsph;
 using namespace tfsph_host;
@@ -77,6 +78,8 @@ extern "C" tfsph_status tfsph_validate(const tfsph_params *p)
     if (p->K == 0.0 && p->t_stop_epstein == 0.0 && !finite_pos(p->t_stop))
         return fail(TFSPH_E_INVALID_ARG, "t_stop must be positive (or K or t_stop_epstein > 0)");
     if (!finite_pos(p->dt)) return fail(TFSPH_E_INVALID_ARG, "dt must be positive");
+    if (p->scheme != TFSPH_SCHEME_IDIC && p->scheme != TFSPH_SCHEME_IMEX2)
+        return fail(TFSPH_E_INVALID_ARG, "scheme must be TFSPH_SCHEME_IDIC or TFSPH_SCHEME_IMEX2");
     if (p->eos == TFSPH_ISOTHERMAL && !finite_pos(p->c_s)) return fail(TFSPH_E_INVALID_ARG, "c_s must be positive");
     if (p->eos == TFSPH_ADIABATIC && !(std::isfinite(p->gamma) && p->gamma > 1.0))
         return fail(TFSPH_E_INVALID_ARG, "gamma must be > 1");
@@ -93,6 +96,67 @@ extern "C" tfsph_status tfsph_validate(const tfsph_params *p)
 namespace {
 
 
+// Workspace of the second-order IMEX step beyond the first-order one: the
+// binning of the stage-2 and stage-3 positions (with the level-n index of each
+// sorted slot), the stage predictors as a phase to bin, and the stage data.
+template <typename R>
+struct ImexViews {
+    Sorted<R> Sg, Sd;
+    Phase<R> Qg, Qd;
+    Stage<R> Xg, Xd;
+};
+
+template <typename R>
+Phase<R> carve_stage_phase(Carver &cv, int n, int dim, bool mass, bool energy, double m_uniform)
+{
+    Phase<R> Q{};
+    Q.n = n;
+    Q.cell = cv.take<int>(n);
+    Q.id = cv.take<int>(n);
+    for (int d = 0; d < dim; ++d) {
+        Q.off[d] = cv.take<R>(n);
+        Q.vel[d] = cv.take<R>(n);
+    }
+    Q.mass = mass ? cv.take<R>(n) : nullptr;
+    Q.m_uniform = R(m_uniform);
+    Q.energy = energy ? cv.take<R>(n) : nullptr;
+    return Q;
+}
+
+template <typename R>
+Stage<R> carve_stage(Carver &cv, int n, int dim, bool gas, bool energy)
+{
+    Stage<R> X{};
+    for (int d = 0; d < dim; ++d) {
+        X.v2[d] = cv.take<R>(n);
+        X.dv2[d] = cv.take<R>(n);
+        if (gas) {
+            X.acc1[d] = cv.take<R>(n);
+            X.acc2[d] = cv.take<R>(n);
+        }
+    }
+    if (gas && energy) {
+        X.de1 = cv.take<R>(n);
+        X.de2 = cv.take<R>(n);
+    }
+    return X;
+}
+
+template <typename R>
+void carve_imex(Carver &cv, const tfsph_params *p, int ng, int nd, PhaseFlags fg, PhaseFlags fd, double mg_uniform,
+                double md_uniform, ImexViews<R> &V)
+{
+    const int ncell = ncell_of(p);
+    V.Sg = carve_phase<R>(cv, ng, p->dim, ncell, fg);
+    V.Sg.src = cv.take<int>(ng);
+    V.Sd = carve_phase<R>(cv, nd, p->dim, ncell, fd);
+    V.Sd.src = cv.take<int>(nd);
+    V.Qg = carve_stage_phase<R>(cv, ng, p->dim, fg.mass, fg.energy, mg_uniform);
+    V.Qd = carve_stage_phase<R>(cv, nd, p->dim, fd.mass, false, md_uniform);
+    V.Xg = carve_stage<R>(cv, ng, p->dim, true, fg.energy);
+    V.Xd = carve_stage<R>(cv, nd, p->dim, false, false);
+}
+
 template <typename R>
 size_t plan_bytes(const tfsph_params *p, int ng, int nd, PhaseFlags fg, PhaseFlags fd)
 {
@@ -103,6 +167,10 @@ size_t plan_bytes(const tfsph_params *p, int ng, int nd, PhaseFlags fg, PhaseFla
     cv.take<int>(size_t(2) * ntiles_of(ncell));
     cv.take<unsigned int>(64);
     cv.take<unsigned long long>(8);
+    if (p->scheme == TFSPH_SCHEME_IMEX2) {
+        ImexViews<R> V;
+        carve_imex<R>(cv, p, ng, nd, fg, fd, 0.0, 0.0, V);
+    }
     return cv.off + 256;
 }
 
@@ -184,7 +252,8 @@ extern "C" tfsph_status tfsph_workspace_size(const tfsph_params *p, int64_t n_ga
 namespace {
 
 template <typename R>
-void carve_all(const tfsph_ctx *c, Sorted<R> &Sg, Sorted<R> &Sd, int *&partial, Flags &F)
+void carve_all(const tfsph_ctx *c, Sorted<R> &Sg, Sorted<R> &Sd, int *&partial, Flags &F,
+               ImexViews<R> *imex = nullptr)
 {
     Carver cv;
     cv.base = c->ws;
@@ -194,6 +263,7 @@ void carve_all(const tfsph_ctx *c, Sorted<R> &Sg, Sorted<R> &Sd, int *&partial, 
     partial = cv.take<int>(size_t(2) * ntiles_of(ncell));
     F.word = cv.take<unsigned int>(64);
     F.one_phase = cv.take<unsigned long long>(8);
+    if (imex) carve_imex<R>(cv, &c->p, c->ng, c->nd, c->fg, c->fd, c->mg_uniform, c->md_uniform, *imex);
 }
 
 }  // namespace
@@ -262,6 +332,134 @@ tfsph_status enqueue_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
 }
 
 template <typename R>
+ImexCoef<R> imex_coef(double tau)
+{
+    const double gam = 1.0 - 1.0 / std::sqrt(2.0);
+    const double del = 1.0 - 1.0 / (2.0 * gam);
+    ImexCoef<R> C;
+    C.tau = R(tau);
+    C.gtau = R(gam * tau);
+    C.del = R(del);
+    C.omd = R(1.0 - del);
+    C.rg = R((1.0 - gam) / gam);
+    return C;
+}
+
+// one drag solve over gamma tau on the binning (Sg, Sd) of a stage
+template <typename R, int DIM, bool FINAL>
+tfsph_status enqueue_relax(const tfsph_ctx *c, const Geom<R> &G, const Phys<R> &PhE, const ImexViews<R> &V,
+                           const Phase<R> &Pg, const Phase<R> &Pd, const R *rho1, const Flags &F, hipStream_t st)
+{
+    const int cpb = c->cells_per_block;
+    const int nblocks = (G.ncell + cpb - 1) / cpb;
+    hipLaunchKernelGGL((k_imex_relax<R, DIM, FINAL>), dim3(nblocks), dim3(kBlock), update_lds_bytes<R>(cpb), st, G,
+                       PhE, V.Sg, V.Sd, V.Xg, V.Xd, Pg, Pd, rho1, F, cpb, nblocks);
+    LAUNCH_CHECK("imex_relax");
+    return TFSPH_OK;
+}
+
+// explicit gas terms at a stage, with the pair-loop kind of the run
+template <typename R, int DIM, typename L>
+void launch_by_kind(const Phys<R> &Ph, const Sorted<R> &S, L &&launch)
+{
+    if (Ph.av || Ph.eos != 0)
+        launch(IntC<kForceGeneral>{});
+    else if (S.has_mass)
+        launch(IntC<kForceIsoMass>{});
+    else
+        launch(IntC<kForceIsoUniform>{});
+}
+
+// One second-order IMEX step: see imex.hpp for the stages.
+template <typename R, int DIM>
+tfsph_status enqueue_step_imex(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
+{
+    const Geom<R> G = make_geom<R>(&c->p);
+    const Phys<R> Ph = make_phys<R>(&c->p);
+    tfsph_params pe = c->p;
+    pe.dt = c->p.dt * (1.0 - 1.0 / std::sqrt(2.0));
+    for (int d = 0; d < 3; ++d) pe.g[d] = 0.0;      // predictors already hold the explicit terms
+    const Phys<R> PhE = make_phys<R>(&pe);
+    const ImexCoef<R> C = imex_coef<R>(c->p.dt);
+    Phase<R> Pg = make_phase<R>(s->gas, DIM), Pd = make_phase<R>(s->dust, DIM);
+    Sorted<R> Sg, Sd;
+    int *partial;
+    Flags F;
+    ImexViews<R> V;
+    carve_all<R>(c, Sg, Sd, partial, F, &V);
+    if (c->variant != TFSPH_VARIANT_AUTO) Sg.nmask = V.Sg.nmask = nullptr;
+    const int ng = c->ng, nd = c->nd;
+    const int bg = blocks_for(ng), bd = blocks_for(nd);
+    tfsph_status r;
+
+    // stage 1: volumes and explicit terms at level n, stage-2 predictors
+    MARK(TFSPH_KERNEL_BIN);
+    r = enqueue_bin<R>(ng, nd, G, Pg, Pd, Sg, Sd, partial, F, st);
+    if (r != TFSPH_OK) return r;
+    MARK(TFSPH_KERNEL_BIN);
+    if (ng > 0) {
+        MARK(TFSPH_KERNEL_DENSITY);
+        r = enqueue_density<R, DIM>(G, Ph, Sg, 1, st, c->variant);
+        if (r != TFSPH_OK) return r;
+        MARK(TFSPH_KERNEL_DENSITY);
+    }
+    MARK(TFSPH_KERNEL_FORCE);
+    if (ng > 0) {
+        launch_by_kind<R, DIM>(Ph, Sg, [&](auto K) {
+            hipLaunchKernelGGL((k_imex_gas1<R, DIM, decltype(K)::value>), dim3(bg), dim3(kBlock), 0, st, G, Ph, Sg,
+                               V.Xg, V.Qg, C, F);
+        });
+        LAUNCH_CHECK("imex_gas1");
+    }
+    if (nd > 0) {
+        hipLaunchKernelGGL((k_imex_dust1<R, DIM>), dim3(bd), dim3(kBlock), 0, st, G, Ph, Sd, V.Qd, C, F);
+        LAUNCH_CHECK("imex_dust1");
+    }
+    MARK(TFSPH_KERNEL_FORCE);
+
+    // stage 2: volumes at the stage-2 positions, drag over gamma tau, explicit terms at Y2
+    MARK(TFSPH_KERNEL_BIN);
+    r = enqueue_bin<R>(ng, nd, G, V.Qg, V.Qd, V.Sg, V.Sd, partial, F, st);
+    if (r != TFSPH_OK) return r;
+    MARK(TFSPH_KERNEL_BIN);
+    MARK(TFSPH_KERNEL_UPDATE);
+    r = enqueue_relax<R, DIM, false>(c, G, PhE, V, Pg, Pd, nullptr, F, st);
+    if (r != TFSPH_OK) return r;
+    MARK(TFSPH_KERNEL_UPDATE);
+    if (ng > 0) {
+        MARK(TFSPH_KERNEL_DENSITY);
+        r = enqueue_density<R, DIM>(G, Ph, V.Sg, 1, st, c->variant);
+        if (r != TFSPH_OK) return r;
+        MARK(TFSPH_KERNEL_DENSITY);
+        MARK(TFSPH_KERNEL_FORCE);
+        launch_by_kind<R, DIM>(Ph, V.Sg, [&](auto K) {
+            hipLaunchKernelGGL((k_imex_gas2<R, DIM, decltype(K)::value>), dim3(bg), dim3(kBlock), 0, st, G, Ph,
+                               V.Sg, V.Xg, F);
+        });
+        LAUNCH_CHECK("imex_gas2");
+        MARK(TFSPH_KERNEL_FORCE);
+    }
+
+    // stage 3: predictors in level-n order, volumes at the stage-3 positions, last drag solve
+    MARK(TFSPH_KERNEL_UPDATE);
+    if (bg + bd > 0) {
+        hipLaunchKernelGGL((k_imex_stage3<R, DIM>), dim3(bg + bd), dim3(kBlock), 0, st, G, Ph, Sg, Sd, V.Xg, V.Xd,
+                           V.Qg, V.Qd, C, bg, F);
+        LAUNCH_CHECK("imex_stage3");
+    }
+    MARK(TFSPH_KERNEL_UPDATE);
+    MARK(TFSPH_KERNEL_BIN);
+    r = enqueue_bin<R>(ng, nd, G, V.Qg, V.Qd, V.Sg, V.Sd, partial, F, st);
+    if (r != TFSPH_OK) return r;
+    MARK(TFSPH_KERNEL_BIN);
+    MARK(TFSPH_KERNEL_UPDATE);
+    r = enqueue_relax<R, DIM, true>(c, G, PhE, V, Pg, Pd, Sg.rho, F, st);
+    if (r != TFSPH_OK) return r;
+    MARK(TFSPH_KERNEL_UPDATE);
+    return TFSPH_OK;
+}
+
+template <typename R>
 tfsph_status enqueue_init(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
 {
     const Geom<R> G = make_geom<R>(&c->p);
@@ -324,10 +522,11 @@ tfsph_status enqueue_density(tfsph_ctx *c, tfsph_state *s, int phase, hipStream_
 template <typename R>
 tfsph_status dispatch_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
 {
+    const bool imex = c->p.scheme == TFSPH_SCHEME_IMEX2;
     switch (c->p.dim) {
-    case 1: return enqueue_step<R, 1>(c, s, st);
-    case 2: return enqueue_step<R, 2>(c, s, st);
-    default: return enqueue_step<R, 3>(c, s, st);
+    case 1: return imex ? enqueue_step_imex<R, 1>(c, s, st) : enqueue_step<R, 1>(c, s, st);
+    case 2: return imex ? enqueue_step_imex<R, 2>(c, s, st) : enqueue_step<R, 2>(c, s, st);
+    default: return imex ? enqueue_step_imex<R, 3>(c, s, st) : enqueue_step<R, 3>(c, s, st);
     }
 }
 

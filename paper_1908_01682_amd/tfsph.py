@@ -25,6 +25,7 @@ TFSPH_FLAG_NONFINITE = 1
 TFSPH_FLAG_EMPTY_PHASE_CELL = 2
 TFSPH_FLAG_BAD_CELL = 4
 TFSPH_FLAG_CELL_OVERFLOW = 8
+TFSPH_SCHEME_IDIC, TFSPH_SCHEME_IMEX2 = 0, 1
 
 STATUS = {0: "TFSPH_OK", -1: "TFSPH_E_INVALID_ARG", -2: "TFSPH_E_WORKSPACE", -3: "TFSPH_E_HIP",
           -4: "TFSPH_E_UNSUPPORTED", -5: "TFSPH_E_STATE"}
@@ -42,7 +43,7 @@ class Params(ctypes.Structure):
                 ("c_s", ctypes.c_double), ("gamma", ctypes.c_double), ("t_stop", ctypes.c_double),
                 ("g", ctypes.c_double * 3), ("dt", ctypes.c_double), ("av_alpha", ctypes.c_double),
                 ("av_beta", ctypes.c_double), ("precision", ctypes.c_int32), ("K", ctypes.c_double),
-                ("t_stop_epstein", ctypes.c_double)]
+                ("t_stop_epstein", ctypes.c_double), ("scheme", ctypes.c_int32)]
 
 
 class PhaseC(ctypes.Structure):
@@ -151,6 +152,7 @@ def make_params(p, precision: int = TFSPH_F32) -> Params:
     c.precision = int(precision)
     c.K = float(getattr(p, "K", 0.0))
     c.t_stop_epstein = float(getattr(p, "t_stop_epstein", 0.0))
+    c.scheme = int(getattr(p, "scheme", TFSPH_SCHEME_IDIC))
     return c
 
 

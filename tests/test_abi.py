@@ -154,3 +154,28 @@ def test_validate_drag_coefficient_mode(lib):
     assert _status(p) == -1
     p.K, p.t_stop_epstein = 0.0, -1.0
     assert _status(p) == -1
+
+
+def test_validate_scheme(lib):
+    """scheme selects the first-order step (0) or the second-order IMEX step (1); anything else
+    is rejected on the host."""
+    p = _good()
+    for ok in (T.TFSPH_SCHEME_IDIC, T.TFSPH_SCHEME_IMEX2):
+        p.scheme = ok
+        assert _status(p) == 0, T.lib().tfsph_last_error()
+    for bad in (-1, 2, 7):
+        p.scheme = bad
+        assert _status(p) == -1
+
+
+def test_imex_workspace_holds_the_stage_data(lib):
+    """The IMEX step keeps, per gas particle, a second sorted copy with its level-n index, the
+    stage predictor (cell, id, offsets, velocity) and the stage data (two accelerations, the
+    stage-2 velocity and its drag increment): in FP32 3D at least 4 + 8 + 24 + 48 bytes more."""
+    prob = I.dusty_box(n_side=16, cells_per_axis=8)
+    p1 = T.make_params(prob.params)
+    p2 = T.make_params(prob.params.replace(scheme=1))
+    n = 4096
+    a = T.tfsph_workspace_size(p1, n, n)
+    b = T.tfsph_workspace_size(p2, n, n)
+    assert b - a >= n * (4 + 8 + 24 + 48)

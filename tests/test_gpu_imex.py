@@ -1,0 +1,177 @@
+"""GPU parity of the second-order IMEX step (scheme TFSPH_SCHEME_IMEX2) through the C ABI against
+the FP64 oracle's IMEX step: 1e-5 normalised per step in FP32, 1e-11 in FP64, on the workloads of
+the first-order parity tests (1D/2D/3D, adiabatic with viscosity, stiff drag, K held constant, the
+Epstein law, gravity, two-cell windows), plus invariance under the pair-loop variant and the launch
+shape, graph replays, and a long FP32 run."""
+import numpy as np
+import pytest
+
+from paper_1908_01682_amd import inputs as I
+from tests.gpu_util import HAVE_GPU, banner, by_id, compare_states, needs_gpu, oracle_phase
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+if HAVE_GPU:
+    import torch
+    from paper_1908_01682_amd import tfsph as T
+
+TOL32 = 1e-5
+TOL64 = 1e-11
+
+
+def _imex(prob, **kw):
+    prob.params = prob.params.replace(scheme=1, **kw)
+    return prob
+
+
+def _sim(prob, precision):
+    banner(f"imex {prob.name} n=({prob.gas.n},{prob.dust.n}) precision={precision}")
+    return T.Simulation(prob, precision=precision)
+
+
+def _parity(orc, prob, precision, nsteps):
+    sim = _sim(prob, precision)
+    p = prob.params
+    og, od = oracle_phase(orc, sim.gas.numpy(), p.dim), oracle_phase(orc, sim.dust.numpy(), p.dim)
+    one_orc = orc.step(p, og, od, nsteps)
+    sim.step(nsteps)
+    torch.cuda.synchronize()
+    err = compare_states(p, sim.gas.numpy(), sim.dust.numpy(), og, od, p.c_s)
+    flags, one = sim.flags()
+    sim.close()
+    return err, flags, one, one_orc
+
+
+CASES = [
+    ("wave1d_f64", lambda: _imex(I.workload("wave1d")), 1),
+    ("wave1d_f32", lambda: _imex(I.dusty_wave(n_side=200, amp=1e-2, cells_per_axis=100)), 0),
+    ("shock_f32", lambda: _imex(I.dusty_shock(n=4000, t_stop=1e-3)), 0),
+    ("shock_f64", lambda: _imex(I.dusty_shock(n=4000, t_stop=1e-3)), 1),
+    ("shock_stiff_f32", lambda: _imex(I.dusty_shock(n=4000, t_stop=1e-5)), 0),
+    ("shock_ragged_tiles", lambda: _imex(I.dusty_shock(n=10002, t_stop=1e-3)), 0),
+    ("box3d_f32", lambda: _imex(I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4)), 0),
+    ("box3d_f64", lambda: _imex(I.dusty_box(n_side=24, cells_per_axis=12, regions_per_axis=4)), 1),
+    ("wave2d_f32", lambda: _imex(I.wave_2d(n_side=64)), 0),
+    ("shock_K500_f32", lambda: _imex(I.dusty_shock(n=4000, K=500.0)), 0),
+    ("box3d_K_f64", lambda: _imex(I.dusty_box(n_side=24, cells_per_axis=12, regions_per_axis=4), K=3000.0), 1),
+    ("box3d_epstein", lambda: _imex(I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4),
+                                    t_stop_epstein=3e-4), 0),
+    ("box3d_gravity", lambda: _imex(I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4),
+                                    g=(0.3, -0.5, 0.2)), 0),
+    ("box3d_window2", lambda: _imex(I.dusty_box(n_side=24, cells_per_axis=16, regions_per_axis=2)), 0),
+    ("wave2d_window2_f64", lambda: _imex(I.dusty_wave(n_side=48, dim=2, amp=1e-2, h_over_dx=1.0,
+                                                      cells_per_axis=32)), 1),
+]
+
+
+@pytest.mark.parametrize("name,make,precision", CASES, ids=[c[0] for c in CASES])
+def test_one_step_parity(orc, name, make, precision):
+    err, flags, one, one_orc = _parity(orc, make(), precision, 1)
+    tol = TOL64 if precision == 1 else TOL32
+    assert all(v <= tol for v in err.values()), err
+    assert not flags & T.TFSPH_FLAG_NONFINITE
+    assert one == one_orc
+
+
+@pytest.mark.parametrize("name,make,precision", [CASES[0], CASES[2], CASES[6], CASES[8], CASES[9]],
+                         ids=["wave1d_f64", "shock", "box3d", "wave2d", "shock_K500"])
+def test_five_step_parity(orc, name, make, precision):
+    """Several steps: each step bins three times and reuses the stage workspace."""
+    err, flags, one, one_orc = _parity(orc, make(), precision, 5)
+    tol = TOL64 if precision == 1 else 5 * TOL32
+    assert all(v <= tol for v in err.values()), err
+    assert one == one_orc
+
+
+def test_one_phase_cells_and_empty_dust(orc):
+    """Cells holding one phase get no drag at either stage (counted per solve, like the oracle);
+    an empty dust phase leaves the gas step as pure SPH."""
+    prob = _imex(I.dusty_wave(n_side=200, amp=1e-2, cells_per_axis=100))
+    keep = np.arange(prob.dust.n) % 3 == 0       # many cells hold gas only
+    prob.dust = I.Phase(prob.dust.x[keep], prob.dust.v[keep], prob.dust.m[keep], prob.dust.id[keep])
+    err, flags, one, one_orc = _parity(orc, prob, 1, 2)
+    assert all(v <= TOL64 for v in err.values()), err
+    assert one == one_orc and one > 0
+    prob = _imex(I.dusty_wave(n_side=200, amp=1e-2, cells_per_axis=100))
+    prob.dust = I.Phase(np.zeros((0, 1)), np.zeros((0, 1)), np.zeros(0), np.zeros(0, dtype=np.int32))
+    err, flags, one, one_orc = _parity(orc, prob, 1, 2)
+    assert all(v <= TOL64 for v in err.values()), err
+
+
+@pytest.mark.parametrize("name,make,precision", [
+    ("box3d", lambda: _imex(I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4)), 0),
+    ("wave2d_f64", lambda: _imex(I.wave_2d(n_side=48, amp=1e-2)), 1),
+    ("shock1d", lambda: _imex(I.dusty_shock(n=3000)), 0),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_variants_and_launch_shape_bitwise_equal(name, make, precision):
+    """Neighbour masks, window scans and LDS bricks, and any cells per block, give the same bits."""
+    prob = make()
+    out = []
+    for variant, cpb in ((T.TFSPH_VARIANT_AUTO, 0), (T.TFSPH_VARIANT_GLOBAL, 0), (T.TFSPH_VARIANT_LDS_BRICKS, 0),
+                         (T.TFSPH_VARIANT_AUTO, 7), (T.TFSPH_VARIANT_AUTO, 256)):
+        sim = _sim(prob, precision)
+        T.tfsph_set_kernel_variant(sim.ctx, variant)
+        if cpb:
+            T.tfsph_set_cells_per_block(sim.ctx, cpb)
+        sim.step(4)
+        torch.cuda.synchronize()
+        out.append((sim.gas.numpy(), sim.dust.numpy()))
+        sim.close()
+    for other in out[1:]:
+        for k in ("cell", "id", "off", "vel", "rho", "energy"):
+            for ph in (0, 1):
+                if out[0][ph].get(k) is not None:
+                    assert np.array_equal(out[0][ph][k], other[ph][k]), (k, ph)
+
+
+@pytest.mark.parametrize("scheme", [0, 1], ids=["first_order", "imex"])
+def test_graph_replays_equal_eager(scheme):
+    """tfsph_step_graph (captured chunks, replayed) gives the bits of tfsph_step, with eager work
+    and synchronisations between the replays."""
+    prob = I.dusty_box(n_side=24, cells_per_axis=12, regions_per_axis=4)
+    prob.params = prob.params.replace(scheme=scheme)
+    eager, graph = _sim(prob, 0), _sim(prob, 0)
+    for _ in range(3):
+        eager.step(5)
+        graph.step_graph(5, chunk=5)
+        torch.cuda.synchronize()
+        a, b = eager.gas.numpy(), graph.gas.numpy()
+        for k in ("cell", "id", "off", "vel", "rho"):
+            assert np.array_equal(a[k], b[k]), k
+        a, b = eager.dust.numpy(), graph.dust.numpy()
+        for k in ("cell", "id", "off", "vel"):
+            assert np.array_equal(a[k], b[k]), k
+    eager.close()
+    graph.close()
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b - np.mean(b)), 1e-300))
+
+
+def test_long_run_wave1d_fp32(orc):
+    """500 IMEX steps of the 1D dusty wave (amplitude 1e-2), FP32 against the FP64 oracle:
+    relative L2 of each velocity field and the density within 1e-3."""
+    prob = _imex(I.dusty_wave(n_side=200, amp=1e-2, t_stop=1e-3, cells_per_axis=100))
+    p = prob.params
+    sim = _sim(prob, 0)
+    og, od = oracle_phase(orc, sim.gas.numpy(), 1), oracle_phase(orc, sim.dust.numpy(), 1)
+    orc.step(p, og, od, 500)
+    sim.step(500)
+    torch.cuda.synchronize()
+    G, D = by_id(sim.gas.numpy()), by_id(sim.dust.numpy())
+    og, od = og.by_id(), od.by_id()
+    errs = {"v": _rel_l2(G["vel"][0], og.vel[0]), "u": _rel_l2(D["vel"][0], od.vel[0]),
+            "rho": _rel_l2(G["rho"], og.rho)}
+    sim.close()
+    banner(f"imex wave1d 500 steps fp32 rel L2 {errs}")
+    assert all(v <= 1e-3 for v in errs.values()), errs
+
+
+def test_full_size_box_one_step(orc):
+    """The 3D box at its benchmark size (128^3 + 128^3, 64^3 cells), one IMEX step: the whole state
+    against the oracle."""
+    prob = _imex(I.dusty_box(n_side=128, cells_per_axis=64, regions_per_axis=8))
+    err, flags, one, one_orc = _parity(orc, prob, 0, 1)
+    assert not flags & T.TFSPH_FLAG_NONFINITE
+    assert all(v <= TOL32 for v in err.values()), err
