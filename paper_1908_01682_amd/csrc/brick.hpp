@@ -147,9 +147,16 @@ __device__ __forceinline__ void for_window_halo(const Geom<R> &G, const BrickGri
     const int wz = DIM > 2 ? G.win[2] : 0;
     const int wy = DIM > 1 ? G.win[1] : 0;
     const int wx = G.win[0];
-    for (int dz = -wz; dz <= wz; ++dz) {
-        const R rz0 = DIM > 2 ? oa[2] - R(dz) * G.delta[2] : R(0);
-        for (int dy = -wy; dy <= wy; ++dy) {
+    const int nrow = (2 * wy + 1) * (2 * wz + 1);
+    // rows in the pair order of for_window_pairs()
+    for (int i = 0; 2 * i < nrow; ++i) {
+        const int nt = 2 * i == nrow - 1 ? 1 : 2;
+#pragma unroll 1
+        for (int t = 0; t < nt; ++t) {
+            const int l = t ? nrow - 1 - i : i;
+            int dy, dz;
+            row_offsets(l, wy, wz, dy, dz);
+            const R rz0 = DIM > 2 ? oa[2] - R(dz) * G.delta[2] : R(0);
             const R ry0 = DIM > 1 ? oa[1] - R(dy) * G.delta[1] : R(0);
             const int row = B.hx * ((ty + dy) + B.hy * (tz + dz));
             for (int dx = -wx; dx <= wx; ++dx) {
@@ -251,7 +258,11 @@ __global__ void __launch_bounds__(NT) k_density_brick(Geom<R> G, Phys<R> Ph, Sor
     const int brick = xcd_brick<DIM>(B.nbricks);
     int bx0, by0, bz0;
     brick_origin<DIM>(B, brick, bx0, by0, bz0);
-    Halo<R> H{sm.data, sm.hstart, sm.gstart, 0};
+    Halo<R> H;           // members assigned one by one: a brace initialiser of LDS
+    H.data = sm.data;    // addresses becomes a constant global, which the backend rejects
+    H.hstart = sm.hstart;
+    H.gstart = sm.gstart;
+    H.total = 0;
     load_halo<R, DIM, NT>(G, B, bx0, by0, bz0, S.start, S.pos, H, sm.waves);
     const int T = brick_targets<R, DIM>(G, B, bx0, by0, bz0, H, sm.tstart);
     for (int t = threadIdx.x; t < T; t += NT) {
@@ -302,7 +313,11 @@ __global__ void __launch_bounds__(NT) k_update_brick(Geom<R> G, Phys<R> Ph, Sort
     int bx0, by0, bz0;
     brick_origin<DIM>(B, brick, bx0, by0, bz0);
     if (threadIdx.x == 0) { s_bad = 0; s_one = 0; }
-    Halo<R> H{sm.data, sm.hstart, sm.gstart, 0};
+    Halo<R> H;           // members assigned one by one: a brace initialiser of LDS
+    H.data = sm.data;    // addresses becomes a constant global, which the backend rejects
+    H.hstart = sm.hstart;
+    H.gstart = sm.gstart;
+    H.total = 0;
     load_halo<R, DIM, NT>(G, B, bx0, by0, bz0, Sg.start, Sg.frc, H, sm.waves);
     const int T = brick_targets<R, DIM>(G, B, bx0, by0, bz0, H, sm.tstart);
 

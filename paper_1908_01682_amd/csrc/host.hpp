@@ -45,15 +45,15 @@ inline int window_of(const tfsph_params *p, int d)
     return (int)std::ceil(2.0 * p->h / D - 1e-12);
 }
 
-// Rows of the neighbour window that carry a 64-bit neighbour mask per gas
-// particle: (2 wy + 1)(2 wz + 1) when the window spans at most 5 cells along x,
-// else 0 (no masks; the force pass scans the window).
+// 64-bit neighbour masks per gas particle: one per pair of opposite window
+// rows, (nrow + 1) / 2 with nrow = (2 wy + 1)(2 wz + 1), when the window spans
+// at most 5 cells along x, else 0 (no masks; the force pass scans the window).
 inline int mask_rows_of(const tfsph_params *p)
 {
     if (window_of(p, 0) > 2) return 0;
     int r = 1;
     for (int d = 1; d < p->dim; ++d) r *= 2 * window_of(p, d) + 1;
-    return r;
+    return (r + 1) / 2;
 }
 
 struct Carver {

@@ -67,29 +67,52 @@ __device__ __forceinline__ void row_ranges(const Geom<R> &G, int cx, int row, co
     }
 }
 
-// Walk the rows of the neighbour window of cell (cx, cy, cz) for a window of
-// WX = G.win[0] cells on each side along x: window z, then y offsets
-// ascending; row_fn(r, bs, be, ry0, rz0) gets the row number, its cell ranges
-// (row_ranges) and the y / z parts of x_a - x_b before the candidate's own
-// offset is subtracted.
-template <typename R, int DIM, int WX, typename RowFn>
-__device__ __forceinline__ void for_window_rows(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
-                                                const int *__restrict__ start, RowFn &&row_fn)
+// Rows of the window are the (dy, dz) offsets, numbered l = (dz + wz)(2 wy + 1)
+// + (dy + wy), l = 0 .. nrow - 1.  They are visited in pairs of opposite rows,
+// l = i and nrow - 1 - i for i = 0, 1, ..., the centre row alone last: opposite
+// rows hold complementary parts of a particle's support, so the pair's
+// neighbour count varies much less between particles than a row's does.
+__device__ __forceinline__ void row_offsets(int l, int wy, int wz, int &dy, int &dz)
+{
+    const int ny = 2 * wy + 1;
+    dz = l / ny - wz;
+    dy = l % ny - wy;
+}
+
+// Walk the window of cell (cx, cy, cz) pair by pair for a window of WX =
+// G.win[0] cells on each side along x: pair_fn(i, bs, be, ry0, rz0) gets the
+// pair number, the cell ranges of its two rows (bs[t], be[t] as row_ranges;
+// the centre row's partner is empty) and the y / z parts of x_a - x_b of each
+// row before the candidate's own offset is subtracted.
+template <typename R, int DIM, int WX, typename PairFn>
+__device__ __forceinline__ void for_window_pairs(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
+                                                 const int *__restrict__ start, PairFn &&pair_fn)
 {
     const int wz = DIM > 2 ? G.win[2] : 0;
     const int wy = DIM > 1 ? G.win[1] : 0;
-    int r = 0;
-    for (int dz = -wz; dz <= wz; ++dz) {
-        const int z = DIM > 2 ? wrap_index(cz + dz, G.nc[2]) : 0;
-        const R rz0 = DIM > 2 ? oa[2] - R(dz) * G.delta[2] : R(0);
-        for (int dy = -wy; dy <= wy; ++dy) {
+    const int nrow = (2 * wy + 1) * (2 * wz + 1);
+    for (int i = 0; 2 * i < nrow; ++i) {
+        int bs[2][2 * WX + 1], be[2][2 * WX + 1];
+        R ry0[2], rz0[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int l = t ? nrow - 1 - i : i;
+            if (t == 1 && l == i) {
+#pragma unroll
+                for (int k = 0; k <= 2 * WX; ++k) bs[1][k] = be[1][k] = 0;
+                ry0[1] = ry0[0];
+                rz0[1] = rz0[0];
+                continue;
+            }
+            int dy, dz;
+            row_offsets(l, wy, wz, dy, dz);
+            const int z = DIM > 2 ? wrap_index(cz + dz, G.nc[2]) : 0;
             const int y = DIM > 1 ? wrap_index(cy + dy, G.nc[1]) : 0;
-            const R ry0 = DIM > 1 ? oa[1] - R(dy) * G.delta[1] : R(0);
-            int bs[2 * WX + 1], be[2 * WX + 1];
-            row_ranges<WX>(G, cx, G.nc[0] * (y + G.nc[1] * z), start, bs, be);
-            row_fn(r, bs, be, ry0, rz0);
-            ++r;
+            rz0[t] = DIM > 2 ? oa[2] - R(dz) * G.delta[2] : R(0);
+            ry0[t] = DIM > 1 ? oa[1] - R(dy) * G.delta[1] : R(0);
+            row_ranges<WX>(G, cx, G.nc[0] * (y + G.nc[1] * z), start, bs[t], be[t]);
         }
+        pair_fn(i, bs, be, ry0, rz0);
     }
 }
 
@@ -112,20 +135,23 @@ __device__ __forceinline__ bool with_row_width(int wx, F &&f)
 }
 
 // Visit every particle of a phase in the neighbour window of a point with
-// offsets oa[] in cell (cx, cy, cz).  Order: window z, y, x offsets
-// ascending, then cell order.  The cell ranges of a row of the window are
-// loaded together before the row is walked.
+// offsets oa[] in cell (cx, cy, cz).  Order: rows in the pair order of
+// for_window_pairs(), inside a row x offsets ascending, then cell order.  The
+// cell ranges of a pair of rows are loaded together before it is walked.
 template <typename R, int DIM, typename Fn>
 __device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
                                            const int *__restrict__ start, const R4<R> *__restrict__ data, Fn &&fn)
 {
     const bool rows = with_row_width(G.win[0], [&](auto W) {
         constexpr int WX = decltype(W)::value;
-        for_window_rows<R, DIM, WX>(G, cx, cy, cz, oa, start, [&](int, const int *bs, const int *be, R ry0, R rz0) {
+        for_window_pairs<R, DIM, WX>(G, cx, cy, cz, oa, start, [&](int, auto &bs, auto &be, const R *ry0, const R *rz0) {
 #pragma unroll
-            for (int k = 0; k <= 2 * WX; ++k) {
-                const R rx0 = oa[0] - R(k - WX) * G.delta[0];
-                visit_range<R, DIM>(bs[k], be[k], data, rx0, ry0, rz0, fn);
+            for (int t = 0; t < 2; ++t) {
+#pragma unroll
+                for (int k = 0; k <= 2 * WX; ++k) {
+                    const R rx0 = oa[0] - R(k - WX) * G.delta[0];
+                    visit_range<R, DIM>(bs[t][k], be[t][k], data, rx0, ry0[t], rz0[t], fn);
+                }
             }
         });
     });
@@ -133,10 +159,15 @@ __device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int
     const int wx = G.win[0];
     const int wz = DIM > 2 ? G.win[2] : 0;
     const int wy = DIM > 1 ? G.win[1] : 0;
-    for (int dz = -wz; dz <= wz; ++dz) {
-        const int z = DIM > 2 ? wrap_index(cz + dz, G.nc[2]) : 0;
-        const R rz0 = DIM > 2 ? oa[2] - R(dz) * G.delta[2] : R(0);
-        for (int dy = -wy; dy <= wy; ++dy) {
+    const int nrow = (2 * wy + 1) * (2 * wz + 1);
+    for (int i = 0; 2 * i < nrow; ++i) {
+        for (int t = 0; t < 2; ++t) {
+            const int l = t ? nrow - 1 - i : i;
+            if (t == 1 && l == i) break;
+            int dy, dz;
+            row_offsets(l, wy, wz, dy, dz);
+            const int z = DIM > 2 ? wrap_index(cz + dz, G.nc[2]) : 0;
+            const R rz0 = DIM > 2 ? oa[2] - R(dz) * G.delta[2] : R(0);
             const int y = DIM > 1 ? wrap_index(cy + dy, G.nc[1]) : 0;
             const R ry0 = DIM > 1 ? oa[1] - R(dy) * G.delta[1] : R(0);
             const int row = G.nc[0] * (y + G.nc[1] * z);
@@ -152,10 +183,11 @@ __device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int
 // ---------------------------------------------------------------------------
 // Neighbour masks.  Positions do not change between the density pass and the
 // force pass, so the density pass records, for every gas particle and every
-// row of its window, which candidates lie inside the support: bit p of row r
-// is the p-th candidate of the row in walking order (cells dx = -wx..wx, each
-// in cell order).  A row with more than 64 candidates is not recorded; the
-// force pass scans such a row.  The support test is q = sqrt(r^2) / h < 2,
+// pair of rows of its window (for_window_pairs()), which candidates lie inside
+// the support: bit p of pair i is the p-th candidate of the pair in walking
+// order (first row, then its opposite; in a row cells dx = -wx..wx, each in
+// cell order).  A pair with more than 64 candidates is not recorded; the force
+// pass scans such a pair.  The support test is q = sqrt(r^2) / h < 2,
 // the same q the force terms use, and those terms vanish exactly for q >= 2
 // (f'(q) = 0), so walking the set bits gives bitwise the sums of the scan.
 // Masks exist only for windows of at most 2 cells on each side along x.
@@ -188,7 +220,7 @@ __device__ __forceinline__ unsigned long long visit_range_bits(int b0, int b1, c
 }
 
 // Walk the window of a point like for_window() and store the neighbour mask
-// of each row at mask[r * stride] (window of at most 2 cells along x).
+// of each pair of rows at mask[i * stride] (window of at most 2 cells along x).
 template <typename R, int DIM, typename Fn>
 __device__ __forceinline__ void for_window_recording(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
                                                      const int *__restrict__ start, const R4<R> *__restrict__ data,
@@ -196,24 +228,30 @@ __device__ __forceinline__ void for_window_recording(const Geom<R> &G, int cx, i
 {
     with_row_width(G.win[0], [&](auto W) {
         constexpr int WX = decltype(W)::value;
-        for_window_rows<R, DIM, WX>(G, cx, cy, cz, oa, start, [&](int r, const int *bs, const int *be, R ry0, R rz0) {
+        for_window_pairs<R, DIM, WX>(G, cx, cy, cz, oa, start, [&](int i, auto &bs, auto &be, const R *ry0,
+                                                                    const R *rz0) {
             unsigned long long m = 0;
             int p0 = 0;
 #pragma unroll
-            for (int k = 0; k <= 2 * WX; ++k) {
-                const R rx0 = oa[0] - R(k - WX) * G.delta[0];
-                m |= visit_range_bits<R, DIM>(bs[k], be[k], data, rx0, ry0, rz0, p0, fn);
-                p0 += be[k] - bs[k];
+            for (int t = 0; t < 2; ++t) {
+#pragma unroll
+                for (int k = 0; k <= 2 * WX; ++k) {
+                    const R rx0 = oa[0] - R(k - WX) * G.delta[0];
+                    m |= visit_range_bits<R, DIM>(bs[t][k], be[t][k], data, rx0, ry0[t], rz0[t], p0, fn);
+                    p0 += be[t][k] - bs[t][k];
+                }
             }
-            mask[size_t(r) * stride] = m;
+            mask[size_t(i) * stride] = m;
         });
     });
 }
 
-// Visit the neighbours of a point recorded in mask[r * stride] (rows of at
-// most kMaskBits candidates) or, for longer rows, every candidate of the row;
-// fn(b, q, rx, ry, rz, valid) as for for_window().  Neighbours are taken kWalk
-// at a time; a lane with fewer left repeats its last one with valid = false.
+// Visit the neighbours of a point recorded in mask[i * stride] (pairs of at
+// most kMaskBits candidates) or, for longer pairs, every candidate of the
+// pair; fn(b, q, rx, ry, rz, valid) as for for_window().  Neighbours are taken
+// kWalk at a time; a lane with fewer left repeats its last one with valid =
+// false.  A set bit p is decoded by the segment (row t, cell k) it falls in:
+// segment s = t (2 WX + 1) + k starts at walking position P[s].
 template <typename R, int DIM, typename Fn>
 __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
                                                const int *__restrict__ start, const R4<R> *__restrict__ data,
@@ -221,29 +259,35 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
 {
     with_row_width(G.win[0], [&](auto W) {
         constexpr int WX = decltype(W)::value;
-        for_window_rows<R, DIM, WX>(G, cx, cy, cz, oa, start, [&](int r, const int *bs, const int *be, R ry0, R rz0) {
-            // first walking position of each cell in the row, and the cell's
-            // index shift and x part of x_a - x_b
-            int P[2 * WX + 1], shift[2 * WX + 1];
-            R rx0[2 * WX + 1];
+        constexpr int NC = 2 * WX + 1;          // cells per row
+        constexpr int NS = 2 * NC;              // segments per pair
+        R rx0[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) rx0[k] = oa[0] - R(k - WX) * G.delta[0];
+        for_window_pairs<R, DIM, WX>(G, cx, cy, cz, oa, start, [&](int i, auto &bs, auto &be, const R *ry0,
+                                                                    const R *rz0) {
+            // first walking position of each segment and its index shift
+            int P[NS], shift[NS];
             int len = 0;
 #pragma unroll
-            for (int k = 0; k <= 2 * WX; ++k) {
-                P[k] = len;
-                shift[k] = bs[k] - len;
-                rx0[k] = oa[0] - R(k - WX) * G.delta[0];
-                len += be[k] - bs[k];
+            for (int s = 0; s < NS; ++s) {
+                const int t = s / NC, k = s % NC;
+                P[s] = len;
+                shift[s] = bs[t][k] - len;
+                len += be[t][k] - bs[t][k];
             }
             if (len > kMaskBits) {
 #pragma unroll
-                for (int k = 0; k <= 2 * WX; ++k) visit_range<R, DIM>(bs[k], be[k], data, rx0[k], ry0, rz0, fn);
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) visit_range<R, DIM>(bs[t][k], be[t][k], data, rx0[k], ry0[t], rz0[t], fn);
                 return;
             }
-            unsigned long long m = mask[size_t(r) * stride];
+            unsigned long long m = mask[size_t(i) * stride];
             int p = 0;
             while (m) {
                 int b[kWalk];
-                R x0[kWalk];
+                R x0[kWalk], y0[kWalk], z0[kWalk];
                 bool ok[kWalk];
 #pragma unroll
                 for (int j = 0; j < kWalk; ++j) {
@@ -253,15 +297,21 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
                     p = ok[j] ? pj : p;
                     m &= m - 1;
                     int sh = shift[0];
-                    R xx = rx0[0];
+                    R xx = rx0[0], yy = ry0[0], zz = rz0[0];
 #pragma unroll
-                    for (int k = 1; k <= 2 * WX; ++k) {
-                        const bool ge = p >= P[k];
-                        sh = ge ? shift[k] : sh;
-                        xx = ge ? rx0[k] : xx;
+                    for (int s = 1; s < NS; ++s) {
+                        const bool ge = p >= P[s];
+                        sh = ge ? shift[s] : sh;
+                        xx = ge ? rx0[s % NC] : xx;
+                        if (s == NC) {
+                            if (DIM > 1) yy = ge ? ry0[1] : yy;
+                            if (DIM > 2) zz = ge ? rz0[1] : zz;
+                        }
                     }
                     b[j] = p + sh;
                     x0[j] = xx;
+                    y0[j] = yy;
+                    z0[j] = zz;
                 }
                 R4<R> q[kWalk];
 #pragma unroll
@@ -269,8 +319,8 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
 #pragma unroll
                 for (int j = 0; j < kWalk; ++j) {
                     const R rx = x0[j] - q[j].x;
-                    const R ry = DIM > 1 ? ry0 - q[j].y : R(0);
-                    const R rz = DIM > 2 ? rz0 - q[j].z : R(0);
+                    const R ry = DIM > 1 ? y0[j] - q[j].y : R(0);
+                    const R rz = DIM > 2 ? z0[j] - q[j].z : R(0);
                     fn(b[j], q[j], rx, ry, rz, ok[j]);
                 }
             }

@@ -129,12 +129,13 @@ def test_tuning_calls_reject_null_context(lib):
 
 
 def test_workspace_holds_neighbour_masks(lib):
-    """AUTO keeps 8 bytes per gas particle and window row for the neighbour masks: 9 rows in 3D
-    with a one-cell window (h = dx, cells of 2h), so 1000 more gas particles need at least 72 kB."""
+    """AUTO keeps 8 bytes per gas particle and pair of opposite window rows for the neighbour
+    masks: 9 rows, so 5 masks, in 3D with a one-cell window (h = dx, cells of 2h); 1000 more gas
+    particles need at least 40 kB."""
     p = T.make_params(I.dusty_box(n_side=16, cells_per_axis=8).params)
     a = T.tfsph_workspace_size(p, 4096, 4096)
     b = T.tfsph_workspace_size(p, 5096, 4096)
-    assert b - a >= 1000 * 8 * 9
+    assert b - a >= 1000 * 8 * 5
 
 
 def test_validate_drag_coefficient_mode(lib):

@@ -175,3 +175,22 @@ def test_full_size_box_one_step(orc):
     err, flags, one, one_orc = _parity(orc, prob, 0, 1)
     assert not flags & T.TFSPH_FLAG_NONFINITE
     assert all(v <= TOL32 for v in err.values()), err
+
+
+def test_second_order_in_time_on_the_gpu():
+    """The HIP path in FP64 converges at second order in tau on the smooth dusty wave (N = 200,
+    t_stop = 0.01, amplitude 1e-4, T = 0.02): successive differences fall by 3.5-4.6 per halving."""
+    outs = []
+    for s in (8, 16, 32, 64):
+        prob = I.dusty_wave(n_side=200, amp=1e-4, t_stop=0.01, cells_per_axis=100)
+        prob.params = prob.params.replace(scheme=1, dt=0.02 / s)
+        sim = _sim(prob, 1)
+        sim.step(s)
+        torch.cuda.synchronize()
+        G, D = by_id(sim.gas.numpy()), by_id(sim.dust.numpy())
+        outs.append(np.concatenate([G["vel"][0], D["vel"][0]]))
+        sim.close()
+    d = [np.max(np.abs(outs[i] - outs[i + 1])) for i in range(3)]
+    r = [d[i] / d[i + 1] for i in range(2)]
+    banner(f"imex gpu successive differences {d} ratios {r}")
+    assert all(3.5 < v < 4.6 for v in r), (d, r)
