@@ -53,12 +53,18 @@ __device__ __forceinline__ R spline_df(R q)
 #define TFSPH_CHUNK 4
 #endif
 #ifndef TFSPH_WALK
-#define TFSPH_WALK 4
+#define TFSPH_WALK 2
 #endif
 #ifdef TFSPH_PAIR_WAVES_PER_EU
 #define TFSPH_PAIR_OCCUPANCY __attribute__((amdgpu_waves_per_eu(TFSPH_PAIR_WAVES_PER_EU)))
+#define TFSPH_FORCE_OCCUPANCY(R, KIND) TFSPH_PAIR_OCCUPANCY
 #else
 #define TFSPH_PAIR_OCCUPANCY
+// The FP32 isothermal force loops fit in 80 VGPRs, six waves per SIMD, and run
+// faster there than at the compiler's choice (89 VGPRs, five waves); the
+// general and FP64 loops would spill, so they keep the compiler's choice.
+#define TFSPH_FORCE_OCCUPANCY(R, KIND) \
+    __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && (KIND) != 2) ? 6 : 1)))
 #endif
 constexpr int kChunk = TFSPH_CHUNK;
 constexpr int kWalk = TFSPH_WALK;

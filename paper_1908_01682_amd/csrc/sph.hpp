@@ -712,7 +712,7 @@ __device__ __forceinline__ bool dust_finish(const Geom<R> &G, const Phys<R> &Ph,
 // Explicit gas terms and predictor, one thread per gas particle, specialised
 // on the kind of force loop.
 template <typename R, int DIM, int KIND>
-__global__ void TFSPH_PAIR_OCCUPANCY __launch_bounds__(kBlock) k_gas_predict(Geom<R> G, Phys<R> Ph, Sorted<R> Sg,
+__global__ void TFSPH_FORCE_OCCUPANCY(R, KIND) __launch_bounds__(kBlock) k_gas_predict(Geom<R> G, Phys<R> Ph, Sorted<R> Sg,
                                                                              Phase<R> Pg)
 {
     const int a = xcd_block(gridDim.x) * kBlock + threadIdx.x;
