@@ -43,12 +43,13 @@ __device__ __forceinline__ void visit_range(int b0, int b1, const R4<R> *__restr
     for (int b = b0; b < b1; b += kChunk) {
         R4<R> q[kChunk];
         load_chunk<Padded>(data, b, b1, q);
+        const int rem = b1 - b;        // >= 1: candidate k of the chunk is real when k < rem
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             const R rx = rx0 - q[k].x;
             const R ry = DIM > 1 ? ry0 - q[k].y : R(0);
             const R rz = DIM > 2 ? rz0 - q[k].z : R(0);
-            fn(b + k, q[k], rx, ry, rz, b + k < b1);
+            fn(b + k, q[k], rx, ry, rz, k == 0 || k < rem);
         }
     }
 }
@@ -205,12 +206,13 @@ __device__ __forceinline__ unsigned long long visit_range_bits(int b0, int b1, c
         R4<R> q[kChunk];
         load_chunk<true>(data, b, b1, q);
         unsigned nib = 0;
+        const int rem = b1 - b;        // >= 1: candidate k of the chunk is real when k < rem
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             const R rx = rx0 - q[k].x;
             const R ry = DIM > 1 ? ry0 - q[k].y : R(0);
             const R rz = DIM > 2 ? rz0 - q[k].z : R(0);
-            nib |= fn(b + k, q[k], rx, ry, rz, b + k < b1) ? (1u << k) : 0u;
+            nib |= fn(b + k, q[k], rx, ry, rz, k == 0 || k < rem) ? (1u << k) : 0u;
         }
         // bits past 63 only occur in rows longer than kMaskBits, which are
         // never read back
