@@ -194,3 +194,13 @@ def test_second_order_in_time_on_the_gpu():
     r = [d[i] / d[i + 1] for i in range(2)]
     banner(f"imex gpu successive differences {d} ratios {r}")
     assert all(3.5 < v < 4.6 for v in r), (d, r)
+
+
+def test_long_run_box3d_fp64(orc):
+    """100 IMEX steps of a small 3D dusty box (24^3 + 24^3 particles, 12^3 cells, uneven dust
+    masses, random velocities) in FP64 against the oracle's IMEX step: normalised max errors
+    within 1e-9 (rounding order only)."""
+    prob = _imex(I.dusty_box(n_side=24, cells_per_axis=12, regions_per_axis=4))
+    err, flags, one, one_orc = _parity(orc, prob, 1, 100)
+    assert not flags & T.TFSPH_FLAG_NONFINITE
+    assert all(v <= 1e-9 for v in err.values()), err
