@@ -81,10 +81,11 @@ void adj_layout(AdjLayout<R> &L, char *base, const tfsph_params *p, int ng, int 
         L.ckpt[s].g = carve_state_phase<R>(cv, ng, dim, mg, false, R(mug));
         L.ckpt[s].d = carve_state_phase<R>(cv, nd, dim, md, false, R(mud));
     }
-    L.tg.assign(K, Sorted<R>{});
-    L.td.assign(K, Sorted<R>{});
-    for (int t = 0; t < K; ++t) {
-        L.tg[t] = carve_phase<R>(cv, ng, dim, ncell, PhaseFlags{mg, false, true});
+    // tapes of one segment's steps, plus one for the binning of the final state
+    L.tg.assign(K + 1, Sorted<R>{});
+    L.td.assign(K + 1, Sorted<R>{});
+    for (int t = 0; t <= K; ++t) {
+        L.tg[t] = carve_phase<R>(cv, ng, dim, ncell, PhaseFlags{mg, false, true, mask_rows_of(p)});
         L.tg[t].src = cv.take<int>(ng);
         L.td[t] = carve_phase<R>(cv, nd, dim, ncell, PhaseFlags{md, false, false});
         L.td[t].src = cv.take<int>(nd);
@@ -187,12 +188,20 @@ tfsph_status rev_step(const Geom<R> &G, const Phys<R> &Ph, AdjLayout<R> &L, int 
         hipLaunchKernelGGL((k_adj_density<R, DIM>), dim3(blocks_for(ng)), dim3(kBlock), 0, st, G, Sg, L.rhobar_g,
                            L.xacc_g[0], L.xacc_g[1], L.xacc_g[2]);
         LAUNCH_CHECK("adj_density");
-        TRY(unsort<R>(ng, DIM, Sg.src, L.xacc_g, L.nxt_g.x, st));
-        TRY(unsort<R>(ng, DIM, Sg.src, L.vtb_g.v, L.nxt_g.v, st));
     }
-    if (nd > 0) {
-        TRY(unsort<R>(nd, DIM, Sd.src, L.cur_d.x, L.nxt_d.x, st));
-        TRY(unsort<R>(nd, DIM, Sd.src, L.ubi_d.v, L.nxt_d.v, st));
+    // undo the step's sorts: gas (x from xacc, v from vtb), dust (x from cur, v from ubi)
+    const int bg = blocks_for(ng), bd = blocks_for(nd);
+    if (bg + bd > 0) {
+        AdjPhase<R> in_g{}, in_d{};
+        for (int k = 0; k < 3; ++k) {
+            in_g.x[k] = L.xacc_g[k];
+            in_g.v[k] = L.vtb_g.v[k];
+            in_d.x[k] = L.cur_d.x[k];
+            in_d.v[k] = L.ubi_d.v[k];
+        }
+        hipLaunchKernelGGL(k_adj_unsort_step<R>, dim3(bg + bd), dim3(kBlock), 0, st, ng, nd, DIM, bg, Sg.src, Sd.src,
+                           in_g, L.nxt_g, in_d, L.nxt_d);
+        LAUNCH_CHECK("adj_unsort_step");
     }
     std::swap(L.cur_g, L.nxt_g);
     std::swap(L.cur_d, L.nxt_d);
@@ -218,15 +227,18 @@ tfsph_status run_adjoint(const tfsph_params *p, const tfsph_state *s, int n_step
     // forward sweep with checkpoints
     TRY(copy_state<R>(Ig, L.W.g, DIM, st));
     TRY(copy_state<R>(Id, L.W.d, DIM, st));
+    // (the last segment's steps keep their tapes, so that segment is not replayed)
+    const int last_first = (nseg - 1) * K;
     for (int i = 0; i < n_steps; ++i) {
         if (i % K == 0) {
             TRY(copy_state<R>(L.W.g, L.ckpt[i / K].g, DIM, st));
             TRY(copy_state<R>(L.W.d, L.ckpt[i / K].d, DIM, st));
         }
-        TRY((fwd_step<R, DIM>(G, Ph, L, 0, st)));
+        TRY((fwd_step<R, DIM>(G, Ph, L, i >= last_first ? i - last_first : 0, st)));
     }
     // loss on the final dust positions and its position adjoint
-    TRY(enqueue_bin<R>(ng, nd, G, L.W.g, L.W.d, L.tg[0], L.td[0], L.partial, L.F, st));
+    Sorted<R> &Fg = L.tg[K], &Fd = L.td[K];
+    TRY(enqueue_bin<R>(ng, nd, G, L.W.g, L.W.d, Fg, Fd, L.partial, L.F, st));
     for (int k = 0; k < DIM; ++k) {
         TRY(fill_dev<R>(L.cur_g.x[k], R(0), ng, st));
         TRY(fill_dev<R>(L.cur_g.v[k], R(0), ng, st));
@@ -236,22 +248,24 @@ tfsph_status run_adjoint(const tfsph_params *p, const tfsph_state *s, int n_step
     }
     if (nd > 0) {
         const int nbd = blocks_for(nd);
-        hipLaunchKernelGGL((k_adj_loss<R, DIM>), dim3(nbd), dim3(kBlock), 0, st, G, L.td[0], target, nd, L.rhobar_d,
+        hipLaunchKernelGGL((k_adj_loss<R, DIM>), dim3(nbd), dim3(kBlock), 0, st, G, Fd, target, nd, L.rhobar_d,
                            L.loss_part);
         LAUNCH_CHECK("adj_loss");
         hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(kBlock), 0, st, L.loss_part, nbd, 1.0 / nd, L.acc + 0, 0);
         LAUNCH_CHECK("adj_reduce");
-        hipLaunchKernelGGL((k_adj_density<R, DIM>), dim3(nbd), dim3(kBlock), 0, st, G, L.td[0], L.rhobar_d,
+        hipLaunchKernelGGL((k_adj_density<R, DIM>), dim3(nbd), dim3(kBlock), 0, st, G, Fd, L.rhobar_d,
                            L.xacc_d[0], L.xacc_d[1], L.xacc_d[2]);
         LAUNCH_CHECK("adj_density");
-        TRY(unsort<R>(nd, DIM, L.td[0].src, L.xacc_d, L.cur_d.x, st));
+        TRY(unsort<R>(nd, DIM, Fd.src, L.xacc_d, L.cur_d.x, st));
     }
     // backward sweep, segment by segment
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int first = seg * K, len = std::min(K, n_steps - first);
-        TRY(copy_state<R>(L.ckpt[seg].g, L.W.g, DIM, st));
-        TRY(copy_state<R>(L.ckpt[seg].d, L.W.d, DIM, st));
-        for (int t = 0; t < len; ++t) TRY((fwd_step<R, DIM>(G, Ph, L, t, st)));
+        if (seg < nseg - 1) {
+            TRY(copy_state<R>(L.ckpt[seg].g, L.W.g, DIM, st));
+            TRY(copy_state<R>(L.ckpt[seg].d, L.W.d, DIM, st));
+            for (int t = 0; t < len; ++t) TRY((fwd_step<R, DIM>(G, Ph, L, t, st)));
+        }
         for (int t = len - 1; t >= 0; --t) TRY((rev_step<R, DIM>(G, Ph, L, t, st)));
     }
     // gradients by id

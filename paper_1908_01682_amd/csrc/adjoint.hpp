@@ -164,7 +164,7 @@ k_adj_force(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, const R *abar0, const R *abar1,
     R Pbar = R(0);
     R xb[3] = {R(0), R(0), R(0)};
     const R inv_h = G.inv_h;
-    for_window<R, DIM>(G, cx, cy, cz, oa, Sg.start, Sg.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
+    auto term = [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
         const R r2 = rx * rx + ry * ry + rz * rz;
         if (ok && r2 < G.support2 && r2 > R(0)) {
             const R ir = frsq(r2);
@@ -183,7 +183,12 @@ k_adj_force(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, const R *abar0, const R *abar1,
             xb[1] -= ps * (f1 * w1 + f2 * rw * ry);
             xb[2] -= ps * (f1 * w2 + f2 * rw * rz);
         }
-    });
+    };
+    // the neighbours recorded by the step's density pass when the tape has masks
+    if (Sg.nmask)
+        for_neighbours<R, DIM>(G, cx, cy, cz, oa, Sg.start, Sg.frc, Sg.nmask + a, Sg.n, term);
+    else
+        for_window<R, DIM>(G, cx, cy, cz, oa, Sg.start, Sg.frc, term);
     Pbar *= G.gnorm;
     rhobar[a] = -Pbar * Pa / Sg.rho[a];
 #pragma unroll
@@ -208,7 +213,7 @@ k_adj_density(Geom<R> G, Sorted<R> S, const R *rhobar, R *xacc0, R *xacc1, R *xa
     const R ma = me.w;
     const R ra = rhobar[a];
     R xb[3] = {R(0), R(0), R(0)};
-    for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
+    auto term = [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
         const R r2 = rx * rx + ry * ry + rz * rz;
         if (ok && r2 < G.support2 && r2 > R(0)) {
             const R ir = frsq(r2);
@@ -218,7 +223,11 @@ k_adj_density(Geom<R> G, Sorted<R> S, const R *rhobar, R *xacc0, R *xacc1, R *xa
             xb[1] += c * ry;
             xb[2] += c * rz;
         }
-    });
+    };
+    if (S.nmask)
+        for_neighbours<R, DIM>(G, cx, cy, cz, oa, S.start, S.pos, S.nmask + a, S.n, term);
+    else
+        for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.pos, term);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) xacc[d][a] += xb[d] * G.gnorm;
 }
@@ -278,6 +287,27 @@ k_adj_unsort(int n, int dim, const int *src, const R *in0, const R *in1, const R
     out0[i] = in0[dst];
     if (dim > 1) out1[i] = in1[dst];
     if (dim > 2) out2[i] = in2[dst];
+}
+
+// The four unsorts of a reverse step in one launch: blocks below blocks_g undo
+// the gas sort (src_g) for positions and velocities, the others the dust sort.
+template <typename R>
+__global__ void __launch_bounds__(kBlock)
+k_adj_unsort_step(int ng, int nd, int dim, int blocks_g, const int *src_g, const int *src_d, AdjPhase<R> in_g,
+                  AdjPhase<R> out_g, AdjPhase<R> in_d, AdjPhase<R> out_d)
+{
+    const bool gas = int(blockIdx.x) < blocks_g;
+    const int dst = (gas ? blockIdx.x : blockIdx.x - blocks_g) * kBlock + threadIdx.x;
+    const int n = gas ? ng : nd;
+    if (dst >= n) return;
+    const int i = (gas ? src_g : src_d)[dst];
+    if (i < 0 || i >= n) return;
+    const AdjPhase<R> &in = gas ? in_g : in_d;
+    const AdjPhase<R> &out = gas ? out_g : out_d;
+    for (int d = 0; d < dim; ++d) {
+        out.x[d][i] = in.x[d][dst];
+        out.v[d][i] = in.v[d][dst];
+    }
 }
 
 // out[d][id[i]] = in[d][i]  (final gradient in id order)
