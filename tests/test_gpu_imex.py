@@ -61,6 +61,10 @@ CASES = [
     ("box3d_window2", lambda: _imex(I.dusty_box(n_side=24, cells_per_axis=16, regions_per_axis=2)), 0),
     ("wave2d_window2_f64", lambda: _imex(I.dusty_wave(n_side=48, dim=2, amp=1e-2, h_over_dx=1.0,
                                                       cells_per_axis=32)), 1),
+    # windows wider than two cells along x: no neighbour masks, the window is scanned
+    ("wave1d_window4", lambda: _imex(I.dusty_wave(n_side=300, amp=1e-2, cells_per_axis=300)), 0),
+    ("wave2d_window3_f64", lambda: _imex(I.dusty_wave(n_side=60, dim=2, amp=1e-2, h_over_dx=1.5,
+                                                      cells_per_axis=60)), 1),
 ]
 
 
