@@ -16,6 +16,13 @@ using namespace tfsph_host;
 
 namespace {
 
+// blocks of k_adj_cell: runs of default_cells_per_block cells
+inline int adj_cell_blocks(int ncell, int dim)
+{
+    const int cpb = default_cells_per_block(dim);
+    return (ncell + cpb - 1) / cpb;
+}
+
 // caller-like state arrays carved from the workspace
 template <typename R>
 struct StateBuf {
@@ -64,6 +71,7 @@ struct AdjLayout {
     R *rhobar_g, *rhobar_d;
     R *xacc_g[3], *xacc_d[3];
     double *sbar_part, *loss_part, *acc;  // acc[0] = loss, acc[1] = dL/dlog t_stop
+    double *sbar_step;                    // per-step sums of sbar_part
     size_t bytes;
 };
 
@@ -106,7 +114,9 @@ void adj_layout(AdjLayout<R> &L, char *base, const tfsph_params *p, int ng, int 
     }
     L.rhobar_g = cv.take<R>(ng);
     L.rhobar_d = cv.take<R>(nd);
-    L.sbar_part = cv.take<double>(blocks_for(ncell));
+    // d/dlog t_stop partials: one per block of k_adj_cell and reverse step, summed once at the end
+    L.sbar_part = cv.take<double>(size_t(nseg) * K * adj_cell_blocks(ncell, dim));
+    L.sbar_step = cv.take<double>(size_t(nseg) * K);
     L.loss_part = cv.take<double>(blocks_for(nd));
     L.acc = cv.take<double>(4);
     L.bytes = cv.off + 256;
@@ -170,17 +180,18 @@ tfsph_status unsort(int n, int dim, const int *src, R *const in[3], R *const out
     return TFSPH_OK;
 }
 
+// reverse of global step `step`, whose tapes are in slot `slot`
 template <typename R, int DIM>
-tfsph_status rev_step(const Geom<R> &G, const Phys<R> &Ph, AdjLayout<R> &L, int slot, hipStream_t st)
+tfsph_status rev_step(const Geom<R> &G, const Phys<R> &Ph, AdjLayout<R> &L, int slot, int step, hipStream_t st)
 {
     Sorted<R> &Sg = L.tg[slot], &Sd = L.td[slot];
     const int ng = Sg.n, nd = Sd.n;
-    const int nb = blocks_for(G.ncell);
-    hipLaunchKernelGGL((k_adj_cell<R, DIM>), dim3(nb), dim3(kBlock), 0, st, G, Ph, Sg, Sd, L.cur_g, L.cur_d, L.vtb_g,
-                       L.abar[0], L.abar[1], L.abar[2], L.ubi_d, L.sbar_part);
+    const int cpb = default_cells_per_block(DIM);
+    const int nb = adj_cell_blocks(G.ncell, DIM);
+    hipLaunchKernelGGL((k_adj_cell<R, DIM>), dim3(nb), dim3(kBlock), adj_cell_lds_bytes<R>(cpb), st, G, Ph, Sg, Sd,
+                       L.cur_g, L.cur_d, L.vtb_g, L.abar[0], L.abar[1], L.abar[2], L.ubi_d,
+                       L.sbar_part + size_t(step) * nb, cpb);
     LAUNCH_CHECK("adj_cell");
-    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(kBlock), 0, st, L.sbar_part, nb, 1.0, L.acc + 1, 1);
-    LAUNCH_CHECK("adj_reduce");
     if (ng > 0) {
         hipLaunchKernelGGL((k_adj_force<R, DIM>), dim3(blocks_for(ng)), dim3(kBlock), 0, st, G, Ph, Sg, L.abar[0],
                            L.abar[1], L.abar[2], L.cur_g, L.xacc_g[0], L.xacc_g[1], L.xacc_g[2], L.rhobar_g);
@@ -266,8 +277,14 @@ tfsph_status run_adjoint(const tfsph_params *p, const tfsph_state *s, int n_step
             TRY(copy_state<R>(L.ckpt[seg].d, L.W.d, DIM, st));
             for (int t = 0; t < len; ++t) TRY((fwd_step<R, DIM>(G, Ph, L, t, st)));
         }
-        for (int t = len - 1; t >= 0; --t) TRY((rev_step<R, DIM>(G, Ph, L, t, st)));
+        for (int t = len - 1; t >= 0; --t) TRY((rev_step<R, DIM>(G, Ph, L, t, first + t, st)));
     }
+    // d/dlog t_stop: every step's block partials, in a fixed order that does not depend on K
+    hipLaunchKernelGGL(k_adj_reduce_rows, dim3(n_steps), dim3(kBlock), 0, st, L.sbar_part,
+                       adj_cell_blocks(G.ncell, DIM), L.sbar_step);
+    LAUNCH_CHECK("adj_reduce_rows");
+    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(kBlock), 0, st, L.sbar_step, n_steps, 1.0, L.acc + 1, 1);
+    LAUNCH_CHECK("adj_reduce");
     // gradients by id
     if (ng > 0) {
         hipLaunchKernelGGL(k_adj_by_id<R>, dim3(blocks_for(ng)), dim3(kBlock), 0, st, ng, DIM, Ig.id, L.cur_g.v[0],

@@ -44,94 +44,183 @@ struct AdjPhase {
 };
 
 // ---------------------------------------------------------------------------
-// per-cell reverse of the implicit update and cell solve; one thread per cell
+// per-cell reverse of the implicit update and cell solve.  A block owns a run
+// of cells_per_block cells: its particles' records (m, v~ or u~, and the
+// incoming adjoint w = vbar + tau xbar) are staged in LDS with coalesced loads
+// (up to kAdjStage per phase, else read from global memory), one thread per
+// cell runs the serial cell sums and the reverse of the 2x2 solve, and the
+// per-particle outputs are written one thread per particle.
 // ---------------------------------------------------------------------------
+constexpr int kAdjStage = kBlock;
+
+template <typename R>
+struct AdjCellOut {
+    R ia, ib, rg, rd;       // 1/(1+alpha), 1/(1+beta), 1/M_g, 1/M_d
+    R Vtb[3], Utb[3];       // adjoints of the cell's mean predictor velocities
+    int both;               // the cell holds both phases (drag acts)
+};
+
+template <typename R>
+constexpr size_t adj_cell_lds_bytes(int cells_per_block)
+{
+    return sizeof(AdjCellOut<R>) * cells_per_block + 4 * sizeof(R4<R>) * kAdjStage;
+}
+
 template <typename R, int DIM>
 __global__ void __launch_bounds__(kBlock)
 k_adj_cell(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, AdjPhase<R> outg, AdjPhase<R> outd,
            AdjPhase<R> vtb_g /* v: v~bar (sorted) */, R *abar0, R *abar1, R *abar2, AdjPhase<R> ubi_d,
-           double *sbar_part)
+           double *sbar_part, int cells_per_block)
 {
+    extern __shared__ unsigned char smem_raw[];
+    R4<R> *gm = reinterpret_cast<R4<R> *>(smem_raw);      // [kAdjStage] gas: m, v~
+    R4<R> *gw = gm + kAdjStage;                             // [kAdjStage] gas: w
+    R4<R> *dm = gw + kAdjStage;                             // [kAdjStage] dust: m, u~
+    R4<R> *dw = dm + kAdjStage;                             // [kAdjStage] dust: z
+    AdjCellOut<R> *co = reinterpret_cast<AdjCellOut<R> *>(dw + kAdjStage);
+    __shared__ double red[kBlock];
     R *abar[3] = {abar0, abar1, abar2};
-    const int c = blockIdx.x * kBlock + threadIdx.x;
+    const R tau = Ph.tau;
+    const int c0 = blockIdx.x * cells_per_block;
+    const int c1 = min(c0 + cells_per_block, G.ncell);
+    const int ga = Sg.start[c0], gb = Sg.start[c1];
+    const int da = Sd.start[c0], db = Sd.start[c1];
+    const bool staged = gb - ga <= kAdjStage && db - da <= kAdjStage;
+
+    // w of gas particle a: the adjoint reaching its new velocity (through x^{n+1} = x + tau v too)
+    auto w_of = [&](int a, int d) { return outg.v[d][a] + tau * outg.x[d][a]; };
+    auto z_of = [&](int j, int d) { return outd.v[d][j] + tau * outd.x[d][j]; };
+    if (staged) {
+        for (int i = threadIdx.x; i < gb - ga; i += kBlock) {
+            const int a = ga + i;
+            gm[i] = mk4<R>(Sg.pos[a].w, Sg.vt[0][a], DIM > 1 ? Sg.vt[1][a] : R(0), DIM > 2 ? Sg.vt[2][a] : R(0));
+            gw[i] = mk4<R>(w_of(a, 0), DIM > 1 ? w_of(a, 1) : R(0), DIM > 2 ? w_of(a, 2) : R(0), R(0));
+        }
+        for (int i = threadIdx.x; i < db - da; i += kBlock) {
+            const int j = da + i;
+            dm[i] = mk4<R>(Sd.pos[j].w, Sd.vel[0][j], DIM > 1 ? Sd.vel[1][j] : R(0), DIM > 2 ? Sd.vel[2][j] : R(0));
+            dw[i] = mk4<R>(z_of(j, 0), DIM > 1 ? z_of(j, 1) : R(0), DIM > 2 ? z_of(j, 2) : R(0), R(0));
+        }
+    }
+    __syncthreads();
+    // per-particle reads, from LDS when staged
+    auto gas_m = [&](int a, R &m, R *v) {
+        if (staged) {
+            const R4<R> q = gm[a - ga];
+            m = q.x; v[0] = q.y; v[1] = q.z; v[2] = q.w;
+        } else {
+            m = Sg.pos[a].w;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) v[d] = Sg.vt[d][a];
+        }
+    };
+    auto dust_m = [&](int j, R &m, R *u) {
+        if (staged) {
+            const R4<R> q = dm[j - da];
+            m = q.x; u[0] = q.y; u[1] = q.z; u[2] = q.w;
+        } else {
+            m = Sd.pos[j].w;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) u[d] = Sd.vel[d][j];
+        }
+    };
+    auto gas_w = [&](int a, R *w) {
+        if (staged) {
+            const R4<R> q = gw[a - ga];
+            w[0] = q.x; w[1] = q.y; w[2] = q.z;
+        } else {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) w[d] = w_of(a, d);
+        }
+    };
+    auto dust_w = [&](int j, R *z) {
+        if (staged) {
+            const R4<R> q = dw[j - da];
+            z[0] = q.x; z[1] = q.y; z[2] = q.z;
+        } else {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) z[d] = z_of(j, d);
+        }
+    };
+
+    // (1) one thread per cell: sums, solve and its reverse
     double sbar = 0.0;
-    if (c < G.ncell) {
+    for (int c = c0 + threadIdx.x; c < c1; c += kBlock) {
         CellSums<R> S;
-        cell_sums<R, DIM>(Ph, Sg, Sd, c, S);
-        CellSolve<R> C;
-        solve_from_sums<R, DIM>(Ph, S, C);
         const int g0 = Sg.start[c], g1 = Sg.start[c + 1];
         const int d0 = Sd.start[c], d1 = Sd.start[c + 1];
-        const R tau = Ph.tau;
-        if (S.ng > 0 && S.nd > 0) {
+        cell_sums_with<R, DIM>(Ph, g0, g1, d0, d1, gas_m, dust_m, S);
+        CellSolve<R> C;
+        solve_from_sums<R, DIM>(Ph, S, C);
+        AdjCellOut<R> &o = co[c - c0];
+        o.both = S.ng > 0 && S.nd > 0;
+        if (o.both) {
             const R ia = R(1) / (R(1) + C.alpha), ib = R(1) / (R(1) + C.beta);
             R Ubar[3] = {R(0), R(0), R(0)}, Vbar[3] = {R(0), R(0), R(0)};
             R abar_c = R(0), bbar_c = R(0);
             for (int a = g0; a < g1; ++a) {
+                R m, vt[3], w[3];
+                gas_m(a, m, vt);
+                gas_w(a, w);
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) {
-                    const R w = outg.v[d][a] + tau * outg.x[d][a];
-                    const R vnew = (Sg.vt[d][a] + C.alpha * C.U[d]) * ia;
-                    Ubar[d] += w * C.alpha * ia;
-                    abar_c += w * (C.U[d] - vnew) * ia;
+                    const R vnew = (vt[d] + C.alpha * C.U[d]) * ia;
+                    Ubar[d] += w[d] * C.alpha * ia;
+                    abar_c += w[d] * (C.U[d] - vnew) * ia;
                 }
             }
             for (int j = d0; j < d1; ++j) {
+                R m, u[3], z[3];
+                dust_m(j, m, u);
+                dust_w(j, z);
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) {
-                    const R z = outd.v[d][j] + tau * outd.x[d][j];
-                    const R ut = Sd.vel[d][j] + tau * Ph.g[d];
+                    const R ut = u[d] + tau * Ph.g[d];
                     const R unew = (ut + C.beta * C.V[d]) * ib;
-                    Vbar[d] += z * C.beta * ib;
-                    bbar_c += z * (C.V[d] - unew) * ib;
+                    Vbar[d] += z[d] * C.beta * ib;
+                    bbar_c += z[d] * (C.V[d] - unew) * ib;
                 }
             }
             const R D = R(1) + C.alpha + C.beta;
-            R Vtb[3], Utb[3];
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
-                Vtb[d] = (Vbar[d] * (R(1) + C.beta) + Ubar[d] * C.beta) / D;
-                Utb[d] = (Vbar[d] * C.alpha + Ubar[d] * (R(1) + C.alpha)) / D;
+                o.Vtb[d] = (Vbar[d] * (R(1) + C.beta) + Ubar[d] * C.beta) / D;
+                o.Utb[d] = (Vbar[d] * C.alpha + Ubar[d] * (R(1) + C.alpha)) / D;
                 abar_c += (Vbar[d] * (S.Ut[d] - C.V[d]) + Ubar[d] * (S.Ut[d] - C.U[d])) / D;
                 bbar_c += (Vbar[d] * (S.Vt[d] - C.V[d]) + Ubar[d] * (S.Vt[d] - C.U[d])) / D;
             }
-            sbar = -double(C.alpha) * double(abar_c) - double(C.beta) * double(bbar_c);
-            const R rg = R(1) / S.Mg, rd = R(1) / S.Md;
-            for (int a = g0; a < g1; ++a) {
-                const R m = Sg.pos[a].w;
-#pragma unroll
-                for (int d = 0; d < DIM; ++d) {
-                    const R w = outg.v[d][a] + tau * outg.x[d][a];
-                    const R vb = w * ia + m * rg * Vtb[d];
-                    vtb_g.v[d][a] = vb;
-                    abar[d][a] = tau * vb;
-                }
-            }
-            for (int j = d0; j < d1; ++j) {
-                const R m = Sd.pos[j].w;
-#pragma unroll
-                for (int d = 0; d < DIM; ++d) {
-                    const R z = outd.v[d][j] + tau * outd.x[d][j];
-                    ubi_d.v[d][j] = z * ib + m * rd * Utb[d];
-                }
-            }
-        } else {
-            for (int a = g0; a < g1; ++a) {
-#pragma unroll
-                for (int d = 0; d < DIM; ++d) {
-                    const R w = outg.v[d][a] + tau * outg.x[d][a];
-                    vtb_g.v[d][a] = w;
-                    abar[d][a] = tau * w;
-                }
-            }
-            for (int j = d0; j < d1; ++j) {
-#pragma unroll
-                for (int d = 0; d < DIM; ++d) ubi_d.v[d][j] = outd.v[d][j] + tau * outd.x[d][j];
-            }
+            sbar += -double(C.alpha) * double(abar_c) - double(C.beta) * double(bbar_c);
+            o.ia = ia;
+            o.ib = ib;
+            o.rg = R(1) / S.Mg;
+            o.rd = R(1) / S.Md;
         }
     }
+    __syncthreads();
+
+    // (2) one thread per particle: the adjoints of v~ and u~
+    for (int a = ga + threadIdx.x; a < gb; a += kBlock) {
+        const AdjCellOut<R> &o = co[Sg.cell[a] - c0];
+        R m, vt[3], w[3];
+        gas_m(a, m, vt);
+        gas_w(a, w);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            const R vb = o.both ? w[d] * o.ia + m * o.rg * o.Vtb[d] : w[d];
+            vtb_g.v[d][a] = vb;
+            abar[d][a] = tau * vb;
+        }
+    }
+    for (int j = da + threadIdx.x; j < db; j += kBlock) {
+        const AdjCellOut<R> &o = co[Sd.cell[j] - c0];
+        R m, u[3], z[3];
+        dust_m(j, m, u);
+        dust_w(j, z);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) ubi_d.v[d][j] = o.both ? z[d] * o.ib + m * o.rd * o.Utb[d] : z[d];
+    }
+
     // block sum of d/d log t_stop in a fixed tree order
-    __shared__ double red[kBlock];
     red[threadIdx.x] = sbar;
     __syncthreads();
     for (int s = kBlock / 2; s > 0; s >>= 1) {
@@ -273,6 +362,22 @@ __global__ void __launch_bounds__(kBlock) k_adj_reduce(const double *part, int n
         __syncthreads();
     }
     if (threadIdx.x == 0) *acc = (accumulate ? *acc : 0.0) + scale * red[0];
+}
+
+// out[b] = sum of part[b n .. (b + 1) n) in a fixed order, one block per row b
+__global__ void __launch_bounds__(kBlock) k_adj_reduce_rows(const double *part, int n, double *out)
+{
+    __shared__ double red[kBlock];
+    const double *row = part + size_t(blockIdx.x) * n;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s += row[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = kBlock / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 // out[src[dst]] = in[dst] for each axis (undo one step's sort); also zero-fills nothing
