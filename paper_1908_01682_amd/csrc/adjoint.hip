@@ -235,6 +235,7 @@ tfsph_status run_adjoint(const tfsph_params *p, const tfsph_state *s, int n_step
     HIP_TRY(hipMemsetAsync(L.F.word, 0, 256, st));
     HIP_TRY(hipMemsetAsync(L.F.one_phase, 0, 64, st));
     TRY(fill_dev<double>(L.acc, 0.0, 4, st));
+    for (int t = 0; t <= K; ++t) TRY(enqueue_zero_counts<R>(G.ncell, L.tg[t], L.td[t], st));
     // forward sweep with checkpoints
     TRY(copy_state<R>(Ig, L.W.g, DIM, st));
     TRY(copy_state<R>(Id, L.W.d, DIM, st));

@@ -152,7 +152,9 @@ k_scan_top(int *partial, int ntiles, int *start_g, int *start_d, int ncell)
 // and k_scan_top is not launched
 constexpr int kScanInlineTiles = 4 * kBlock;
 
-// per-tile exclusive scan plus tile prefix -> start[].  With `inline_prefix`
+// per-tile exclusive scan plus tile prefix -> start[], and the counts reset to
+// zero (every count array is zero between binnings: cleared once when its
+// workspace is set up, then here).  With `inline_prefix`
 // the prefix is the sum of the raw tile totals of the tiles before this one
 // (and the last tile writes start[ncell]); otherwise k_scan_top has turned
 // partial[] into exclusive prefixes.
@@ -169,6 +171,8 @@ k_scan_down(const int *count_g, const int *count_d, int ncell, const int *partia
     for (int k = 0; k < kScanItems; ++k) {
         const int i = base + k * kBlock + threadIdx.x;
         tile[k * kBlock + threadIdx.x] = i < ncell ? count[i] : 0;
+        // the counts are consumed here: leave them zero for the next binning's claims
+        if (i < ncell) const_cast<int *>(count)[i] = 0;
     }
     int prefix = 0;
     if (inline_prefix) {

@@ -17,8 +17,18 @@ inline int default_cells_per_block(int dim) { return dim == 1 ? 128 : (dim == 2 
 // next to the staged particle records (under 64 KiB in FP64)
 constexpr int kMaxCellsPerBlock = 256;
 
-// zero + count + scan + scatter + rank/gather of both phases into the workspace
-// Counting sort of both phases into (cell, id) order.
+// zero the cell counts of a phase pair: once per workspace, before its first binning
+template <typename R>
+inline tfsph_status enqueue_zero_counts(int ncell, Sorted<R> &Sg, Sorted<R> &Sd, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(ncell)), dim3(kBlock), 0, st, Sg.count, ncell, Sd.count, ncell);
+    LAUNCH_CHECK("fill_zero");
+    return TFSPH_OK;
+}
+
+// count + scan + scatter + rank/gather of both phases into the workspace:
+// counting sort of both phases into (cell, id) order.  The counts must be zero
+// on entry (enqueue_zero_counts() once, then every binning leaves them zero).
 template <typename R>
 inline tfsph_status enqueue_bin(int ng, int nd, const Geom<R> &G, const Phase<R> &Pg, const Phase<R> &Pd,
                                 Sorted<R> &Sg, Sorted<R> &Sd, int *partial, const Flags &F, hipStream_t st)
@@ -26,8 +36,6 @@ inline tfsph_status enqueue_bin(int ng, int nd, const Geom<R> &G, const Phase<R>
     const int ncell = G.ncell;
     const int ntiles = ntiles_of(ncell);
     const int bg = blocks_for(ng), bd = blocks_for(nd);
-    hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(ncell)), dim3(kBlock), 0, st, Sg.count, ncell, Sd.count, ncell);
-    LAUNCH_CHECK("fill_zero");
     if (bg + bd > 0) {
         hipLaunchKernelGGL(k_count, dim3(bg + bd), dim3(kBlock), 0, st, Pg.cell, ng, Sg.count, Sg.slot, Pd.cell,
                            nd, Sd.count, Sd.slot, bg, ncell, F.word);

@@ -467,9 +467,17 @@ tfsph_status enqueue_init(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
     Sorted<R> Sg, Sd;
     int *partial;
     Flags F;
-    carve_all<R>(c, Sg, Sd, partial, F);
+    ImexViews<R> V;
+    const bool imex = c->p.scheme == TFSPH_SCHEME_IMEX2;
+    carve_all<R>(c, Sg, Sd, partial, F, imex ? &V : nullptr);
     HIP_TRY(hipMemsetAsync(F.word, 0, 256, st));
     HIP_TRY(hipMemsetAsync(F.one_phase, 0, 64, st));
+    tfsph_status z = enqueue_zero_counts<R>(G.ncell, Sg, Sd, st);
+    if (z != TFSPH_OK) return z;
+    if (imex) {
+        z = enqueue_zero_counts<R>(G.ncell, V.Sg, V.Sd, st);
+        if (z != TFSPH_OK) return z;
+    }
     if (c->ng > 0) {
         hipLaunchKernelGGL(k_canonicalize<R>, dim3(blocks_for(c->ng)), dim3(kBlock), 0, st, G, Pg, F);
         LAUNCH_CHECK("canonicalize");
