@@ -259,9 +259,10 @@ k_imex_relax(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Stage<R> Xg, Sta
         const int i = Sg.src[a];
         const R4<R> me = Sg.pos[a];
         const R oo[3] = {me.x, me.y, me.z};
+        const R4<R> sv = staged ? stg[a - ga] : R4<R>{};      // (m, v~) from LDS when staged
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            const R vt = Sg.vel[d][a];
+            const R vt = staged ? (d == 0 ? sv.y : d == 1 ? sv.z : sv.w) : Sg.vel[d][a];
             const R v = (vt + Cs.alpha * Cs.U[d]) * inv;
             bad |= !finite_r(v);
             if constexpr (FINAL) {
@@ -287,9 +288,10 @@ k_imex_relax(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Stage<R> Xg, Sta
         const int i = Sd.src[j];
         const R4<R> me = Sd.pos[j];
         const R oo[3] = {me.x, me.y, me.z};
+        const R4<R> su = staged ? std_[j - da] : R4<R>{};     // (m, u~) from LDS when staged
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            const R ut = Sd.vel[d][j];
+            const R ut = staged ? (d == 0 ? su.y : d == 1 ? su.z : su.w) : Sd.vel[d][j];
             const R u = (ut + Cs.beta * Cs.V[d]) * inv;
             bad |= !finite_r(u);
             if constexpr (FINAL) {

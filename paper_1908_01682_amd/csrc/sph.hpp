@@ -658,7 +658,8 @@ __device__ __forceinline__ void gas_predict(const Geom<R> &G, const Phys<R> &Ph,
 // x^{n+1} = x^n + tau v^{n+1} and the carry; writes the caller's arrays at a.
 template <typename R, int DIM>
 __device__ __forceinline__ bool gas_finish(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg,
-                                           const Phase<R> &Pg, int a, const CellSolve<R> &C)
+                                           const Phase<R> &Pg, int a, const CellSolve<R> &C,
+                                           const R4<R> *staged = nullptr)
 {
     const int c = Sg.cell[a];
     const R inv = R(1) / (R(1) + C.alpha);
@@ -667,9 +668,19 @@ __device__ __forceinline__ bool gas_finish(const Geom<R> &G, const Phys<R> &Ph, 
     const R4<R> me = Sg.pos[a];
     const R oo[3] = {me.x, me.y, me.z};
     bool ok = true;
+    // v~ from the block's LDS copy when it has one: (m, v~x, v~y, v~z)
+    R vt[3];
+    if (staged) {
+        vt[0] = staged->y;
+        vt[1] = staged->z;
+        vt[2] = staged->w;
+    } else {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) vt[d] = Sg.vt[d][a];
+    }
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        const R v = (Sg.vt[d][a] + C.alpha * C.U[d]) * inv;
+        const R v = (vt[d] + C.alpha * C.U[d]) * inv;
         R o = oo[d] + Ph.tau * v;
         ok &= finite_r(v);
         ok &= carry(o, cc[d], G.delta[d], G.nc[d]);
@@ -686,7 +697,8 @@ __device__ __forceinline__ bool gas_finish(const Geom<R> &G, const Phys<R> &Ph, 
 // Implicit update of eq. (20) for dust particle j of cell C, then move + carry.
 template <typename R, int DIM>
 __device__ __forceinline__ bool dust_finish(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sd,
-                                            const Phase<R> &Pd, int j, const CellSolve<R> &C)
+                                            const Phase<R> &Pd, int j, const CellSolve<R> &C,
+                                            const R4<R> *staged = nullptr)
 {
     const int c = Sd.cell[j];
     const R inv = R(1) / (R(1) + C.beta);
@@ -695,9 +707,19 @@ __device__ __forceinline__ bool dust_finish(const Geom<R> &G, const Phys<R> &Ph,
     const R4<R> me = Sd.pos[j];
     const R oo[3] = {me.x, me.y, me.z};
     bool ok = true;
+    // u from the block's LDS copy when it has one: (m, ux, uy, uz)
+    R uu[3];
+    if (staged) {
+        uu[0] = staged->y;
+        uu[1] = staged->z;
+        uu[2] = staged->w;
+    } else {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) uu[d] = Sd.vel[d][j];
+    }
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        const R ut = Sd.vel[d][j] + Ph.tau * Ph.g[d];
+        const R ut = uu[d] + Ph.tau * Ph.g[d];
         const R u = (ut + C.beta * C.V[d]) * inv;
         R o = oo[d] + Ph.tau * u;
         ok &= finite_r(u);
@@ -799,9 +821,9 @@ k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R
     // (2) implicit particle update (eqs. 19-20), position update, carry
     int bad = 0;
     for (int a = ga + threadIdx.x; a < gb; a += kBlock)
-        bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0]);
+        bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0], staged ? &stg[a - ga] : nullptr);
     for (int j = da + threadIdx.x; j < db; j += kBlock)
-        bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[Sd.cell[j] - c0]);
+        bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[Sd.cell[j] - c0], staged ? &std_[j - da] : nullptr);
     if (bad) atomicOr(&s_bad, 1);
     __syncthreads();
     if (threadIdx.x == 0) {
