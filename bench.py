@@ -5,7 +5,8 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload box3d|shock1d|wa
 Prints ONE JSON line: gas+dust particle-steps/s of whole IDIC steps
 (bin -> density -> force + predictor -> cell solve + update) with inputs
 resident in HBM; the roofline of the dominant kernel (its launches timed with
-HIP events on the stream they run on; the pair kernels are bound by vector
+HIP events on the stream they run on, one kernel kind per step in turn, inside
+the timed steps; the pair kernels are bound by vector
 ALU work, priced in algorithmic flops against the FP32 vector peak, the update
 kernel by HBM bytes); the whole step's algorithmic HBM bytes against the HBM
 peak; and the FP64 CPU oracle timed on the host cores on a bounded sample of
@@ -306,7 +307,9 @@ def main(argv=None):
     torch.cuda.synchronize()
     print(f"[bench] warmup done, timing {a.steps} steps", file=sys.stderr, flush=True)
 
-    T.tfsph_profile(sim.ctx, True)
+    # HIP events around one kernel kind per step, the kinds in turn (every kind is timed in a
+    # quarter of the steps), so that fewer events sit between the timed launches
+    T.tfsph_profile(sim.ctx, True, rotate=a.steps >= 4)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(a.steps)

@@ -309,7 +309,11 @@ tfsph_status tfsph_set_cells_per_block(tfsph_ctx *ctx, int32_t cells);
 /* Kernel timing for measurement.  tfsph_profile(ctx, 1) starts recording a
  * HIP event pair around every launch of the timed kernels on the stream the
  * launch uses (it creates the events on the host; nothing is allocated on the
- * device); tfsph_profile(ctx, 0) stops and keeps what was recorded.
+ * device); tfsph_profile(ctx, 2) does the same for one kernel kind per step,
+ * the kinds taken in turn (step i times kind i mod 4, counted from the call),
+ * so that the events perturb the steps they bracket less;
+ * tfsph_profile(ctx, 0) stops and keeps what was recorded.  Steps replayed
+ * from a graph are not timed.  Another mode returns TFSPH_E_INVALID_ARG.
  * tfsph_profile_read() synchronises, then returns the summed duration in ms
  * and the number of launches of one kernel:
  *   TFSPH_KERNEL_UPDATE  (cell sums + implicit solve + particle update; with

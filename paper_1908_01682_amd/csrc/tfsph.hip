@@ -192,6 +192,9 @@ struct StepGraph {
 struct tfsph_ctx {
     tfsph_params p;
     bool profiling = false;
+    bool prof_rotate = false;   // time one kernel kind per step, in turn
+    int prof_kind = 0;          // the kind timed in the current step (rotating mode)
+    long long prof_steps = 0;   // steps dispatched since profiling was enabled
     KernelTimer timers[4];
     StepGraph sg;
     hipStream_t capture_stream = nullptr;
@@ -208,7 +211,7 @@ struct tfsph_ctx {
 // record one event of a (start, stop) pair for kernel kind k when profiling
 static tfsph_status timer_mark(tfsph_ctx *c, int k, hipStream_t st)
 {
-    if (!c->profiling) return TFSPH_OK;
+    if (!c->profiling || (c->prof_rotate && k != c->prof_kind)) return TFSPH_OK;
     KernelTimer &T = c->timers[k];
     if (T.used == T.ev.size()) {
         hipEvent_t e;
@@ -531,6 +534,7 @@ template <typename R>
 tfsph_status dispatch_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
 {
     const bool imex = c->p.scheme == TFSPH_SCHEME_IMEX2;
+    if (c->profiling) c->prof_kind = int(c->prof_steps++ % 4);
     switch (c->p.dim) {
     case 1: return imex ? enqueue_step_imex<R, 1>(c, s, st) : enqueue_step<R, 1>(c, s, st);
     case 2: return imex ? enqueue_step_imex<R, 2>(c, s, st) : enqueue_step<R, 2>(c, s, st);
@@ -676,10 +680,13 @@ extern "C" tfsph_status tfsph_set_kernel_variant(tfsph_ctx *c, int32_t variant)
 extern "C" tfsph_status tfsph_profile(tfsph_ctx *c, int32_t enable)
 {
     if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
+    if (enable < 0 || enable > 2) return fail(TFSPH_E_INVALID_ARG, "profile mode %d outside 0..2", enable);
     if (enable) {
         for (auto &T : c->timers) T.used = 0;
+        c->prof_steps = 0;
     }
     c->profiling = enable != 0;
+    c->prof_rotate = enable == 2;
     return TFSPH_OK;
 }
 

@@ -208,8 +208,10 @@ def tfsph_set_cells_per_block(ctx, cells: int) -> None:
     _check(lib().tfsph_set_cells_per_block(ctx, int(cells)), "tfsph_set_cells_per_block")
 
 
-def tfsph_profile(ctx, enable: bool) -> None:
-    _check(lib().tfsph_profile(ctx, 1 if enable else 0), "tfsph_profile")
+def tfsph_profile(ctx, enable, rotate: bool = False) -> None:
+    """Start (enable true) or stop kernel timing; with rotate, one kernel kind is timed per step."""
+    mode = 0 if not enable else (2 if rotate else 1)
+    _check(lib().tfsph_profile(ctx, mode), "tfsph_profile")
 
 
 def tfsph_profile_read(ctx, kernel: int):

@@ -461,6 +461,37 @@ def test_both_phases_empty():
     assert flags == 0 and one == 0
 
 
+@pytest.mark.parametrize("scheme,density_per_step", [(0, 1), (1, 2)], ids=["first_order", "imex"])
+def test_profile_modes_count_launches(scheme, density_per_step):
+    """Kernel timing: mode 1 brackets every launch, mode 2 one kernel kind per step in turn (8 steps:
+    each kind in 2 of them); the timing changes no bits of the state; graph replays are not timed;
+    another mode is rejected."""
+    prob = I.dusty_box(n_side=16, cells_per_axis=8, regions_per_axis=2)
+    prob.params = prob.params.replace(scheme=scheme)
+    ref, sim = _sim(prob, 0), _sim(prob, 0)
+    ref.step(24)
+    L = T.lib()
+    for mode, steps_per_kind in ((1, 8), (2, 2)):
+        T.tfsph_profile(sim.ctx, True, rotate=mode == 2)
+        sim.step(8)
+        T.tfsph_profile(sim.ctx, False)
+        ms, n = T.tfsph_profile_read(sim.ctx, T.TFSPH_KERNEL_DENSITY)
+        assert n == steps_per_kind * density_per_step and ms > 0.0, (mode, n, ms)
+        for kind in (T.TFSPH_KERNEL_UPDATE, T.TFSPH_KERNEL_BIN, T.TFSPH_KERNEL_FORCE):
+            assert T.tfsph_profile_read(sim.ctx, kind)[1] > 0
+    T.tfsph_profile(sim.ctx, True)
+    sim.step_graph(8, chunk=4)
+    T.tfsph_profile(sim.ctx, False)
+    assert T.tfsph_profile_read(sim.ctx, T.TFSPH_KERNEL_DENSITY)[1] == 0
+    assert L.tfsph_profile(sim.ctx, 3) == -1
+    torch.cuda.synchronize()
+    a, b = ref.gas.numpy(), sim.gas.numpy()
+    for k in ("cell", "id", "off", "vel", "rho"):
+        assert np.array_equal(a[k], b[k]), k
+    ref.close()
+    sim.close()
+
+
 def test_large_box_one_step(orc):
     """A 3D box eight times the benchmark's: 256^3 + 256^3 particles (33.5M), 128^3 cells, the
     default kernels; one step against the oracle."""
