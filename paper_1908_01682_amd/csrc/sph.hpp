@@ -253,7 +253,11 @@ __device__ __forceinline__ void for_window_recording(const Geom<R> &G, int cx, i
 // pair; fn(b, q, rx, ry, rz, valid) as for for_window().  Neighbours are taken
 // kWalk at a time; a lane with fewer left repeats its last one with valid =
 // false.  A set bit p is decoded by the segment (row t, cell k) it falls in:
-// segment s = t (2 WX + 1) + k starts at walking position P[s].
+// segment s = t (2 WX + 1) + k starts at walking position P[s]; the row is
+// the second one when p >= P[2 WX + 1], the cell the last one of that row
+// whose segment starts at or before p.  When no lane's window wraps around
+// the box along x, the cells of every row are consecutive in the sorted
+// order, so one index shift serves the whole row.
 template <typename R, int DIM, typename Fn>
 __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
                                                const int *__restrict__ start, const R4<R> *__restrict__ data,
@@ -266,6 +270,7 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
         R rx0[NC];
 #pragma unroll
         for (int k = 0; k < NC; ++k) rx0[k] = oa[0] - R(k - WX) * G.delta[0];
+        const bool wave_rows_contiguous = __ballot(cx < WX || cx + WX >= G.nc[0]) == 0ull;
         for_window_pairs<R, DIM, WX>(G, cx, cy, cz, oa, start, [&](int i, auto &bs, auto &be, const R *ry0,
                                                                     const R *rz0) {
             // first walking position of each segment and its index shift
@@ -285,47 +290,52 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
                     for (int k = 0; k < NC; ++k) visit_range<R, DIM>(bs[t][k], be[t][k], data, rx0[k], ry0[t], rz0[t], fn);
                 return;
             }
-            unsigned long long m = mask[size_t(i) * stride];
-            int p = 0;
-            while (m) {
-                int b[kWalk];
-                R x0[kWalk], y0[kWalk], z0[kWalk];
-                bool ok[kWalk];
+            const unsigned long long m0 = mask[size_t(i) * stride];
+            auto walk = [&](auto RowRuns) {
+                constexpr bool kRowRuns = decltype(RowRuns)::value != 0;
+                unsigned long long m = m0;
+                int p = 0;
+                while (m) {
+                    int b[kWalk];
+                    R x0[kWalk], y0[kWalk], z0[kWalk];
+                    bool ok[kWalk];
 #pragma unroll
-                for (int j = 0; j < kWalk; ++j) {
-                    ok[j] = m != 0;
-                    // m | bit 63 keeps the count defined when m is empty
-                    const int pj = __builtin_ctzll(m | (1ull << 63));
-                    p = ok[j] ? pj : p;
-                    m &= m - 1;
-                    int sh = shift[0];
-                    R xx = rx0[0], yy = ry0[0], zz = rz0[0];
+                    for (int j = 0; j < kWalk; ++j) {
+                        ok[j] = m != 0;
+                        // m | bit 63 keeps the count defined when m is empty
+                        const int pj = __builtin_ctzll(m | (1ull << 63));
+                        p = ok[j] ? pj : p;
+                        m &= m - 1;
+                        const bool t1 = p >= P[NC];
+                        int sh = t1 ? shift[NC] : shift[0];
+                        R xx = rx0[0];
 #pragma unroll
-                    for (int s = 1; s < NS; ++s) {
-                        const bool ge = p >= P[s];
-                        sh = ge ? shift[s] : sh;
-                        xx = ge ? rx0[s % NC] : xx;
-                        if (s == NC) {
-                            if (DIM > 1) yy = ge ? ry0[1] : yy;
-                            if (DIM > 2) zz = ge ? rz0[1] : zz;
+                        for (int k = 1; k < NC; ++k) {
+                            const bool ge = p >= (t1 ? P[NC + k] : P[k]);
+                            if constexpr (!kRowRuns) sh = ge ? (t1 ? shift[NC + k] : shift[k]) : sh;
+                            xx = ge ? rx0[k] : xx;
                         }
+                        b[j] = p + sh;
+                        x0[j] = xx;
+                        y0[j] = DIM > 1 ? (t1 ? ry0[1] : ry0[0]) : ry0[0];
+                        z0[j] = DIM > 2 ? (t1 ? rz0[1] : rz0[0]) : rz0[0];
                     }
-                    b[j] = p + sh;
-                    x0[j] = xx;
-                    y0[j] = yy;
-                    z0[j] = zz;
-                }
-                R4<R> q[kWalk];
+                    R4<R> q[kWalk];
 #pragma unroll
-                for (int j = 0; j < kWalk; ++j) q[j] = data[b[j]];
+                    for (int j = 0; j < kWalk; ++j) q[j] = data[b[j]];
 #pragma unroll
-                for (int j = 0; j < kWalk; ++j) {
-                    const R rx = x0[j] - q[j].x;
-                    const R ry = DIM > 1 ? y0[j] - q[j].y : R(0);
-                    const R rz = DIM > 2 ? z0[j] - q[j].z : R(0);
-                    fn(b[j], q[j], rx, ry, rz, ok[j]);
+                    for (int j = 0; j < kWalk; ++j) {
+                        const R rx = x0[j] - q[j].x;
+                        const R ry = DIM > 1 ? y0[j] - q[j].y : R(0);
+                        const R rz = DIM > 2 ? z0[j] - q[j].z : R(0);
+                        fn(b[j], q[j], rx, ry, rz, ok[j]);
+                    }
                 }
-            }
+            };
+            if (wave_rows_contiguous)
+                walk(IntC<1>{});
+            else
+                walk(IntC<0>{});
         });
     });
 }
