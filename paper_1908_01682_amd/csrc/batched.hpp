@@ -75,7 +75,7 @@ __device__ __forceinline__ void block_scan_cells(const int *count, int *start, i
 // known there); `first` does the counting from scratch for the first step of
 // a launch, since the state may have been written outside this kernel.
 template <typename R, int DIM>
-__device__ void batched_step(const Inst<R> &I, int *lds, unsigned int *flags, int &bad, int &one, bool first)
+__device__ __forceinline__ void batched_step(const Inst<R> &I, int *lds, unsigned int *flags, int &bad, int &one, bool first)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     const Geom<R> &G = I.G;
