@@ -358,6 +358,14 @@ def test_full_size_one_step(orc, name):
     assert not (flags & T.TFSPH_FLAG_NONFINITE)
 
 
+def test_full_size_box_five_steps(orc):
+    """The benchmark's 3D box (128^3 + 128^3 particles, 64^3 cells) over five steps of one call,
+    as the benchmark runs them: the whole state against the oracle, 1e-5 per step."""
+    err, flags = _step_parity(orc, I.workload("box3d"), 0, 5)
+    assert all(v <= 5 * TOL32 for v in err.values()), err
+    assert not (flags & T.TFSPH_FLAG_NONFINITE)
+
+
 @pytest.mark.parametrize("name,make,precision", [
     ("box3d_bricks", lambda: I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4), 0),
     ("box3d_ragged_bricks", lambda: I.dusty_box(n_side=26, cells_per_axis=13, regions_per_axis=1), 0),
