@@ -276,6 +276,9 @@ def main(argv=None):
                     help="time step timed: the paper's first-order step (default) or the second-order IMEX step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times (reference for HBM byte counters)")
+    ap.add_argument("--only", choices=("adjoint", "batched"),
+                    help="run only that extra measurement and print its record as the JSON line "
+                         "(for profiling it on its own; not the benchmark line)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); this build has no multi-GPU path.",
@@ -287,6 +290,12 @@ def main(argv=None):
         return 2
     from paper_1908_01682_amd import inputs as I
     from paper_1908_01682_amd import tfsph as T
+
+    if a.only:
+        run = adjoint_ratio if a.only == "adjoint" else batched_throughput
+        print(f"[bench] {a.only} only", file=sys.stderr, flush=True)
+        print(json.dumps({"only": a.only, **run(I, T, torch)}), flush=True)
+        return 0
 
     if a.copy_calibration:
         src = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda")
