@@ -5,8 +5,8 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload box3d|shock1d|wa
 Prints ONE JSON line: gas+dust particle-steps/s of whole IDIC steps
 (bin -> density -> force + predictor -> cell solve + update) with inputs
 resident in HBM; the roofline of the dominant kernel (its launches timed with
-HIP events on the stream they run on, one kernel kind per step in turn, inside
-the timed steps; the pair kernels are bound by vector
+HIP events on the stream they run on, one kernel kind in every few steps, the
+kinds in turn, inside the timed steps; the pair kernels are bound by vector
 ALU work, priced in algorithmic flops against the FP32 vector peak, the update
 kernel by HBM bytes); the whole step's algorithmic HBM bytes against the HBM
 peak; and the FP64 CPU oracle timed on the host cores on a bounded sample of
@@ -267,7 +267,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed steps first: the first few hundred steps after start-up run slower")
     ap.add_argument("--workload", default="box3d", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -316,9 +317,10 @@ def main(argv=None):
     torch.cuda.synchronize()
     print(f"[bench] warmup done, timing {a.steps} steps", file=sys.stderr, flush=True)
 
-    # HIP events around one kernel kind per step, the kinds in turn (every kind is timed in a
-    # quarter of the steps), so that fewer events sit between the timed launches
-    T.tfsph_profile(sim.ctx, True, rotate=a.steps >= 4)
+    # HIP events around one kernel kind in every `every`-th step, the kinds in turn, so that few
+    # events sit between the timed launches; each kind still gets about 12 timed steps of 200
+    every = max(1, a.steps // 48)
+    T.tfsph_profile(sim.ctx, True, rotate=a.steps >= 4, every=every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(a.steps)

@@ -312,6 +312,9 @@ tfsph_status tfsph_set_cells_per_block(tfsph_ctx *ctx, int32_t cells);
  * device); tfsph_profile(ctx, 2) does the same for one kernel kind per step,
  * the kinds taken in turn (step i times kind i mod 4, counted from the call),
  * so that the events perturb the steps they bracket less;
+ * tfsph_profile_sampled(ctx, every) does the same in every `every`-th step
+ * only (step i is timed when i mod every = 0, kind (i / every) mod 4; every
+ * >= 1, else TFSPH_E_INVALID_ARG);
  * tfsph_profile(ctx, 0) stops and keeps what was recorded.  Steps replayed
  * from a graph are not timed.  Another mode returns TFSPH_E_INVALID_ARG.
  * tfsph_profile_read() synchronises, then returns the summed duration in ms
@@ -324,6 +327,7 @@ tfsph_status tfsph_set_cells_per_block(tfsph_ctx *ctx, int32_t cells);
  * Returns TFSPH_E_INVALID_ARG for another kernel id. */
 enum { TFSPH_KERNEL_UPDATE = 0, TFSPH_KERNEL_DENSITY = 1, TFSPH_KERNEL_BIN = 2, TFSPH_KERNEL_FORCE = 3 };
 tfsph_status tfsph_profile(tfsph_ctx *ctx, int32_t enable);
+tfsph_status tfsph_profile_sampled(tfsph_ctx *ctx, int32_t every);
 tfsph_status tfsph_profile_read(tfsph_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 
 /* Convert n absolute FP64 positions x (device, layout [dim][n], inside or

@@ -192,8 +192,9 @@ struct StepGraph {
 struct tfsph_ctx {
     tfsph_params p;
     bool profiling = false;
-    bool prof_rotate = false;   // time one kernel kind per step, in turn
-    int prof_kind = 0;          // the kind timed in the current step (rotating mode)
+    bool prof_rotate = false;   // time one kernel kind per sampled step, in turn
+    int prof_every = 1;         // rotating mode: every prof_every-th step is sampled
+    int prof_kind = 0;          // the kind timed in the current step (-1: none)
     long long prof_steps = 0;   // steps dispatched since profiling was enabled
     KernelTimer timers[4];
     StepGraph sg;
@@ -534,7 +535,10 @@ template <typename R>
 tfsph_status dispatch_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
 {
     const bool imex = c->p.scheme == TFSPH_SCHEME_IMEX2;
-    if (c->profiling) c->prof_kind = int(c->prof_steps++ % 4);
+    if (c->profiling) {
+        const long long i = c->prof_steps++;
+        c->prof_kind = i % c->prof_every == 0 ? int((i / c->prof_every) % 4) : -1;
+    }
     switch (c->p.dim) {
     case 1: return imex ? enqueue_step_imex<R, 1>(c, s, st) : enqueue_step<R, 1>(c, s, st);
     case 2: return imex ? enqueue_step_imex<R, 2>(c, s, st) : enqueue_step<R, 2>(c, s, st);
@@ -677,17 +681,30 @@ extern "C" tfsph_status tfsph_set_kernel_variant(tfsph_ctx *c, int32_t variant)
     return TFSPH_OK;
 }
 
+static tfsph_status start_profile(tfsph_ctx *c, bool on, bool rotate, int every)
+{
+    if (on) {
+        for (auto &T : c->timers) T.used = 0;
+        c->prof_steps = 0;
+    }
+    c->profiling = on;
+    c->prof_rotate = rotate;
+    c->prof_every = every;
+    return TFSPH_OK;
+}
+
 extern "C" tfsph_status tfsph_profile(tfsph_ctx *c, int32_t enable)
 {
     if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
     if (enable < 0 || enable > 2) return fail(TFSPH_E_INVALID_ARG, "profile mode %d outside 0..2", enable);
-    if (enable) {
-        for (auto &T : c->timers) T.used = 0;
-        c->prof_steps = 0;
-    }
-    c->profiling = enable != 0;
-    c->prof_rotate = enable == 2;
-    return TFSPH_OK;
+    return start_profile(c, enable != 0, enable == 2, 1);
+}
+
+extern "C" tfsph_status tfsph_profile_sampled(tfsph_ctx *c, int32_t every)
+{
+    if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
+    if (every < 1) return fail(TFSPH_E_INVALID_ARG, "sampling interval %d below 1", every);
+    return start_profile(c, true, true, every);
 }
 
 extern "C" tfsph_status tfsph_profile_read(tfsph_ctx *c, int32_t kernel, double *total_ms, int64_t *launches)

@@ -90,6 +90,7 @@ def lib():
         L.tfsph_positions_to_cells.argtypes = [P, ctypes.c_int64, vp, vp, ctypes.c_void_p * 3, vp]
         L.tfsph_cells_to_positions.argtypes = [P, ctypes.c_int64, vp, ctypes.c_void_p * 3, vp, vp]
         L.tfsph_profile.argtypes = [vp, ctypes.c_int32]
+        L.tfsph_profile_sampled.argtypes = [vp, ctypes.c_int32]
         L.tfsph_set_kernel_variant.argtypes = [vp, ctypes.c_int32]
         L.tfsph_set_cells_per_block.argtypes = [vp, ctypes.c_int32]
         L.tfsph_profile_read.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -109,7 +110,7 @@ def lib():
                                          ctypes.c_void_p * 3, vp, vp, vp, ctypes.c_size_t, vp]
         for name in ("tfsph_validate", "tfsph_workspace_size", "tfsph_init", "tfsph_step", "tfsph_density",
                      "tfsph_get_flags", "tfsph_destroy", "tfsph_positions_to_cells", "tfsph_cells_to_positions",
-                     "tfsph_profile", "tfsph_profile_read", "tfsph_set_kernel_variant", "tfsph_set_cells_per_block", "tfsph_step_graph", "tfsph_batch_workspace_size",
+                     "tfsph_profile", "tfsph_profile_sampled", "tfsph_profile_read", "tfsph_set_kernel_variant", "tfsph_set_cells_per_block", "tfsph_step_graph", "tfsph_batch_workspace_size",
                      "tfsph_batch_init", "tfsph_batch_set_tuning", "tfsph_step_batched", "tfsph_step_batched_graph",
                      "tfsph_batch_get_flags", "tfsph_batch_destroy", "tfsph_adjoint_workspace_size",
                      "tfsph_step_adjoint"):
@@ -208,8 +209,12 @@ def tfsph_set_cells_per_block(ctx, cells: int) -> None:
     _check(lib().tfsph_set_cells_per_block(ctx, int(cells)), "tfsph_set_cells_per_block")
 
 
-def tfsph_profile(ctx, enable, rotate: bool = False) -> None:
-    """Start (enable true) or stop kernel timing; with rotate, one kernel kind is timed per step."""
+def tfsph_profile(ctx, enable, rotate: bool = False, every: int = 1) -> None:
+    """Start (enable true) or stop kernel timing; with rotate, one kernel kind is timed in every
+    `every`-th step, the kinds in turn."""
+    if enable and rotate and every != 1:
+        _check(lib().tfsph_profile_sampled(ctx, int(every)), "tfsph_profile_sampled")
+        return
     mode = 0 if not enable else (2 if rotate else 1)
     _check(lib().tfsph_profile(ctx, mode), "tfsph_profile")
 

@@ -126,6 +126,7 @@ def test_tuning_calls_reject_null_context(lib):
     assert L.tfsph_set_kernel_variant(None, 0) == -1
     assert L.tfsph_set_cells_per_block(None, 32) == -1
     assert L.tfsph_profile(None, 1) == -1
+    assert L.tfsph_profile_sampled(None, 4) == -1
 
 
 def test_workspace_holds_neighbour_masks(lib):

@@ -472,19 +472,19 @@ def test_both_phases_empty():
 @pytest.mark.parametrize("scheme,density_per_step", [(0, 1), (1, 2)], ids=["first_order", "imex"])
 def test_profile_modes_count_launches(scheme, density_per_step):
     """Kernel timing: mode 1 brackets every launch, mode 2 one kernel kind per step in turn (8 steps:
-    each kind in 2 of them); the timing changes no bits of the state; graph replays are not timed;
-    another mode is rejected."""
+    each kind in 2 of them), the sampled mode one kind in every second step (each kind in 1); the
+    timing changes no bits of the state; graph replays are not timed; other modes are rejected."""
     prob = I.dusty_box(n_side=16, cells_per_axis=8, regions_per_axis=2)
     prob.params = prob.params.replace(scheme=scheme)
     ref, sim = _sim(prob, 0), _sim(prob, 0)
-    ref.step(24)
+    ref.step(32)
     L = T.lib()
-    for mode, steps_per_kind in ((1, 8), (2, 2)):
-        T.tfsph_profile(sim.ctx, True, rotate=mode == 2)
+    for mode, every, steps_per_kind in ((1, 1, 8), (2, 1, 2), (2, 2, 1)):
+        T.tfsph_profile(sim.ctx, True, rotate=mode == 2, every=every)
         sim.step(8)
         T.tfsph_profile(sim.ctx, False)
         ms, n = T.tfsph_profile_read(sim.ctx, T.TFSPH_KERNEL_DENSITY)
-        assert n == steps_per_kind * density_per_step and ms > 0.0, (mode, n, ms)
+        assert n == steps_per_kind * density_per_step and ms > 0.0, (mode, every, n, ms)
         for kind in (T.TFSPH_KERNEL_UPDATE, T.TFSPH_KERNEL_BIN, T.TFSPH_KERNEL_FORCE):
             assert T.tfsph_profile_read(sim.ctx, kind)[1] > 0
     T.tfsph_profile(sim.ctx, True)
@@ -492,6 +492,7 @@ def test_profile_modes_count_launches(scheme, density_per_step):
     T.tfsph_profile(sim.ctx, False)
     assert T.tfsph_profile_read(sim.ctx, T.TFSPH_KERNEL_DENSITY)[1] == 0
     assert L.tfsph_profile(sim.ctx, 3) == -1
+    assert L.tfsph_profile_sampled(sim.ctx, 0) == -1
     torch.cuda.synchronize()
     a, b = ref.gas.numpy(), sim.gas.numpy()
     for k in ("cell", "id", "off", "vel", "rho"):
