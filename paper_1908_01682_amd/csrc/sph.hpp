@@ -769,7 +769,7 @@ constexpr size_t update_lds_bytes(int cells_per_block)
 // The block first copies mass and velocity of its particles into LDS with
 // coalesced loads, so the serial per-cell sums read LDS.
 template <typename R, int DIM>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1)))
 k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R> Pd, Flags F, int cells_per_block,
          int nblocks)
 {
