@@ -46,11 +46,17 @@ __device__ __forceinline__ R spline_df(R q)
     return R(3) * (t1 * t1 - s * s);
 }
 
-// Tuning knobs, fixed at compile time: candidates loaded together before any
-// is used (window scans), neighbours taken together by the mask walk, and an
-// optional waves-per-SIMD floor for the pair kernels.
+// Tuning knobs, fixed at compile time: records loaded together before any is
+// used (cell sums, id ranking), candidates loaded together by the window
+// scans of the pair kernels, neighbours taken together by the mask walk, and
+// an optional waves-per-SIMD floor for the pair kernels.
 #ifndef TFSPH_CHUNK
 #define TFSPH_CHUNK 4
+#endif
+// Two candidates per load in the window scans: the 3D density pass takes
+// 0.347 ms against 0.370 with four (fewer registers held by loads in flight).
+#ifndef TFSPH_SCAN_CHUNK
+#define TFSPH_SCAN_CHUNK 2
 #endif
 #ifndef TFSPH_WALK
 #define TFSPH_WALK 2
@@ -67,8 +73,10 @@ __device__ __forceinline__ R spline_df(R q)
     __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && (KIND) != 2) ? 6 : 1)))
 #endif
 constexpr int kChunk = TFSPH_CHUNK;
+constexpr int kScanChunk = TFSPH_SCAN_CHUNK;
 constexpr int kWalk = TFSPH_WALK;
-constexpr int kPad = kChunk;   // records past the end of a sorted pos / frc array that may be read
+// records past the end of a sorted pos / frc array that may be read
+constexpr int kPad = kChunk > kScanChunk ? kChunk : kScanChunk;
 
 // Grid + kernel geometry of one problem (uniform periodic cells, Section 2.3).
 template <typename R>

@@ -15,24 +15,24 @@
 
 namespace tfsph {
 
-// Load the chunk of kChunk records starting at b of a range ending at b1.
+// Load the chunk of kScanChunk records starting at b of a range ending at b1.
 // Padded arrays (sorted pos / frc in global memory, kPad spare records at
 // the end) are read straight past b1 from one address; otherwise (LDS) the
 // indices are clamped to the range.
 template <bool Padded, typename V>
-__device__ __forceinline__ void load_chunk(const V *__restrict__ data, int b, int b1, V q[kChunk])
+__device__ __forceinline__ void load_chunk(const V *__restrict__ data, int b, int b1, V q[kScanChunk])
 {
     if (Padded) {
         const V *p = data + b;
 #pragma unroll
-        for (int k = 0; k < kChunk; ++k) q[k] = p[k];
+        for (int k = 0; k < kScanChunk; ++k) q[k] = p[k];
     } else {
 #pragma unroll
-        for (int k = 0; k < kChunk; ++k) q[k] = data[min(b + k, b1 - 1)];
+        for (int k = 0; k < kScanChunk; ++k) q[k] = data[min(b + k, b1 - 1)];
     }
 }
 
-// Visit candidates [b0, b1) of one cell: records are loaded kChunk at a time
+// Visit candidates [b0, b1) of one cell: records are loaded kScanChunk at a time
 // so one memory wait serves several candidates; fn(b, q, rx, ry, rz, valid)
 // gets the record, r = x_a - x_b and whether b is a real candidate (false
 // past b1 in the last chunk; such records are finite but belong elsewhere).
@@ -40,12 +40,12 @@ template <typename R, int DIM, bool Padded = true, typename Fn>
 __device__ __forceinline__ void visit_range(int b0, int b1, const R4<R> *__restrict__ data, R rx0, R ry0, R rz0,
                                             Fn &fn)
 {
-    for (int b = b0; b < b1; b += kChunk) {
-        R4<R> q[kChunk];
+    for (int b = b0; b < b1; b += kScanChunk) {
+        R4<R> q[kScanChunk];
         load_chunk<Padded>(data, b, b1, q);
         const int rem = b1 - b;        // >= 1: candidate k of the chunk is real when k < rem
 #pragma unroll
-        for (int k = 0; k < kChunk; ++k) {
+        for (int k = 0; k < kScanChunk; ++k) {
             const R rx = rx0 - q[k].x;
             const R ry = DIM > 1 ? ry0 - q[k].y : R(0);
             const R rz = DIM > 2 ? rz0 - q[k].z : R(0);
@@ -202,13 +202,13 @@ __device__ __forceinline__ unsigned long long visit_range_bits(int b0, int b1, c
                                                                R ry0, R rz0, int p0, Fn &fn)
 {
     unsigned long long m = 0;
-    for (int b = b0; b < b1; b += kChunk) {
-        R4<R> q[kChunk];
+    for (int b = b0; b < b1; b += kScanChunk) {
+        R4<R> q[kScanChunk];
         load_chunk<true>(data, b, b1, q);
         unsigned nib = 0;
         const int rem = b1 - b;        // >= 1: candidate k of the chunk is real when k < rem
 #pragma unroll
-        for (int k = 0; k < kChunk; ++k) {
+        for (int k = 0; k < kScanChunk; ++k) {
             const R rx = rx0 - q[k].x;
             const R ry = DIM > 1 ? ry0 - q[k].y : R(0);
             const R rz = DIM > 2 ? rz0 - q[k].z : R(0);
