@@ -48,7 +48,7 @@ __device__ __forceinline__ void set_flag(const Flags &F, bool bad)
 // explicit terms f(Y1) (stored) and the stage-2 predictor into Q at a:
 //   x2 = x^n + gamma tau v^n,  v2~ = v^n + gamma tau (A + g),  e2 = e^n + gamma tau de/dt.
 template <typename R, int DIM, int KIND>
-__global__ void TFSPH_FORCE_OCCUPANCY(R, KIND) __launch_bounds__(kBlock)
+__global__ void TFSPH_STAGE_OCCUPANCY(R, KIND) __launch_bounds__(kBlock)
 k_imex_gas1(Geom<R> G, Phys<R> Ph, Sorted<R> S, Stage<R> X, Phase<R> Q, ImexCoef<R> C, Flags F)
 {
     const int a = xcd_block(gridDim.x) * kBlock + threadIdx.x;
@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(kBlock) k_imex_dust1(Geom<R> G, Phys<R> Ph, So
 // Explicit terms f(Y2) of the gas at the stage-2 binning S2 (velocities v2,
 // energies e2), stored at the level-n index src[a].
 template <typename R, int DIM, int KIND>
-__global__ void TFSPH_FORCE_OCCUPANCY(R, KIND) __launch_bounds__(kBlock)
+__global__ void TFSPH_STAGE_OCCUPANCY(R, KIND) __launch_bounds__(kBlock)
 k_imex_gas2(Geom<R> G, Phys<R> Ph, Sorted<R> S, Stage<R> X, Flags F)
 {
     const int a = xcd_block(gridDim.x) * kBlock + threadIdx.x;

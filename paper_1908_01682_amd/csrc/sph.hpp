@@ -405,7 +405,7 @@ __device__ __forceinline__ int xcd_block(int nblocks)
 }
 
 template <typename R, int DIM>
-__global__ void TFSPH_PAIR_OCCUPANCY __launch_bounds__(kBlock) k_density(Geom<R> G, Phys<R> Ph, Sorted<R> S,
+__global__ void TFSPH_DENSITY_OCCUPANCY(R) __launch_bounds__(kBlock) k_density(Geom<R> G, Phys<R> Ph, Sorted<R> S,
                                                                          int want_frc)
 {
     const int a = xcd_block(gridDim.x) * kBlock + threadIdx.x;
