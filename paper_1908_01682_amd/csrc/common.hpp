@@ -69,14 +69,13 @@ __device__ __forceinline__ R spline_df(R q)
 // Waves per SIMD of the FP32 pair kernels on the 3D box, against the
 // compiler's choice: the density pass at 7 (72 VGPRs, a 20-byte spill) takes
 // 0.336 ms against 0.345 at 6 (79 VGPRs); the isothermal force pass at 7
-// (72 VGPRs, 12 bytes spilled) 0.162 ms against 0.170 at 6.  The IMEX force
-// stages do more per neighbour and stay at 6; the general force loop and FP64
-// would spill heavily, so they keep the compiler's choice.
+// (72 VGPRs, 12 bytes spilled) 0.162 ms against 0.170 at 6; the IMEX step
+// with its force stages at 7 1.687 ms against 1.702 at 6.  The general force
+// loop and FP64 would spill heavily, so they keep the compiler's choice.
 #define TFSPH_DENSITY_OCCUPANCY(R) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 7 : 1)))
 #define TFSPH_FORCE_OCCUPANCY(R, KIND) \
     __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && (KIND) != 2) ? 7 : 1)))
-#define TFSPH_STAGE_OCCUPANCY(R, KIND) \
-    __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && (KIND) != 2) ? 6 : 1)))
+#define TFSPH_STAGE_OCCUPANCY(R, KIND) TFSPH_FORCE_OCCUPANCY(R, KIND)
 #endif
 constexpr int kChunk = TFSPH_CHUNK;
 constexpr int kScanChunk = TFSPH_SCAN_CHUNK;
