@@ -222,7 +222,7 @@ def batched_throughput(I, T, torch, steps=500, plain_steps=20):
             "plain_path_value": plain, "vs_plain": value / plain, "nonfinite": bool(flags & 1)}
 
 
-def imex_throughput(prob, T, torch, steps=50, warmup=3):
+def imex_throughput(prob, T, torch, steps=100, warmup=100):
     """The same workload with the second-order IMEX step (three binnings, two density and force
     passes, two drag solves per step)."""
     q = prob.copy()
