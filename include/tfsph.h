@@ -54,8 +54,11 @@ enum {
     TFSPH_FLAG_NONFINITE = 1u,         /* a velocity, offset or density became NaN/Inf */
     TFSPH_FLAG_EMPTY_PHASE_CELL = 2u,  /* some cell held particles of one phase only */
     TFSPH_FLAG_BAD_CELL = 4u,          /* a state cell index was out of range (treated as cell 0) */
-    TFSPH_FLAG_CELL_OVERFLOW = 8u      /* a cell held more than 4096 particles of one phase: its
+    TFSPH_FLAG_CELL_OVERFLOW = 8u,     /* a cell held more than 4096 particles of one phase: its
                                           in-cell order fell back to arrival order (not reproducible) */
+    TFSPH_FLAG_CFL = 16u               /* with tfsph_params.cfl > 0: after some step the Courant
+                                          bound of eq. (4), tau < CFL h / max(|v|, c), no longer
+                                          held for the next step (see tfsph_signal_speed) */
 };
 
 enum { TFSPH_F32 = 0, TFSPH_F64 = 1 };
@@ -99,6 +102,12 @@ typedef struct {
                                on exit is the density at the start of the step and the one-phase
                                count covers both solves.  The batched and adjoint entry points
                                accept TFSPH_SCHEME_IDIC only (TFSPH_E_UNSUPPORTED otherwise). */
+    double cfl;             /* Courant number CFL of eq. (4) (the paper takes CFL < 1).  0: no check.
+                               > 0: at the end of every step each particle's signal speed
+                               s = max(|v|, c) is compared with CFL h / tau, where c is the gas sound
+                               speed (c_s, or sqrt(gamma (gamma-1) e) per gas particle for the
+                               adiabatic EOS), and TFSPH_FLAG_CFL is set where it is exceeded.  The
+                               largest s is kept either way (tfsph_signal_speed). */
 } tfsph_params;
 
 /* One particle phase (gas: indices a, b; dust: j, k in the paper's notation).
@@ -187,6 +196,23 @@ tfsph_status tfsph_density(tfsph_ctx *ctx, tfsph_state *s, int32_t phase, void *
 /* Read and clear the sticky flags and the count of one-phase cells seen
  * since the last call.  Synchronises the context's last stream. */
 tfsph_status tfsph_get_flags(tfsph_ctx *ctx, uint32_t *flags, int64_t *one_phase_cells);
+
+/* Largest signal speed max over particles of max(|v|, c) (eq. 4; c as for
+ * tfsph_params.cfl; with the isothermal EOS c_s is included) seen since the
+ * last call: the state tfsph_init() started from and the end of every step
+ * since (tfsph_step, tfsph_step_graph).  Reads and clears it; synchronises the
+ * context's last stream.  The maximum does not depend on the order in which
+ * particles are visited. */
+tfsph_status tfsph_signal_speed(tfsph_ctx *ctx, double *signal_speed);
+
+/* Host only: the time step of the Courant bound, eq. (4):
+ *   *dt = p->cfl * p->h / max(signal_speed, c)
+ * with c = p->c_s for the isothermal EOS and no floor for the adiabatic one
+ * (the signal speed from tfsph_signal_speed() already holds each gas
+ * particle's sound speed).  Only cfl, h, eos and c_s of p are read.
+ * TFSPH_E_INVALID_ARG when cfl or h are not positive and finite, the signal
+ * speed is negative or non-finite, or the bound is infinite (zero speed). */
+tfsph_status tfsph_cfl_dt(const tfsph_params *p, double signal_speed, double *dt);
 
 /* Replay form of tfsph_step: the launches of `chunk` consecutive steps are
  * captured once into a hipGraph (on a private stream of default priority,

@@ -39,13 +39,36 @@ FLAGS = [
 
 
 def build(verbose: bool = True) -> str:
-    """Compile every HIP source of the package into libtfsph.so (always rebuilds)."""
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc()] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + SOURCES
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    """Compile every HIP source of the package into libtfsph.so (always rebuilds).
+
+    Each source is compiled to an object in its own hipcc process (they run
+    concurrently), then the objects are linked into the shared library."""
+    tag = f".tmp{os.getpid()}"
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(os.path.basename(src))[0] + tag + ".o")
+        cmd = [hipcc()] + compile_flags + ["-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        jobs.append((obj, subprocess.Popen(cmd)))
+    failed = [obj for obj, proc in jobs if proc.wait() != 0]
+    objs = [obj for obj, _ in jobs]
+    try:
+        if failed:
+            raise subprocess.CalledProcessError(1, "hipcc -c", f"failed: {failed}")
+        tmp = LIB + tag
+        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(tmp, LIB)
+    finally:
+        for obj in objs:
+            if os.path.exists(obj):
+                os.remove(obj)
     return LIB
 
 

@@ -75,7 +75,8 @@ __device__ __forceinline__ void block_scan_cells(const int *count, int *start, i
 // known there); `first` does the counting from scratch for the first step of
 // a launch, since the state may have been written outside this kernel.
 template <typename R, int DIM>
-__device__ __forceinline__ void batched_step(const Inst<R> &I, int *lds, unsigned int *flags, int &bad, int &one, bool first)
+__device__ __forceinline__ void batched_step(const Inst<R> &I, int *lds, unsigned int *flags, int &bad, int &one,
+                                             R &s2, bool first)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     const Geom<R> &G = I.G;
@@ -134,7 +135,7 @@ __device__ __forceinline__ void batched_step(const Inst<R> &I, int *lds, unsigne
         const int a = base + tid;
         int key = -1;
         if (a < ng) {
-            bad |= !gas_finish<R, DIM>(G, I.Ph, I.Sg, I.Pg, a, I.cs[I.Sg.cell[a]]);
+            bad |= !gas_finish<R, DIM>(G, I.Ph, I.Sg, I.Pg, a, I.cs[I.Sg.cell[a]], s2);
             key = I.Pg.cell[a];
         }
         const int sl = claim_slot(I.Sg.count, key);
@@ -144,7 +145,7 @@ __device__ __forceinline__ void batched_step(const Inst<R> &I, int *lds, unsigne
         const int j = base + tid;
         int key = -1;
         if (j < nd) {
-            bad |= !dust_finish<R, DIM>(G, I.Ph, I.Sd, I.Pd, j, I.cs[I.Sd.cell[j]]);
+            bad |= !dust_finish<R, DIM>(G, I.Ph, I.Sd, I.Pd, j, I.cs[I.Sd.cell[j]], s2);
             key = I.Pd.cell[j];
         }
         const int sl = claim_slot(I.Sd.count, key);
@@ -163,7 +164,9 @@ k_batched(const Inst<R> *__restrict__ insts, const int *__restrict__ order, int 
     if (threadIdx.x == 0) { s_bad = 0; s_one = 0; }
     const Inst<R> &I = insts[order[blockIdx.x]];
     int bad = 0, one = 0;
-    for (int s = 0; s < n_steps; ++s) batched_step<R, DIM>(I, lds, F.word, bad, one, s == 0);
+    R s2 = signal_floor(I.Ph);
+    for (int s = 0; s < n_steps; ++s) batched_step<R, DIM>(I, lds, F.word, bad, one, s2, s == 0);
+    if (I.Ph.vlim2 > R(0) && s2 > I.Ph.vlim2) atomicOr(F.word, kFlagCfl);
     if (bad) atomicOr(&s_bad, 1);
     if (one) atomicAdd(&s_one, one);
     __syncthreads();

@@ -367,13 +367,14 @@ __global__ void __launch_bounds__(NT) k_update_brick(Geom<R> G, Phys<R> Ph, Sort
 
     // (3) implicit particle update, move, carry: gas targets, then the brick's dust
     int bad = 0;
+    R s2 = signal_floor(Ph);
     for (int t = threadIdx.x; t < T; t += NT) {
         const int k = find_brick_cell(sm.tstart, NC, t);
         int lx, ly, lz, c;
         brick_cell<R, DIM>(G, bx0, by0, bz0, k, lx, ly, lz, c);
         const int hc = lx + B.hx * (ly + B.hy * lz);
         const int a = H.gstart[hc] + (t - sm.tstart[k]);
-        bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[k]);
+        bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[k], s2);
     }
     __syncthreads();
     // dust targets: reuse tstart for the brick's dust counts
@@ -391,8 +392,9 @@ __global__ void __launch_bounds__(NT) k_update_brick(Geom<R> G, Phys<R> Ph, Sort
     for (int t = threadIdx.x; t < TD; t += NT) {
         const int k = find_brick_cell(sm.tstart, NC, t);
         const int j = Sd.start[cell_of[k]] + (t - sm.tstart[k]);
-        bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[k]);
+        bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[k], s2);
     }
+    publish_speed(Ph, F, s2);
     if (bad) atomicOr(&s_bad, 1);
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -115,6 +115,7 @@ struct Phys {
     R av_alpha, av_beta;
     R eta2;              // 0.01 h^2 in the viscosity denominator
     R h;
+    R vlim2;             // Courant bound of eq. (4): (CFL h / tau)^2; 0 = no check
 };
 
 // Caller-owned arrays of one phase.
@@ -184,8 +185,11 @@ struct Sorted {
 
 struct Flags {
     unsigned int *word;                 // sticky TFSPH_FLAG_* bits
-    unsigned long long *one_phase;      // count of one-phase cells
+    unsigned long long *one_phase;      // [0]: count of one-phase cells; [1]: bits of the largest
+                                        // squared signal speed max(|v|, c)^2 (a double) seen
 };
+
+constexpr unsigned int kFlagCfl = 16u;  // TFSPH_FLAG_CFL
 
 // A cell index read from caller memory; anything out of range is treated as
 // cell 0 (and reported by the kernels that read it) so no access leaves the

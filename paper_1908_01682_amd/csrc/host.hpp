@@ -152,6 +152,7 @@ Phys<R> make_phys(const tfsph_params *p)
     P.av_beta = R(p->av_beta);
     P.eta2 = R(0.01 * p->h * p->h);
     P.h = R(p->h);
+    P.vlim2 = p->cfl > 0.0 ? R((p->cfl * p->h / p->dt) * (p->cfl * p->h / p->dt)) : R(0);
     return P;
 }
 

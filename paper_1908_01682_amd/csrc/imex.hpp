@@ -253,6 +253,7 @@ k_imex_relax(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Stage<R> Xg, Sta
     __syncthreads();
 
     int bad = 0;
+    R s2 = signal_floor(Ph);
     for (int a = ga + threadIdx.x; a < gb; a += kBlock) {
         const CellSolve<R> &Cs = cs[Sg.cell[a] - c0];
         const R inv = R(1) / (R(1) + Cs.alpha);
@@ -260,6 +261,7 @@ k_imex_relax(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Stage<R> Xg, Sta
         const R4<R> me = Sg.pos[a];
         const R oo[3] = {me.x, me.y, me.z};
         const R4<R> sv = staged ? stg[a - ga] : R4<R>{};      // (m, v~) from LDS when staged
+        R v2 = R(0);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
             const R vt = staged ? (d == 0 ? sv.y : d == 1 ? sv.z : sv.w) : Sg.vel[d][a];
@@ -268,6 +270,7 @@ k_imex_relax(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Stage<R> Xg, Sta
             if constexpr (FINAL) {
                 Pg.vel[d][a] = v;
                 Pg.off[d][a] = oo[d];
+                v2 += v * v;
             } else {
                 Sg.vel[d][a] = v;
                 Xg.v2[d][i] = v;
@@ -280,6 +283,8 @@ k_imex_relax(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Stage<R> Xg, Sta
             if (Sg.has_mass && Pg.mass) const_cast<R *>(Pg.mass)[a] = me.w;
             if (Sg.energy) Pg.energy[a] = Sg.energy[a];
             Pg.rho[a] = rho1[i];
+            s2 = fmax(s2, v2);
+            if (Ph.eos != 0 && Sg.energy) s2 = fmax(s2, Ph.ggm1 * Sg.energy[a]);
         }
     }
     for (int j = da + threadIdx.x; j < db; j += kBlock) {
@@ -289,6 +294,7 @@ k_imex_relax(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Stage<R> Xg, Sta
         const R4<R> me = Sd.pos[j];
         const R oo[3] = {me.x, me.y, me.z};
         const R4<R> su = staged ? std_[j - da] : R4<R>{};     // (m, u~) from LDS when staged
+        R u2 = R(0);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
             const R ut = staged ? (d == 0 ? su.y : d == 1 ? su.z : su.w) : Sd.vel[d][j];
@@ -297,6 +303,7 @@ k_imex_relax(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Stage<R> Xg, Sta
             if constexpr (FINAL) {
                 Pd.vel[d][j] = u;
                 Pd.off[d][j] = oo[d];
+                u2 += u * u;
             } else {
                 Sd.vel[d][j] = u;
                 Xd.v2[d][i] = u;
@@ -307,8 +314,10 @@ k_imex_relax(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Stage<R> Xg, Sta
             Pd.cell[j] = Sd.cell[j];
             Pd.id[j] = Sd.id[j];
             if (Sd.has_mass && Pd.mass) const_cast<R *>(Pd.mass)[j] = me.w;
+            s2 = fmax(s2, u2);
         }
     }
+    if constexpr (FINAL) publish_speed(Ph, F, s2);
     if (bad) atomicOr(&s_bad, 1);
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -668,7 +668,7 @@ __device__ __forceinline__ void gas_predict(const Geom<R> &G, const Phys<R> &Ph,
 // x^{n+1} = x^n + tau v^{n+1} and the carry; writes the caller's arrays at a.
 template <typename R, int DIM>
 __device__ __forceinline__ bool gas_finish(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg,
-                                           const Phase<R> &Pg, int a, const CellSolve<R> &C,
+                                           const Phase<R> &Pg, int a, const CellSolve<R> &C, R &s2,
                                            const R4<R> *staged = nullptr)
 {
     const int c = Sg.cell[a];
@@ -688,6 +688,7 @@ __device__ __forceinline__ bool gas_finish(const Geom<R> &G, const Phys<R> &Ph, 
 #pragma unroll
         for (int d = 0; d < DIM; ++d) vt[d] = Sg.vt[d][a];
     }
+    R v2 = R(0);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         const R v = (vt[d] + C.alpha * C.U[d]) * inv;
@@ -696,7 +697,11 @@ __device__ __forceinline__ bool gas_finish(const Geom<R> &G, const Phys<R> &Ph, 
         ok &= carry(o, cc[d], G.delta[d], G.nc[d]);
         Pg.vel[d][a] = v;
         Pg.off[d][a] = o;
+        v2 += v * v;
     }
+    // signal speed of eq. (4): max(|v|, c), with the sound speed of the new energy
+    s2 = fmax(s2, v2);
+    if (Ph.eos != 0 && Sg.energy) s2 = fmax(s2, Ph.ggm1 * Pg.energy[a]);
     Pg.cell[a] = join_cell(G, cc[0], cc[1], cc[2]);
     Pg.id[a] = Sg.id[a];
     if (Sg.has_mass && Pg.mass) const_cast<R *>(Pg.mass)[a] = me.w;
@@ -707,7 +712,7 @@ __device__ __forceinline__ bool gas_finish(const Geom<R> &G, const Phys<R> &Ph, 
 // Implicit update of eq. (20) for dust particle j of cell C, then move + carry.
 template <typename R, int DIM>
 __device__ __forceinline__ bool dust_finish(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sd,
-                                            const Phase<R> &Pd, int j, const CellSolve<R> &C,
+                                            const Phase<R> &Pd, int j, const CellSolve<R> &C, R &s2,
                                             const R4<R> *staged = nullptr)
 {
     const int c = Sd.cell[j];
@@ -727,6 +732,7 @@ __device__ __forceinline__ bool dust_finish(const Geom<R> &G, const Phys<R> &Ph,
 #pragma unroll
         for (int d = 0; d < DIM; ++d) uu[d] = Sd.vel[d][j];
     }
+    R u2 = R(0);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         const R ut = uu[d] + Ph.tau * Ph.g[d];
@@ -736,11 +742,55 @@ __device__ __forceinline__ bool dust_finish(const Geom<R> &G, const Phys<R> &Ph,
         ok &= carry(o, cc[d], G.delta[d], G.nc[d]);
         Pd.vel[d][j] = u;
         Pd.off[d][j] = o;
+        u2 += u * u;
     }
+    s2 = fmax(s2, u2);
     Pd.cell[j] = join_cell(G, cc[0], cc[1], cc[2]);
     Pd.id[j] = Sd.id[j];
     if (Sd.has_mass && Pd.mass) const_cast<R *>(Pd.mass)[j] = me.w;
     return ok;
+}
+
+// Courant bound of eq. (4), tau < CFL h / max(|v|, c).  A thread's largest
+// squared signal speed s2 (isothermal: starts at c_s^2) sets TFSPH_FLAG_CFL when
+// it exceeds (CFL h / tau)^2, and raises the device maximum in F.one_phase[1]:
+// the bit pattern of a non-negative double orders like its value, so the
+// maximum is an integer maximum and does not depend on the order of arrival.
+// Every lane of the wave must call it (wave-wide maximum first).
+template <typename R>
+__device__ __forceinline__ R signal_floor(const Phys<R> &Ph)
+{
+    return Ph.eos == 0 ? Ph.cs2 : R(0);
+}
+
+template <typename R>
+__device__ __forceinline__ void publish_speed(const Phys<R> &Ph, const Flags &F, R s2)
+{
+    if (Ph.vlim2 > R(0) && s2 > Ph.vlim2) atomicOr(F.word, kFlagCfl);
+    double m = double(s2);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0 && m > 0.0) {
+        unsigned long long *dst = F.one_phase + 1;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
+        if (bits > __atomic_load_n(dst, __ATOMIC_RELAXED)) atomicMax(dst, bits);
+    }
+}
+
+// Signal speed of a phase held in the caller's arrays (any order): the device
+// maximum of publish_speed() for the state tfsph_init() starts from.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_signal_speed(Geom<R> G, Phys<R> Ph, Phase<R> P, int gas, Flags F)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    R s2 = signal_floor(Ph);
+    if (i < P.n) {
+        R v2 = R(0);
+        for (int d = 0; d < G.dim; ++d) v2 += P.vel[d][i] * P.vel[d][i];
+        s2 = fmax(s2, v2);
+        if (gas && Ph.eos != 0 && P.energy) s2 = fmax(s2, Ph.ggm1 * P.energy[i]);
+    }
+    publish_speed(Ph, F, s2);
 }
 
 // Explicit gas terms and predictor, one thread per gas particle, specialised
@@ -830,10 +880,12 @@ k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R
 
     // (2) implicit particle update (eqs. 19-20), position update, carry
     int bad = 0;
+    R s2 = signal_floor(Ph);
     for (int a = ga + threadIdx.x; a < gb; a += kBlock)
-        bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0], staged ? &stg[a - ga] : nullptr);
+        bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0], s2, staged ? &stg[a - ga] : nullptr);
     for (int j = da + threadIdx.x; j < db; j += kBlock)
-        bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[Sd.cell[j] - c0], staged ? &std_[j - da] : nullptr);
+        bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[Sd.cell[j] - c0], s2, staged ? &std_[j - da] : nullptr);
+    publish_speed(Ph, F, s2);
     if (bad) atomicOr(&s_bad, 1);
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -87,6 +87,22 @@ extern "C" tfsph_status tfsph_validate(const tfsph_params *p)
         return fail(TFSPH_E_INVALID_ARG, "viscosity coefficients must be >= 0");
     for (int d = 0; d < 3; ++d)
         if (!std::isfinite(p->g[d])) return fail(TFSPH_E_INVALID_ARG, "g must be finite");
+    if (!(std::isfinite(p->cfl) && p->cfl >= 0.0)) return fail(TFSPH_E_INVALID_ARG, "cfl must be >= 0 and finite");
+    return TFSPH_OK;
+}
+
+extern "C" tfsph_status tfsph_cfl_dt(const tfsph_params *p, double signal_speed, double *dt)
+{
+    g_last_error[0] = 0;
+    if (!p || !dt) return fail(TFSPH_E_INVALID_ARG, "params / dt is NULL");
+    if (!(std::isfinite(p->cfl) && p->cfl > 0.0)) return fail(TFSPH_E_INVALID_ARG, "cfl must be positive and finite");
+    if (!finite_pos(p->h)) return fail(TFSPH_E_INVALID_ARG, "h must be positive and finite");
+    if (!(std::isfinite(signal_speed) && signal_speed >= 0.0))
+        return fail(TFSPH_E_INVALID_ARG, "signal speed must be >= 0 and finite");
+    // eq. (4): tau = CFL h / max(v, c); the isothermal sound speed is a floor of the signal speed
+    const double s = p->eos == TFSPH_ISOTHERMAL ? std::max(signal_speed, p->c_s) : signal_speed;
+    if (!(s > 0.0)) return fail(TFSPH_E_INVALID_ARG, "signal speed is zero: no Courant bound");
+    *dt = p->cfl * p->h / s;
     return TFSPH_OK;
 }
 
@@ -383,7 +399,8 @@ tfsph_status enqueue_step_imex(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
     tfsph_params pe = c->p;
     pe.dt = c->p.dt * (1.0 - 1.0 / std::sqrt(2.0));
     for (int d = 0; d < 3; ++d) pe.g[d] = 0.0;      // predictors already hold the explicit terms
-    const Phys<R> PhE = make_phys<R>(&pe);
+    Phys<R> PhE = make_phys<R>(&pe);
+    PhE.vlim2 = Ph.vlim2;                            // the Courant bound is on the whole step tau
     const ImexCoef<R> C = imex_coef<R>(c->p.dt);
     Phase<R> Pg = make_phase<R>(s->gas, DIM), Pd = make_phase<R>(s->dust, DIM);
     Sorted<R> Sg, Sd;
@@ -463,6 +480,22 @@ tfsph_status enqueue_step_imex(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
     return TFSPH_OK;
 }
 
+// sticky flags (64 words) and the one-phase count / signal-speed words (8) to zero
+__global__ void k_clear_flags(unsigned int *word, unsigned long long *one_phase)
+{
+    word[threadIdx.x] = 0u;
+    if (threadIdx.x < 8) one_phase[threadIdx.x] = 0ull;
+}
+
+// copy the flags and the one-phase count into caller arrays (either may be null)
+__global__ void k_export_flags(const unsigned int *word, const unsigned long long *one_phase, uint32_t *flags_out,
+                               int64_t *one_phase_out)
+{
+    if (threadIdx.x != 0) return;
+    if (flags_out) *flags_out = word[0];
+    if (one_phase_out) *one_phase_out = (int64_t)one_phase[0];
+}
+
 template <typename R>
 tfsph_status enqueue_init(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
 {
@@ -474,8 +507,10 @@ tfsph_status enqueue_init(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
     ImexViews<R> V;
     const bool imex = c->p.scheme == TFSPH_SCHEME_IMEX2;
     carve_all<R>(c, Sg, Sd, partial, F, imex ? &V : nullptr);
-    HIP_TRY(hipMemsetAsync(F.word, 0, 256, st));
-    HIP_TRY(hipMemsetAsync(F.one_phase, 0, 64, st));
+    // a fill kernel rather than a memset node: the no-allocation entry point
+    // enqueues this sequence on streams a caller may be capturing
+    hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, st, F.word, F.one_phase);
+    LAUNCH_CHECK("clear_flags");
     tfsph_status z = enqueue_zero_counts<R>(G.ncell, Sg, Sd, st);
     if (z != TFSPH_OK) return z;
     if (imex) {
@@ -489,6 +524,15 @@ tfsph_status enqueue_init(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
     if (c->nd > 0) {
         hipLaunchKernelGGL(k_canonicalize<R>, dim3(blocks_for(c->nd)), dim3(kBlock), 0, st, G, Pd, F);
         LAUNCH_CHECK("canonicalize");
+    }
+    const Phys<R> Ph = make_phys<R>(&c->p);
+    if (c->ng > 0) {
+        hipLaunchKernelGGL(k_signal_speed<R>, dim3(blocks_for(c->ng)), dim3(kBlock), 0, st, G, Ph, Pg, 1, F);
+        LAUNCH_CHECK("signal_speed");
+    }
+    if (c->nd > 0) {
+        hipLaunchKernelGGL(k_signal_speed<R>, dim3(blocks_for(c->nd)), dim3(kBlock), 0, st, G, Ph, Pd, 0, F);
+        LAUNCH_CHECK("signal_speed");
     }
     tfsph_status r = enqueue_bin<R>(c->ng, c->nd, G, Pg, Pd, Sg, Sd, partial, F, st);
     if (r != TFSPH_OK) return r;
@@ -651,6 +695,29 @@ extern "C" tfsph_status tfsph_get_flags(tfsph_ctx *c, uint32_t *flags, int64_t *
     HIP_TRY(hipMemset(F.one_phase, 0, sizeof(n)));
     if (flags) *flags = w;
     if (one_phase_cells) *one_phase_cells = (int64_t)n;
+    return TFSPH_OK;
+}
+
+extern "C" tfsph_status tfsph_signal_speed(tfsph_ctx *c, double *signal_speed)
+{
+    if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
+    if (!signal_speed) return fail(TFSPH_E_INVALID_ARG, "signal_speed is NULL");
+    Sorted<float> Sg, Sd;
+    int *partial;
+    Flags F;
+    if (c->p.precision == TFSPH_F64) {
+        Sorted<double> a, b;
+        carve_all<double>(c, a, b, partial, F);
+    } else {
+        carve_all<float>(c, Sg, Sd, partial, F);
+    }
+    unsigned long long bits = 0;
+    HIP_TRY(hipStreamSynchronize(c->last_stream));
+    HIP_TRY(hipMemcpy(&bits, F.one_phase + 1, sizeof(bits), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(F.one_phase + 1, 0, sizeof(bits)));
+    double s2;
+    std::memcpy(&s2, &bits, sizeof(s2));
+    *signal_speed = std::sqrt(s2);
     return TFSPH_OK;
 }
 

@@ -25,6 +25,7 @@ TFSPH_FLAG_NONFINITE = 1
 TFSPH_FLAG_EMPTY_PHASE_CELL = 2
 TFSPH_FLAG_BAD_CELL = 4
 TFSPH_FLAG_CELL_OVERFLOW = 8
+TFSPH_FLAG_CFL = 16
 TFSPH_SCHEME_IDIC, TFSPH_SCHEME_IMEX2 = 0, 1
 
 STATUS = {0: "TFSPH_OK", -1: "TFSPH_E_INVALID_ARG", -2: "TFSPH_E_WORKSPACE", -3: "TFSPH_E_HIP",
@@ -43,7 +44,7 @@ class Params(ctypes.Structure):
                 ("c_s", ctypes.c_double), ("gamma", ctypes.c_double), ("t_stop", ctypes.c_double),
                 ("g", ctypes.c_double * 3), ("dt", ctypes.c_double), ("av_alpha", ctypes.c_double),
                 ("av_beta", ctypes.c_double), ("precision", ctypes.c_int32), ("K", ctypes.c_double),
-                ("t_stop_epstein", ctypes.c_double), ("scheme", ctypes.c_int32)]
+                ("t_stop_epstein", ctypes.c_double), ("scheme", ctypes.c_int32), ("cfl", ctypes.c_double)]
 
 
 class PhaseC(ctypes.Structure):
@@ -86,6 +87,8 @@ def lib():
         L.tfsph_step.argtypes = [vp, ctypes.POINTER(StateC), ctypes.c_int32, vp]
         L.tfsph_density.argtypes = [vp, ctypes.POINTER(StateC), ctypes.c_int32, vp]
         L.tfsph_get_flags.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int64)]
+        L.tfsph_signal_speed.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.tfsph_cfl_dt.argtypes = [P, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
         L.tfsph_destroy.argtypes = [vp]
         L.tfsph_positions_to_cells.argtypes = [P, ctypes.c_int64, vp, vp, ctypes.c_void_p * 3, vp]
         L.tfsph_cells_to_positions.argtypes = [P, ctypes.c_int64, vp, ctypes.c_void_p * 3, vp, vp]
@@ -109,7 +112,7 @@ def lib():
         L.tfsph_step_adjoint.argtypes = [P, ST, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_void_p * 3,
                                          ctypes.c_void_p * 3, vp, vp, vp, ctypes.c_size_t, vp]
         for name in ("tfsph_validate", "tfsph_workspace_size", "tfsph_init", "tfsph_step", "tfsph_density",
-                     "tfsph_get_flags", "tfsph_destroy", "tfsph_positions_to_cells", "tfsph_cells_to_positions",
+                     "tfsph_get_flags", "tfsph_signal_speed", "tfsph_cfl_dt", "tfsph_destroy", "tfsph_positions_to_cells", "tfsph_cells_to_positions",
                      "tfsph_profile", "tfsph_profile_sampled", "tfsph_profile_read", "tfsph_set_kernel_variant", "tfsph_set_cells_per_block", "tfsph_step_graph", "tfsph_batch_workspace_size",
                      "tfsph_batch_init", "tfsph_batch_set_tuning", "tfsph_step_batched", "tfsph_step_batched_graph",
                      "tfsph_batch_get_flags", "tfsph_batch_destroy", "tfsph_adjoint_workspace_size",
@@ -154,6 +157,7 @@ def make_params(p, precision: int = TFSPH_F32) -> Params:
     c.K = float(getattr(p, "K", 0.0))
     c.t_stop_epstein = float(getattr(p, "t_stop_epstein", 0.0))
     c.scheme = int(getattr(p, "scheme", TFSPH_SCHEME_IDIC))
+    c.cfl = float(getattr(p, "cfl", 0.0))
     return c
 
 
@@ -193,6 +197,20 @@ def tfsph_get_flags(ctx):
     n = ctypes.c_int64(0)
     _check(lib().tfsph_get_flags(ctx, ctypes.byref(f), ctypes.byref(n)), "tfsph_get_flags")
     return int(f.value), int(n.value)
+
+
+def tfsph_signal_speed(ctx) -> float:
+    """Largest max(|v|, c) since the last call (eq. 4); synchronises."""
+    out = ctypes.c_double(0.0)
+    _check(lib().tfsph_signal_speed(ctx, ctypes.byref(out)), "tfsph_signal_speed")
+    return float(out.value)
+
+
+def tfsph_cfl_dt(params: Params, signal_speed: float) -> float:
+    """Time step of the Courant bound of eq. (4) (host only)."""
+    out = ctypes.c_double(0.0)
+    _check(lib().tfsph_cfl_dt(ctypes.byref(params), float(signal_speed), ctypes.byref(out)), "tfsph_cfl_dt")
+    return float(out.value)
 
 
 TFSPH_KERNEL_UPDATE, TFSPH_KERNEL_DENSITY, TFSPH_KERNEL_BIN, TFSPH_KERNEL_FORCE = 0, 1, 2, 3
@@ -355,6 +373,9 @@ class Simulation:
     def density(self, phase: int) -> None:
         tfsph_density(self.ctx, self.state, phase, self.stream)
 
+    def signal_speed(self) -> float:
+        return tfsph_signal_speed(self.ctx)
+
     def flags(self):
         return tfsph_get_flags(self.ctx)
 
@@ -479,6 +500,9 @@ class BatchedSimulation:
 
     def step_graph(self, n: int) -> None:
         tfsph_step_batched_graph(self.handle, self.state, n, self.stream)
+
+    def signal_speed(self) -> float:
+        return tfsph_signal_speed(self.ctx)
 
     def flags(self):
         return tfsph_batch_get_flags(self.handle)

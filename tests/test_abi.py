@@ -181,3 +181,42 @@ def test_imex_workspace_holds_the_stage_data(lib):
     a = T.tfsph_workspace_size(p1, n, n)
     b = T.tfsph_workspace_size(p2, n, n)
     assert b - a >= n * (4 + 8 + 24 + 48)
+
+
+def test_validate_cfl(lib):
+    """cfl = 0 turns the Courant check off; a positive finite value turns it on; negative or
+    non-finite values are rejected on the host."""
+    p = _good()
+    for ok in (0.0, 0.25, 0.9):
+        p.cfl = ok
+        assert _status(p) == 0, T.lib().tfsph_last_error()
+    for bad in (-0.1, float("nan"), float("inf")):
+        p.cfl = bad
+        assert _status(p) == -1
+
+
+def test_cfl_dt_is_the_courant_bound(lib):
+    """Eq. (4): tau = CFL h / max(v, c).  Isothermal: c_s is a floor of the signal speed;
+    adiabatic: the signal speed is taken as given (it holds each gas particle's sound speed)."""
+    p = _good()                                   # 1D wave, isothermal, c_s = 1, h = 0.01
+    p.cfl = 0.25
+    assert T.tfsph_cfl_dt(p, 0.0) == pytest.approx(0.25 * p.h / p.c_s, rel=1e-15)
+    assert T.tfsph_cfl_dt(p, 0.5) == pytest.approx(0.25 * p.h / p.c_s, rel=1e-15)
+    assert T.tfsph_cfl_dt(p, 4.0) == pytest.approx(0.25 * p.h / 4.0, rel=1e-15)
+    # the wave generator computes its own tau the same way
+    prob = I.workload("wave1d")
+    q = T.make_params(prob.params)
+    q.cfl = 0.25
+    vmax = float(abs(prob.gas.v).max())
+    assert T.tfsph_cfl_dt(q, vmax) == pytest.approx(prob.params.dt, rel=1e-15)
+    a = T.make_params(I.dusty_shock(n=2000).params)
+    a.cfl = 0.1
+    assert T.tfsph_cfl_dt(a, 2.0) == pytest.approx(0.1 * a.h / 2.0, rel=1e-15)
+    with pytest.raises(T.TfsphError):
+        T.tfsph_cfl_dt(a, 0.0)                    # no floor for the adiabatic EOS: infinite bound
+    for bad_speed in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(T.TfsphError):
+            T.tfsph_cfl_dt(p, bad_speed)
+    p.cfl = 0.0
+    with pytest.raises(T.TfsphError):
+        T.tfsph_cfl_dt(p, 1.0)
