@@ -369,7 +369,30 @@ tfsph_status tfsph_positions_to_cells(const tfsph_params *p, int64_t n, const do
 tfsph_status tfsph_cells_to_positions(const tfsph_params *p, int64_t n, const int32_t *cell, void *const off[3],
                                       double *x, void *hip_stream);
 
-/* Release the context (host memory only; the workspace stays the caller's). */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): tfsph_init
+ * followed by tfsph_step(n_steps) in one call, with no context and no
+ * caller workspace.  The workspace is the library's static device array of
+ * 64 MiB per GPU (held from the library's first use on that GPU until the
+ * process ends); the call makes no hipMalloc/hipFree or other allocating
+ * call, and enqueues its kernels asynchronously on hip_stream.
+ *   p, s           as for tfsph_init / tfsph_step: on return the state holds
+ *                  level n_steps in canonical order (bitwise what tfsph_init +
+ *                  tfsph_step give)
+ *   flags_out      device uint32 (nullable): the sticky TFSPH_FLAG_* bits of
+ *                  this call (the canonical ordering and every step)
+ *   one_phase_out  device int64 (nullable): one-phase cells counted by this
+ *                  call
+ * Errors (host-side, nothing enqueued): those of tfsph_init, n_steps < 0, and
+ * TFSPH_E_WORKSPACE when the problem needs more workspace than the static
+ * array holds (tfsph_workspace_size() for the same sizes is an upper bound of
+ * the need).  Every call on one GPU shares that GPU's array and starts by
+ * clearing what must start at zero; calls that overlap in time on one GPU
+ * (other streams, other threads) race and must not be issued. */
+tfsph_status tfsph_step_noalloc(const tfsph_params *p, tfsph_state *s, int32_t n_steps, uint32_t *flags_out,
+                                int64_t *one_phase_out, void *hip_stream);
+
+/* Release the context (host memory only; the workspace stays the caller's). *//* Release the context (host memory only; the workspace stays the caller's). */
 tfsph_status tfsph_destroy(tfsph_ctx *ctx);
 
 #ifdef __cplusplus

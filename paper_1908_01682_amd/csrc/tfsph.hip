@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -862,6 +863,95 @@ extern "C" tfsph_status tfsph_destroy(tfsph_ctx *c)
         if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     }
     delete c;
+    return TFSPH_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Entry point for callers that cannot allocate: the workspace is the library's
+// own device array `scratch` (one copy per GPU, held until the process ends).
+// Host code never passes the array's name to a kernel or a copy: on the host
+// it is only a stand-in for the symbol.  Its device address is looked up once
+// per device with hipGetSymbolAddress and kept in g_scratch_ptr.
+// ----------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = size_t(64) << 20;     // 64 MiB per GPU
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mutex;
+}  // namespace
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static tfsph_status scratch_of_current_device(void **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TFSPH_E_UNSUPPORTED, "device %d beyond %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(TFSPH_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return TFSPH_OK;
+}
+
+extern "C" tfsph_status tfsph_step_noalloc(const tfsph_params *p, tfsph_state *s, int32_t n_steps, uint32_t *flags_out,
+                                           int64_t *one_phase_out, void *hip_stream)
+{
+    tfsph_status r = tfsph_validate(p);
+    if (r != TFSPH_OK) return r;
+    if (!s) return fail(TFSPH_E_INVALID_ARG, "state is NULL");
+    if (n_steps < 0) return fail(TFSPH_E_INVALID_ARG, "n_steps must be >= 0");
+    r = check_phase(s->gas, p->dim, true, p->eos == TFSPH_ADIABATIC, "gas");
+    if (r != TFSPH_OK) return r;
+    r = check_phase(s->dust, p->dim, false, false, "dust");
+    if (r != TFSPH_OK) return r;
+    const PhaseFlags fg = gas_flags(p, s->gas.mass != nullptr), fd = dust_flags(s->dust.mass != nullptr);
+    const size_t need = p->precision == TFSPH_F64 ? plan_bytes<double>(p, (int)s->gas.n, (int)s->dust.n, fg, fd)
+                                                  : plan_bytes<float>(p, (int)s->gas.n, (int)s->dust.n, fg, fd);
+    if (need > kScratchBytes)
+        return fail(TFSPH_E_WORKSPACE, "the problem needs %zu bytes of workspace; the library's static scratch holds %zu",
+                    need, kScratchBytes);
+    void *ws = nullptr;
+    r = scratch_of_current_device(&ws);
+    if (r != TFSPH_OK) return r;
+    // a context on the stack: nothing is allocated on the host or the device
+    tfsph_ctx c;
+    c.p = *p;
+    c.ng = (int)s->gas.n;
+    c.nd = (int)s->dust.n;
+    c.fg = fg;
+    c.fd = fd;
+    c.mg_uniform = s->gas.mass_uniform;
+    c.md_uniform = s->dust.mass_uniform;
+    c.ws = static_cast<char *>(ws);
+    c.ws_bytes = kScratchBytes;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    c.last_stream = st;
+    c.cells_per_block = default_cells_per_block(p->dim);
+    r = p->precision == TFSPH_F64 ? enqueue_init<double>(&c, s, st) : enqueue_init<float>(&c, s, st);
+    if (r != TFSPH_OK) return r;
+    for (int i = 0; i < n_steps; ++i) {
+        r = p->precision == TFSPH_F64 ? dispatch_step<double>(&c, s, st) : dispatch_step<float>(&c, s, st);
+        if (r != TFSPH_OK) return r;
+    }
+    if (flags_out || one_phase_out) {
+        Sorted<float> Sg, Sd;
+        int *partial;
+        Flags F;
+        if (p->precision == TFSPH_F64) {
+            Sorted<double> a, b;
+            carve_all<double>(&c, a, b, partial, F);
+        } else {
+            carve_all<float>(&c, Sg, Sd, partial, F);
+        }
+        hipLaunchKernelGGL(k_export_flags, dim3(1), dim3(64), 0, st, F.word, F.one_phase, flags_out, one_phase_out);
+        LAUNCH_CHECK("export_flags");
+    }
     return TFSPH_OK;
 }
 

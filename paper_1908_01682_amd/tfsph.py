@@ -89,6 +89,7 @@ def lib():
         L.tfsph_get_flags.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int64)]
         L.tfsph_signal_speed.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.tfsph_cfl_dt.argtypes = [P, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+        L.tfsph_step_noalloc.argtypes = [P, ctypes.POINTER(StateC), ctypes.c_int32, vp, vp, vp]
         L.tfsph_destroy.argtypes = [vp]
         L.tfsph_positions_to_cells.argtypes = [P, ctypes.c_int64, vp, vp, ctypes.c_void_p * 3, vp]
         L.tfsph_cells_to_positions.argtypes = [P, ctypes.c_int64, vp, ctypes.c_void_p * 3, vp, vp]
@@ -112,7 +113,7 @@ def lib():
         L.tfsph_step_adjoint.argtypes = [P, ST, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_void_p * 3,
                                          ctypes.c_void_p * 3, vp, vp, vp, ctypes.c_size_t, vp]
         for name in ("tfsph_validate", "tfsph_workspace_size", "tfsph_init", "tfsph_step", "tfsph_density",
-                     "tfsph_get_flags", "tfsph_signal_speed", "tfsph_cfl_dt", "tfsph_destroy", "tfsph_positions_to_cells", "tfsph_cells_to_positions",
+                     "tfsph_get_flags", "tfsph_signal_speed", "tfsph_cfl_dt", "tfsph_step_noalloc", "tfsph_destroy", "tfsph_positions_to_cells", "tfsph_cells_to_positions",
                      "tfsph_profile", "tfsph_profile_sampled", "tfsph_profile_read", "tfsph_set_kernel_variant", "tfsph_set_cells_per_block", "tfsph_step_graph", "tfsph_batch_workspace_size",
                      "tfsph_batch_init", "tfsph_batch_set_tuning", "tfsph_step_batched", "tfsph_step_batched_graph",
                      "tfsph_batch_get_flags", "tfsph_batch_destroy", "tfsph_adjoint_workspace_size",
@@ -211,6 +212,14 @@ def tfsph_cfl_dt(params: Params, signal_speed: float) -> float:
     out = ctypes.c_double(0.0)
     _check(lib().tfsph_cfl_dt(ctypes.byref(params), float(signal_speed), ctypes.byref(out)), "tfsph_cfl_dt")
     return float(out.value)
+
+
+def tfsph_step_noalloc(params: Params, state: StateC, n_steps: int, flags_out=None, one_phase_out=None,
+                       stream=None) -> None:
+    """tfsph_init + tfsph_step(n_steps) on the library's static workspace (no allocation);
+    flags_out / one_phase_out: optional device tensors (uint32 / int64, one element)."""
+    _check(lib().tfsph_step_noalloc(ctypes.byref(params), ctypes.byref(state), int(n_steps), _ptr(flags_out),
+                                    _ptr(one_phase_out), _stream_handle(stream)), "tfsph_step_noalloc")
 
 
 TFSPH_KERNEL_UPDATE, TFSPH_KERNEL_DENSITY, TFSPH_KERNEL_BIN, TFSPH_KERNEL_FORCE = 0, 1, 2, 3
@@ -326,8 +335,9 @@ def _torch_dtype(precision):
     return torch.float64 if precision == TFSPH_F64 else torch.float32
 
 
-class Simulation:
-    """A state + workspace + context for one problem on one GPU."""
+class DeviceState:
+    """Both phases of one problem in device arrays (torch tensors), in the cell-relative form
+    of the C ABI, with the C structs pointing at them.  No workspace and no context."""
 
     def __init__(self, prob, precision: int = TFSPH_F32, device="cuda", stream=None, dust_rho: bool = True):
         import torch
@@ -348,12 +358,6 @@ class Simulation:
             ph.mass_uniform = mu if mu is not None else 0.0
             self._upload(ph, src)
         self.state = StateC(self.gas.cstruct(), self.dust.cstruct())
-        self.ws_bytes = tfsph_workspace_size(self.params, g.n, d.n)
-        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        self._ws_off = (-base) % 256
-        self._ws = self.workspace[self._ws_off:]
-        self.ctx = tfsph_init(self.params, self.state, self._ws, self.ws_bytes, stream)
 
     def _upload(self, ph: DevicePhase, src):
         import torch
@@ -366,6 +370,21 @@ class Simulation:
             ph.mass.copy_(torch.as_tensor(src.m).to(ph.mass.dtype))
         if ph.energy is not None:
             ph.energy.copy_(torch.as_tensor(src.e).to(ph.energy.dtype))
+
+
+class Simulation(DeviceState):
+    """A state + workspace + context for one problem on one GPU."""
+
+    def __init__(self, prob, precision: int = TFSPH_F32, device="cuda", stream=None, dust_rho: bool = True):
+        import torch
+        super().__init__(prob, precision, device, stream, dust_rho)
+        g, d = prob.gas, prob.dust
+        self.ws_bytes = tfsph_workspace_size(self.params, g.n, d.n)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_off = (-base) % 256
+        self._ws = self.workspace[self._ws_off:]
+        self.ctx = tfsph_init(self.params, self.state, self._ws, self.ws_bytes, stream)
 
     def step(self, n: int = 1) -> None:
         tfsph_step(self.ctx, self.state, n, self.stream)
