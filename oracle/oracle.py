@@ -60,6 +60,10 @@ def lib():
         L.orc_step.restype = ctypes.c_int64
         L.orc_step_imex.argtypes = [P, PH, PH, ctypes.c_int32]
         L.orc_step_imex.restype = ctypes.c_int64
+        L.orc_step_mk.argtypes = [P, PH, PH, ctypes.c_int32]
+        L.orc_step_mk.restype = None
+        L.orc_step_isph.argtypes = [P, PH, PH, ctypes.c_int32]
+        L.orc_step_isph.restype = ctypes.c_int64
         L.orc_phase_density.argtypes = [P, PH, ctypes.c_void_p]
         L.orc_phase_forces.argtypes = [P, PH, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_canonicalize.argtypes = [P, PH]
@@ -182,15 +186,30 @@ def positions(p, ph: OPhase) -> np.ndarray:
     return np.stack([p.lo[k] + cs[k] * D[k] + ph.off[k] for k in range(dim)], axis=1)
 
 
+SCHEME_IDIC, SCHEME_IMEX2, SCHEME_MK, SCHEME_ISPH = 0, 1, 2, 3
+
+
 def step(p, gas: OPhase, dust: OPhase, nsteps: int = 1, cell_diag: Optional[np.ndarray] = None) -> int:
-    """Advance both phases ``nsteps`` steps in place; returns the one-phase-cell count (summed over
-    the drag solves).  ``p.scheme`` 0: the first-order IDIC step; 1: the second-order IMEX step
-    (ARS(2,2,2) with the drag in cell as its implicit part; ``cell_diag`` is not filled)."""
+    """Advance both phases ``nsteps`` steps in place.  ``p.scheme``:
+    0: the first-order IDIC step (returns the one-phase-cell count summed over the drag solves);
+    1: the second-order IMEX step (ARS(2,2,2) with the drag in cell as its implicit part; the same
+       count over both solves; ``cell_diag`` is not filled);
+    2: the explicit Monaghan-Kocharyan pairwise drag of Section 2.1 (returns 0);
+    3: the semi-implicit ISPH drag of Section 2.2 (returns the number of particles with no particle
+       of the other phase within 2h, summed over the steps).
+    On exit the dust ``rho`` holds the dust summation density of the last step for schemes 2 and 3."""
     sg, sd = gas._struct(), dust._struct()
-    if getattr(p, "scheme", 0) == 1:
-        if cell_diag is not None:
-            raise ValueError("cell_diag is only filled by the first-order step")
+    scheme = getattr(p, "scheme", 0)
+    if scheme != SCHEME_IDIC and cell_diag is not None:
+        raise ValueError("cell_diag is only filled by the first-order IDIC step")
+    if scheme == SCHEME_IMEX2:
         r = lib().orc_step_imex(ctypes.byref(params_struct(p)), ctypes.byref(sg), ctypes.byref(sd), int(nsteps))
+        return int(r)
+    if scheme == SCHEME_MK:
+        lib().orc_step_mk(ctypes.byref(params_struct(p)), ctypes.byref(sg), ctypes.byref(sd), int(nsteps))
+        return 0
+    if scheme == SCHEME_ISPH:
+        r = lib().orc_step_isph(ctypes.byref(params_struct(p)), ctypes.byref(sg), ctypes.byref(sd), int(nsteps))
         return int(r)
     ptr = cell_diag.ctypes.data if cell_diag is not None else None
     r = lib().orc_step(ctypes.byref(params_struct(p)), ctypes.byref(sg), ctypes.byref(sd), int(nsteps), ptr)

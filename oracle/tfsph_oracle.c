@@ -687,6 +687,269 @@ int64_t orc_step_imex(const orc_params *p, orc_phase *G, orc_phase *Dd, int32_t 
     return empty_total;
 }
 
+/* ------------------------------------------------------------------------ */
+/* The paper's two comparison schemes for the drag (Section 2.1 and 2.2).    */
+/* Both share the SPH part of the IDIC step above: summation densities, the  */
+/* gas pressure (and viscosity) terms of eq. (8) / (12), the gas energy      */
+/* equation, and the symplectic position update x^{n+1} = x^n + tau v^{n+1}. */
+/* They differ from it only in how the drag is computed.                     */
+/*                                                                           */
+/* The drag coefficient of a pair or a point follows the run's drag law:     */
+/*   K held constant (p->K > 0):       K;                                    */
+/*   t_stop held constant:             K = rho_d / t_stop (eq. 7), rho_d the */
+/*                                     dust density at the point;            */
+/*   Epstein, t_stop = tse / rho_g:    K = rho_g rho_d / tse (eq. 10 and 16  */
+/*                                     with c_s / (s rho_s) = 1 / tse).      */
+/* ------------------------------------------------------------------------ */
+static double orc_drag_K(const orc_params *p, double rho_g, double rho_d)
+{
+    if (p->K > 0.0) return p->K;
+    if (p->tse > 0.0) return rho_g * rho_d / p->tse;
+    return rho_d / p->tstop;
+}
+
+/* --- Monaghan-Kocharyan explicit pairwise drag, eqs. (8)-(10) ----------- */
+/* For gas a and dust j with r_ja = x_j - x_a, the pair term                 */
+/*   X_aj = K_aj / (rho_a rho_j) ((v_a - u_j) . r_ja) / (r_ja^2 + eta^2)     */
+/*          r_ja W(r_ja, h),          eta^2 = 0.001 h^2,                     */
+/* enters dv_a/dt as -sigma sum_j m_j X_aj and du_j/dt as +sigma sum_a m_a   */
+/* X_aj, with the velocities of level n.  sigma = 1 in 1D (stated); for d    */
+/* dimensions sigma = d, which makes the kernel average of r r / r^2 equal   */
+/* the identity, so a uniform relative velocity feels the continuum drag.    */
+typedef struct {
+    const orc_params *p; const orc_phase *A; const orc_phase *B;
+    const double *rhoA; const double *rhoB; int a_is_gas;
+    double acc[3];
+} orc_mk_ctx;
+
+static void orc_mk_pair(void *vctx, int64_t a, int64_t b, const double r[3])
+{
+    orc_mk_ctx *c = (orc_mk_ctx *)vctx;
+    const orc_params *p = c->p;
+    const int dim = p->dim;
+    const double rr2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double rr = sqrt(rr2);
+    if (!(rr < 2.0 * p->h)) return;
+    const int64_t na = c->A->n, nb = c->B->n;
+    /* gas velocity minus dust velocity, whichever phase is the target */
+    double dv[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < dim; ++d) {
+        const double va = c->A->vel[d * na + a], vb = c->B->vel[d * nb + b];
+        dv[d] = c->a_is_gas ? va - vb : vb - va;
+    }
+    const double rho_g = c->a_is_gas ? c->rhoA[a] : c->rhoB[b];
+    const double rho_d = c->a_is_gas ? c->rhoB[b] : c->rhoA[a];
+    double vr = 0.0;
+    for (int d = 0; d < dim; ++d) vr += dv[d] * r[d];
+    const double eta2 = 0.001 * p->h * p->h;
+    const double X = orc_drag_K(p, rho_g, rho_d) / (rho_g * rho_d) * vr / (rr2 + eta2) *
+                     orc_kernel_w(dim, p->h, rr);
+    const double sgn = c->a_is_gas ? -1.0 : 1.0;
+    for (int d = 0; d < dim; ++d) c->acc[d] += sgn * (double)dim * c->B->mass[b] * X * r[d];
+}
+
+/* drag accelerations of every particle of A from the particles of B */
+static void orc_mk_drag(const orc_params *p, const orc_phase *A, const orc_phase *B, const int64_t *startB,
+                        const double *rhoA, const double *rhoB, int a_is_gas, double *out /* [dim][nA] */)
+{
+    const int64_t n = A->n;
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < n; ++a) {
+        orc_mk_ctx c = {p, A, B, rhoA, rhoB, a_is_gas, {0.0, 0.0, 0.0}};
+        orc_for_neighbours(p, A, a, B, startB, orc_mk_pair, &c);
+        for (int d = 0; d < p->dim; ++d) out[d * n + a] = c.acc[d];
+    }
+}
+
+/* One explicit MK step n -> n+1 (first order in time): v^{n+1} = v^n + tau   */
+/* (pressure + g + drag), u^{n+1} = u^n + tau (g + drag), e^{n+1} = e^n + tau */
+/* de/dt, then x^{n+1} = x^n + tau v^{n+1}.  rho of both phases on exit is    */
+/* the summation density of level n.  Stable only for tau below about t_stop */
+/* (eq. 5).                                                                   */
+void orc_step_mk(const orc_params *p, orc_phase *G, orc_phase *Dd, int32_t nsteps)
+{
+    const int dim = p->dim;
+    const int64_t nc = orc_ncells(p);
+    const int64_t ng = G->n, nd = Dd->n, mg = ng ? ng : 1, md = nd ? nd : 1;
+    const double tau = p->dt;
+    int64_t *sg = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+    int64_t *sd = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+    double *acc = (double *)malloc(sizeof(double) * dim * mg);
+    double *dedt = (double *)malloc(sizeof(double) * mg);
+    double *dg = (double *)malloc(sizeof(double) * dim * mg);
+    double *dd = (double *)malloc(sizeof(double) * dim * md);
+    for (int32_t s = 0; s < nsteps; ++s) {
+        orc_canonicalize(p, G);
+        orc_canonicalize(p, Dd);
+        orc_sort(p, G);
+        orc_sort(p, Dd);
+        orc_cell_start(p, G, sg);
+        orc_cell_start(p, Dd, sd);
+        orc_density(p, G, sg, G->rho);
+        orc_density(p, Dd, sd, Dd->rho);
+        orc_gas_forces(p, G, sg, acc, G->energy ? dedt : NULL);
+        orc_mk_drag(p, G, Dd, sd, G->rho, Dd->rho, 1, dg);
+        orc_mk_drag(p, Dd, G, sg, Dd->rho, G->rho, 0, dd);
+        for (int d = 0; d < dim; ++d) {
+            for (int64_t a = 0; a < ng; ++a) G->vel[d * ng + a] += tau * (acc[d * ng + a] + dg[d * ng + a]);
+            for (int64_t j = 0; j < nd; ++j) Dd->vel[d * nd + j] += tau * (p->g[d] + dd[d * nd + j]);
+        }
+        if (G->energy)
+            for (int64_t a = 0; a < ng; ++a) G->energy[a] += tau * dedt[a];
+        for (int d = 0; d < dim; ++d) {
+            for (int64_t a = 0; a < ng; ++a) G->off[d * ng + a] += tau * G->vel[d * ng + a];
+            for (int64_t j = 0; j < nd; ++j) Dd->off[d * nd + j] += tau * Dd->vel[d * nd + j];
+        }
+        orc_canonicalize(p, G);
+        orc_canonicalize(p, Dd);
+    }
+    free(sg); free(sd); free(acc); free(dedt); free(dg); free(dd);
+}
+
+/* --- ISPH: semi-implicit drag with SPH interpolation, eqs. (11)-(16) ----- */
+/* At every particle the other phase's velocity is interpolated (eq. 11):    */
+/*   at dust j:  v_j = sum_a m_a (v_a / rho_a) W_aj;                         */
+/*   at gas a:   u_a = sum_j m_j (u_j / rho_j) W_ja;                         */
+/* with the other quantities the scheme marks as interpolated: the dust      */
+/* density at a gas point, rho_a,d = sum_j m_j W_ja; at a dust point the gas  */
+/* density rho_j,g = sum_a m_a W_aj and pressure p_j = sum_a m_a (p_a/rho_a)  */
+/* W_aj.  Every particle then solves its own two-velocity system with first- */
+/* order time differences (eqs. 12-15): with alpha = tau K / rho_g and       */
+/* beta = tau K / rho_d at the point, and the predictors v~ = v + tau A,     */
+/* u~ = u + tau g,                                                           */
+/*   (1 + alpha) v - alpha u = v~,   -beta v + (1 + beta) u = u~,            */
+/* the gas particle keeps v (eq. 12) and the dust particle keeps u (eq. 15). */
+/* At a gas particle A is its SPH acceleration of eq. (12); at a dust point  */
+/* it is the gas pressure gradient of eq. (14),                              */
+/*   A_j = -sum_i m_i (p_i / rho_i^2 + p_j / rho_j,g^2) grad_j W_ij + g.      */
+/* eq. (15) writes rho^n_{a,d} for the dust density, read as rho^n_{j,d}, the */
+/* dust particle's own.  A particle with no particle of the other phase      */
+/* within 2h gets no drag (counted in the return value).                     */
+typedef struct {
+    const orc_params *p; const orc_phase *B; const double *rhoB; const double *presB;
+    double rho, vel[3], pres;
+} orc_interp_ctx;
+
+static void orc_interp_pair(void *vctx, int64_t a, int64_t b, const double r[3])
+{
+    (void)a;
+    orc_interp_ctx *c = (orc_interp_ctx *)vctx;
+    const orc_params *p = c->p;
+    const double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(rr < 2.0 * p->h)) return;
+    const double mW = c->B->mass[b] * orc_kernel_w(p->dim, p->h, rr);
+    const int64_t nb = c->B->n;
+    c->rho += mW;
+    for (int d = 0; d < p->dim; ++d) c->vel[d] += mW * c->B->vel[d * nb + b] / c->rhoB[b];
+    if (c->presB) c->pres += mW * c->presB[b] / c->rhoB[b];
+}
+
+typedef struct {
+    const orc_params *p; const orc_phase *G; const double *rhoG; const double *presG;
+    double Pj;      /* p_j / rho_j,g^2 at the dust point */
+    double acc[3];
+} orc_dpg_ctx;
+
+static void orc_dust_pgrad_pair(void *vctx, int64_t j, int64_t i, const double r[3])
+{
+    (void)j;
+    orc_dpg_ctx *c = (orc_dpg_ctx *)vctx;
+    const orc_params *p = c->p;
+    const double rr2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double rr = sqrt(rr2);
+    if (!(rr < 2.0 * p->h) || rr == 0.0) return;
+    const double dw = orc_kernel_dw(p->dim, p->h, rr);
+    const double Pi = c->presG[i] / (c->rhoG[i] * c->rhoG[i]);
+    for (int d = 0; d < p->dim; ++d) c->acc[d] -= c->G->mass[i] * (Pi + c->Pj) * dw * r[d] / rr;
+}
+
+int64_t orc_step_isph(const orc_params *p, orc_phase *G, orc_phase *Dd, int32_t nsteps)
+{
+    const int dim = p->dim;
+    const int64_t nc = orc_ncells(p);
+    const int64_t ng = G->n, nd = Dd->n, mg = ng ? ng : 1, md = nd ? nd : 1;
+    const double tau = p->dt;
+    int64_t *sg = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+    int64_t *sd = (int64_t *)malloc(sizeof(int64_t) * (nc + 1));
+    double *acc = (double *)malloc(sizeof(double) * dim * mg);
+    double *dedt = (double *)malloc(sizeof(double) * mg);
+    double *pres = (double *)malloc(sizeof(double) * mg);
+    double *vnew = (double *)malloc(sizeof(double) * dim * mg);
+    double *unew = (double *)malloc(sizeof(double) * dim * md);
+    int64_t lonely_total = 0;
+    for (int32_t s = 0; s < nsteps; ++s) {
+        orc_canonicalize(p, G);
+        orc_canonicalize(p, Dd);
+        orc_sort(p, G);
+        orc_sort(p, Dd);
+        orc_cell_start(p, G, sg);
+        orc_cell_start(p, Dd, sd);
+        orc_density(p, G, sg, G->rho);
+        orc_density(p, Dd, sd, Dd->rho);
+        orc_gas_forces(p, G, sg, acc, G->energy ? dedt : NULL);
+        for (int64_t a = 0; a < ng; ++a) pres[a] = orc_pressure(p, G->rho[a], G->energy ? G->energy[a] : 0.0);
+        int64_t lonely = 0;
+        /* gas particles: eqs. (12)-(13) */
+#pragma omp parallel for schedule(static) reduction(+ : lonely)
+        for (int64_t a = 0; a < ng; ++a) {
+            orc_interp_ctx c = {p, Dd, Dd->rho, NULL, 0.0, {0.0, 0.0, 0.0}, 0.0};
+            orc_for_neighbours(p, G, a, Dd, sd, orc_interp_pair, &c);
+            const double rho_g = G->rho[a];
+            double alpha = 0.0, beta = 0.0;
+            if (c.rho > 0.0) {
+                const double K = orc_drag_K(p, rho_g, c.rho);
+                alpha = tau * K / rho_g;
+                beta = tau * K / c.rho;
+            } else {
+                lonely += 1;
+            }
+            const double D = 1.0 + alpha + beta;
+            for (int d = 0; d < dim; ++d) {
+                const double vt = G->vel[d * ng + a] + tau * acc[d * ng + a];
+                const double ut = (c.rho > 0.0 ? c.vel[d] : 0.0) + tau * p->g[d];
+                vnew[d * ng + a] = ((1.0 + beta) * vt + alpha * ut) / D;
+            }
+        }
+        /* dust particles: eqs. (14)-(15) */
+#pragma omp parallel for schedule(static) reduction(+ : lonely)
+        for (int64_t j = 0; j < nd; ++j) {
+            orc_interp_ctx c = {p, G, G->rho, pres, 0.0, {0.0, 0.0, 0.0}, 0.0};
+            orc_for_neighbours(p, Dd, j, G, sg, orc_interp_pair, &c);
+            const double rho_d = Dd->rho[j];
+            double alpha = 0.0, beta = 0.0, Aj[3] = {0.0, 0.0, 0.0};
+            if (c.rho > 0.0) {
+                orc_dpg_ctx q = {p, G, G->rho, pres, c.pres / (c.rho * c.rho), {0.0, 0.0, 0.0}};
+                orc_for_neighbours(p, Dd, j, G, sg, orc_dust_pgrad_pair, &q);
+                for (int d = 0; d < dim; ++d) Aj[d] = q.acc[d];
+                const double K = orc_drag_K(p, c.rho, rho_d);
+                alpha = tau * K / c.rho;
+                beta = tau * K / rho_d;
+            } else {
+                lonely += 1;
+            }
+            const double D = 1.0 + alpha + beta;
+            for (int d = 0; d < dim; ++d) {
+                const double vt = c.vel[d] + tau * (Aj[d] + p->g[d]);
+                const double ut = Dd->vel[d * nd + j] + tau * p->g[d];
+                unew[d * nd + j] = (beta * vt + (1.0 + alpha) * ut) / D;
+            }
+        }
+        lonely_total += lonely;
+        memcpy(G->vel, vnew, sizeof(double) * dim * ng);
+        memcpy(Dd->vel, unew, sizeof(double) * dim * nd);
+        if (G->energy)
+            for (int64_t a = 0; a < ng; ++a) G->energy[a] += tau * dedt[a];
+        for (int d = 0; d < dim; ++d) {
+            for (int64_t a = 0; a < ng; ++a) G->off[d * ng + a] += tau * G->vel[d * ng + a];
+            for (int64_t j = 0; j < nd; ++j) Dd->off[d * nd + j] += tau * Dd->vel[d * nd + j];
+        }
+        orc_canonicalize(p, G);
+        orc_canonicalize(p, Dd);
+    }
+    free(sg); free(sd); free(acc); free(dedt); free(pres); free(vnew); free(unew);
+    return lonely_total;
+}
+
 /* Density sums on the phase's current positions (sorts the phase first). */
 void orc_phase_density(const orc_params *p, orc_phase *ph, double *rho_out)
 {

@@ -313,10 +313,10 @@ def paper_dustywave(h: float = 0.01, dt: float = 0.00025, n: int = 600, K: float
                     amp: float = 1e-4, t_end: float = 0.5, scheme: int = 0) -> Problem:
     """The Dustywave runs of Table 1: N = 2 x 600 particles on [0, 1), K = 500 held constant
     (eq. 22, dust/gas ratio 1, so t_stop = 0.002), c_s = 1, the given h and tau, to t = 0.5.
-    Drag cells are h wide.  The amplitude is not printed; 1e-4 keeps the wave linear."""
+    Drag cells are one particle spacing wide, so each holds one gas and one dust particle.
+    The amplitude is not printed; 1e-4 keeps the wave linear."""
     prob = dusty_wave(n_side=n, dim=1, amp=amp, eps=eps, c_s=1.0, t_stop=eps / K, h_over_dx=h * n,
-                      cells_per_axis=int(round(1.0 / h)), steps=int(round(t_end / dt)),
-                      name=f"paper_dustywave_h{h:g}")
+                      cells_per_axis=n, steps=int(round(t_end / dt)), name=f"paper_dustywave_h{h:g}")
     prob.params = prob.params.replace(dt=dt, K=K, scheme=scheme)
     return prob
 
@@ -328,7 +328,7 @@ def paper_dustyshock(h: float = 0.01, dt: float = 0.000025, n_left: int = 880, n
     the spacing jumps 8:1 with the Sod densities 1 | 0.125 (pressures 1 | 0.1), on the mirrored
     periodic tube [-0.5, 0.5) (left state on [-0.5, 0)); gas and dust share the lattice; K = 500
     held constant (t_stop = 0.002 | 0.00025), the given h and tau, to t = 0.2.  Drag cells are
-    h wide.  Adiabatic gas with Monaghan-Gingold viscosity."""
+    one left-state spacing wide.  Adiabatic gas with Monaghan-Gingold viscosity."""
     rho_l, p_l, rho_r, p_r = 1.0, 1.0, 0.125, 0.1
     dxl, dxr = 0.5 / n_left, 0.5 / n_right
     x = np.concatenate([-0.5 + (np.arange(n_left) + 0.5) * dxl, (np.arange(n_right) + 0.5) * dxr])[:, None]
@@ -342,7 +342,7 @@ def paper_dustyshock(h: float = 0.01, dt: float = 0.000025, n_left: int = 880, n
     gas = Phase(x=x.copy(), v=np.zeros((n, 1)), m=m.copy(), id=ids.copy(), e=e)
     dust = Phase(x=x.copy(), v=np.zeros((n, 1)), m=eps * m, id=ids.copy())
     c_max = math.sqrt(gamma * p_l / rho_l)
-    params = Params(dim=1, n_cells=(int(round(1.0 / h)), 1, 1), lo=(-0.5, 0.0, 0.0), hi=(0.5, 1.0, 1.0), h=h,
+    params = Params(dim=1, n_cells=(2 * n_left, 1, 1), lo=(-0.5, 0.0, 0.0), hi=(0.5, 1.0, 1.0), h=h,
                     c_s=c_max, t_stop=eps * rho_r / K, dt=dt, eos=ADIABATIC, gamma=gamma,
                     av_alpha=av_alpha, av_beta=av_beta, K=K, scheme=scheme)
     extra = dict(rho_l=rho_l, p_l=p_l, rho_r=rho_r, p_r=p_r, eps=eps, gamma=gamma)
