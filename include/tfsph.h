@@ -63,7 +63,7 @@ enum {
 
 enum { TFSPH_F32 = 0, TFSPH_F64 = 1 };
 enum { TFSPH_ISOTHERMAL = 0, TFSPH_ADIABATIC = 1 };
-enum { TFSPH_SCHEME_IDIC = 0, TFSPH_SCHEME_IMEX2 = 1 };
+enum { TFSPH_SCHEME_IDIC = 0, TFSPH_SCHEME_IMEX2 = 1, TFSPH_SCHEME_MK = 2, TFSPH_SCHEME_ISPH = 3 };
 
 /* Run parameters; symbols follow the paper. */
 typedef struct {
@@ -100,8 +100,28 @@ typedef struct {
                                gamma tau (gamma = 1 - 1/sqrt(2)) on that stage's volumes.  Per step:
                                three binnings, two density and force passes, two drag solves; rho
                                on exit is the density at the start of the step and the one-phase
-                               count covers both solves.  The batched and adjoint entry points
-                               accept TFSPH_SCHEME_IDIC only (TFSPH_E_UNSUPPORTED otherwise). */
+                               count covers both solves.
+                               The paper's two comparison schemes, with no drag volumes (the cells
+                               only serve the neighbour search):
+                               TFSPH_SCHEME_MK: the explicit pairwise drag of Monaghan & Kocharyan,
+                               Section 2.1, eqs. (8)-(10): for gas a and dust j,
+                               X = K_aj/(rho_a rho_j) ((v_a - u_j).r) r W(r)/(r^2 + eta^2),
+                               eta^2 = 0.001 h^2, enters dv_a/dt as -sigma sum_j m_j X and du_j/dt
+                               as +sigma sum_a m_a X with the velocities of level n, sigma = dim;
+                               v += tau (A + g + drag), u += tau (g + drag); stable for tau below
+                               about t_stop (eq. 5).
+                               TFSPH_SCHEME_ISPH: the semi-implicit drag with SPH interpolation,
+                               Section 2.2, eqs. (11)-(16): each particle interpolates the other
+                               phase's velocity and density (dust points also the gas pressure)
+                               and solves its own 2x2 system with alpha = tau K/rho_g,
+                               beta = tau K/rho_d at the point; gas keeps v, dust keeps u.  A
+                               particle with no particle of the other phase within 2h gets no drag
+                               and is counted as a one-phase cell.
+                               In all schemes K follows the drag law: K (K > 0), rho_d/t_stop, or
+                               rho_g rho_d/t_stop_epstein; on exit both rho arrays (dust rho when
+                               given) hold the summation densities of the last step.
+                               The batched and adjoint entry points accept TFSPH_SCHEME_IDIC only
+                               (TFSPH_E_UNSUPPORTED otherwise). */
     double cfl;             /* Courant number CFL of eq. (4) (the paper takes CFL < 1).  0: no check.
                                > 0: at the end of every step each particle's signal speed
                                s = max(|v|, c) is compared with CFL h / tau, where c is the gas sound
@@ -141,7 +161,7 @@ const char *tfsph_last_error(void);
 /* Host-only check of a parameter set (no device call).  Fails with
  * TFSPH_E_INVALID_ARG when: dim not in 1..3; a cell count < 1 or, on an
  * axis >= dim, != 1; box_hi <= box_lo; h <= 0; an axis with fewer than
- * 2W+1 cells where W = ceil(2h / Delta) is the neighbour window; W > 8;
+ * 2W+1 cells where W = ceil(2h / Delta) is the neighbour window; W > 128;
  * K or t_stop_epstein < 0 or non-finite, or both > 0; both 0 with t_stop <= 0
  * or non-finite; dt <= 0 or non-finite; isothermal with c_s <= 0; adiabatic
  * with gamma <= 1; negative viscosity coefficients; unknown eos/precision;

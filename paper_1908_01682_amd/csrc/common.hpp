@@ -10,10 +10,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace tfsph {
 
 constexpr int kBlock = 256;          // threads per block of the streaming kernels
-constexpr int kMaxWindow = 8;        // largest neighbour window half-width (cells)
+constexpr int kMaxWindow = 128;      // largest neighbour window half-width (cells)
 
 // --------------------------------------------------------------------------
 // Smoothing kernel W(h, r) of Section 2.1: M4 cubic spline, support 2h,
@@ -77,6 +79,24 @@ __device__ __forceinline__ R spline_df(R q)
     __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && (KIND) != 2) ? 7 : 1)))
 #define TFSPH_STAGE_OCCUPANCY(R, KIND) TFSPH_FORCE_OCCUPANCY(R, KIND)
 #endif
+// Arithmetic of the pressure-force pair sums of an FP32 state:
+// 0: FP32 separations, terms and sums; 1: FP32 terms summed in FP64;
+// 2: FP64 separations, terms and sums (from the FP32 offsets).
+#ifndef TFSPH_FORCE_ARITH
+#define TFSPH_FORCE_ARITH 0
+#endif
+template <typename R>
+struct ForceArith {
+    using S = R;     // separations
+    using T = R;     // pair terms
+    using A = R;     // sums
+};
+template <>
+struct ForceArith<float> {
+    using S = typename std::conditional<(TFSPH_FORCE_ARITH >= 2), double, float>::type;
+    using T = typename std::conditional<(TFSPH_FORCE_ARITH == 2), double, float>::type;
+    using A = typename std::conditional<(TFSPH_FORCE_ARITH >= 1), double, float>::type;
+};
 constexpr int kChunk = TFSPH_CHUNK;
 constexpr int kScanChunk = TFSPH_SCAN_CHUNK;
 constexpr int kWalk = TFSPH_WALK;
@@ -116,6 +136,9 @@ struct Phys {
     R eta2;              // 0.01 h^2 in the viscosity denominator
     R h;
     R vlim2;             // Courant bound of eq. (4): (CFL h / tau)^2; 0 = no check
+    // the drag coefficient K of eq. (7) at a point of the pairwise schemes, by drag law:
+    // law 0: rho_d / t_stop; law 1: K; law 2: rho_g rho_d / T_E
+    R inv_tstop, Kc, inv_te;
 };
 
 // Caller-owned arrays of one phase.

@@ -153,6 +153,9 @@ Phys<R> make_phys(const tfsph_params *p)
     P.eta2 = R(0.01 * p->h * p->h);
     P.h = R(p->h);
     P.vlim2 = p->cfl > 0.0 ? R((p->cfl * p->h / p->dt) * (p->cfl * p->h / p->dt)) : R(0);
+    P.inv_tstop = P.drag_law == 0 ? R(1.0 / p->t_stop) : R(0);
+    P.Kc = R(p->K);
+    P.inv_te = P.drag_law == 2 ? R(1.0 / p->t_stop_epstein) : R(0);
     return P;
 }
 

@@ -1,0 +1,248 @@
+// The paper's two comparison schemes for the drag, both without drag volumes
+// (Sections 2.1 and 2.2).  They share the SPH part of the IDIC step (binning,
+// summation densities, the gas pressure / viscosity terms and energy
+// equation, x^{n+1} = x^n + tau v^{n+1}) and replace its cell solve:
+//
+// MK, eqs. (8)-(10): explicit pairwise drag with the velocities of level n.
+//   For gas a and dust j, X_aj = K_aj / (rho_a rho_j) ((v_a - u_j) . r)
+//   / (r^2 + eta^2) r W(r), eta^2 = 0.001 h^2;
+//   dv_a/dt gets -sigma sum_j m_j X_aj, du_j/dt gets +sigma sum_a m_a X_aj,
+//   with sigma = the dimension (the paper's sigma = 1 in 1D; sigma = d makes
+//   the kernel average of r r / r^2 the identity).
+// ISPH, eqs. (11)-(16): every particle interpolates the other phase at its
+//   own position (velocity, density; at a dust point also the gas pressure)
+//   and solves its own two-velocity system with first-order differences:
+//   alpha = tau K / rho_g, beta = tau K / rho_d at the point, predictors
+//   v~ = v + tau A and u~ = u + tau g; the gas keeps
+//   v = ((1 + beta) v~ + alpha u~) / D, the dust u = (beta v~ + (1 + alpha) u~)
+//   / D, D = 1 + alpha + beta.  At a dust point A is the gas pressure gradient
+//   -sum_i m_i (P_i + P_j) grad_j W_ij + g, P = p / rho^2, summed here as
+//   -(sum_i m_i P_i grad W + P_j sum_i m_i grad W).
+//
+// All sums are gathers over the other phase's window in the sorted
+// workspace (no atomics), so results are bitwise reproducible.  One thread
+// per particle; each writes its particle's new state to the caller's arrays
+// at its sorted index, as k_update does.
+#pragma once
+
+#include "sph.hpp"
+
+namespace tfsph {
+
+enum { kPairMK = 0, kPairISPH = 1 };
+
+// K / (rho_g rho_d) and K of eq. (7) at a point or a pair, by drag law
+template <typename R>
+__device__ __forceinline__ R drag_coef(const Phys<R> &Ph, R rho_g, R rho_d)
+{
+    if (Ph.drag_law == 1) return Ph.Kc;
+    if (Ph.drag_law == 2) return rho_g * rho_d * Ph.inv_te;
+    return rho_d * Ph.inv_tstop;
+}
+
+// x^{n+1} = x^n + tau v^{n+1}, carry, and the caller's arrays at sorted index i
+template <typename R, int DIM>
+__device__ __forceinline__ bool store_moved(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &S,
+                                            const Phase<R> &P, int i, const R v[3], R &s2)
+{
+    int cc[3];
+    split_cell(G, S.cell[i], cc[0], cc[1], cc[2]);
+    const R4<R> me = S.pos[i];
+    const R oo[3] = {me.x, me.y, me.z};
+    bool ok = true;
+    R v2 = R(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        R o = oo[d] + Ph.tau * v[d];
+        ok &= finite_r(v[d]);
+        ok &= carry(o, cc[d], G.delta[d], G.nc[d]);
+        P.vel[d][i] = v[d];
+        P.off[d][i] = o;
+        v2 += v[d] * v[d];
+    }
+    s2 = fmax(s2, v2);
+    P.cell[i] = join_cell(G, cc[0], cc[1], cc[2]);
+    P.id[i] = S.id[i];
+    if (S.has_mass && P.mass) const_cast<R *>(P.mass)[i] = me.w;
+    if (P.rho) P.rho[i] = S.rho[i];
+    return ok;
+}
+
+// One gas particle of MK or ISPH: pressure terms (masks of the density pass
+// when present), the drag from the dust window, update, move.
+template <typename R, int DIM, int KIND, int SCHEME>
+__global__ void __launch_bounds__(kBlock)
+k_pair_gas(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Flags F)
+{
+    const int a = xcd_block(gridDim.x) * kBlock + threadIdx.x;
+    R s2 = signal_floor(Ph);
+    int bad = 0, lonely = 0;
+    if (a < Sg.n) {
+        R acc[3], dedt;
+        gas_force_at<R, DIM, KIND>(G, Ph, Sg, a, acc, dedt);
+        int cx, cy, cz;
+        split_cell(G, Sg.cell[a], cx, cy, cz);
+        const R4<R> me = Sg.pos[a];
+        const R oa[3] = {me.x, me.y, me.z};
+        const R va[3] = {Sg.vel[0][a], DIM > 1 ? Sg.vel[1][a] : R(0), DIM > 2 ? Sg.vel[2][a] : R(0)};
+        const R rho_a = Sg.rho[a];
+        R vn[3];
+        if constexpr (SCHEME == kPairMK) {
+            const R eta2 = R(0.001) * G.h * G.h;
+            R dx = R(0), dy = R(0), dz = R(0);
+            for_window<R, DIM>(G, cx, cy, cz, oa, Sd.start, Sd.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
+                if (!ok) return;
+                const R r2 = rx * rx + ry * ry + rz * rz;
+                const R w = spline_f(fsqrt(r2) * G.inv_h);
+                const R rho_b = Sd.rho[b];
+                const R vr = (va[0] - Sd.vel[0][b]) * rx + (DIM > 1 ? (va[1] - Sd.vel[1][b]) * ry : R(0)) +
+                             (DIM > 2 ? (va[2] - Sd.vel[2][b]) * rz : R(0));
+                const R X = q.w * drag_coef(Ph, rho_a, rho_b) / (rho_a * rho_b) * vr / (r2 + eta2) * w;
+                dx -= X * rx;
+                dy -= X * ry;
+                dz -= X * rz;
+            });
+            const R sw = R(DIM) * G.wnorm;
+            const R dr[3] = {dx * sw, dy * sw, dz * sw};
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) vn[d] = va[d] + Ph.tau * (acc[d] + Ph.g[d] + dr[d]);
+        } else {
+            R rd = R(0), ux = R(0), uy = R(0), uz = R(0);
+            for_window<R, DIM>(G, cx, cy, cz, oa, Sd.start, Sd.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
+                if (!ok) return;
+                const R r2 = rx * rx + ry * ry + rz * rz;
+                const R mw = q.w * spline_f(fsqrt(r2) * G.inv_h);
+                const R f = mw / Sd.rho[b];
+                rd += mw;
+                ux += f * Sd.vel[0][b];
+                if (DIM > 1) uy += f * Sd.vel[1][b];
+                if (DIM > 2) uz += f * Sd.vel[2][b];
+            });
+            rd *= G.wnorm;
+            const R ua[3] = {ux * G.wnorm, uy * G.wnorm, uz * G.wnorm};
+            R alpha = R(0), beta = R(0);
+            if (rd > R(0)) {
+                const R K = drag_coef(Ph, rho_a, rd);
+                alpha = Ph.tau * K / rho_a;
+                beta = Ph.tau * K / rd;
+            } else {
+                lonely = 1;
+            }
+            const R D = R(1) + alpha + beta;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                const R vt = va[d] + Ph.tau * (acc[d] + Ph.g[d]);
+                const R ut = (rd > R(0) ? ua[d] : R(0)) + Ph.tau * Ph.g[d];
+                vn[d] = ((R(1) + beta) * vt + alpha * ut) / D;
+            }
+        }
+        if (Sg.energy) {
+            const R e = Sg.energy[a] + Ph.tau * dedt;
+            Pg.energy[a] = e;
+            if (Ph.eos != 0) s2 = fmax(s2, Ph.ggm1 * e);
+        }
+        bad = !store_moved<R, DIM>(G, Ph, Sg, Pg, a, vn, s2);
+    }
+    publish_speed(Ph, F, s2);
+    if (bad) atomicOr(F.word, 1u);
+    if (lonely) {
+        atomicOr(F.word, 2u);
+        atomicAdd(F.one_phase, 1ull);
+    }
+}
+
+// One dust particle of MK or ISPH: the drag (MK) or the interpolated gas state
+// and pressure gradient (ISPH) from the gas window, update, move.  The gas
+// records read are frc = (ox, oy, oz, P = p / rho^2) of the density pass.
+template <typename R, int DIM, int SCHEME>
+__global__ void __launch_bounds__(kBlock)
+k_pair_dust(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pd, Flags F)
+{
+    const int j = xcd_block(gridDim.x) * kBlock + threadIdx.x;
+    R s2 = signal_floor(Ph);
+    int bad = 0, lonely = 0;
+    if (j < Sd.n) {
+        int cx, cy, cz;
+        split_cell(G, Sd.cell[j], cx, cy, cz);
+        const R4<R> me = Sd.pos[j];
+        const R oj[3] = {me.x, me.y, me.z};
+        const R uj[3] = {Sd.vel[0][j], DIM > 1 ? Sd.vel[1][j] : R(0), DIM > 2 ? Sd.vel[2][j] : R(0)};
+        const R rho_j = Sd.rho[j];
+        R un[3];
+        if constexpr (SCHEME == kPairMK) {
+            const R eta2 = R(0.001) * G.h * G.h;
+            R dx = R(0), dy = R(0), dz = R(0);
+            for_window<R, DIM>(G, cx, cy, cz, oj, Sg.start, Sg.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
+                if (!ok) return;
+                const R r2 = rx * rx + ry * ry + rz * rz;
+                const R w = spline_f(fsqrt(r2) * G.inv_h);
+                const R rho_b = Sg.rho[b];
+                const R vr = (Sg.vel[0][b] - uj[0]) * rx + (DIM > 1 ? (Sg.vel[1][b] - uj[1]) * ry : R(0)) +
+                             (DIM > 2 ? (Sg.vel[2][b] - uj[2]) * rz : R(0));
+                const R X = q.w * drag_coef(Ph, rho_b, rho_j) / (rho_b * rho_j) * vr / (r2 + eta2) * w;
+                dx += X * rx;
+                dy += X * ry;
+                dz += X * rz;
+            });
+            const R sw = R(DIM) * G.wnorm;
+            const R dr[3] = {dx * sw, dy * sw, dz * sw};
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) un[d] = uj[d] + Ph.tau * (Ph.g[d] + dr[d]);
+        } else {
+            R rg = R(0), pj = R(0), vx = R(0), vy = R(0), vz = R(0);
+            R gp[3] = {R(0), R(0), R(0)}, g1[3] = {R(0), R(0), R(0)};
+            for_window<R, DIM>(G, cx, cy, cz, oj, Sg.start, Sg.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
+                if (!ok) return;
+                const R r2 = rx * rx + ry * ry + rz * rz;
+                const R r = fsqrt(r2);
+                const R qq = r * G.inv_h;
+                const R m = Sg.pos[b].w;
+                const R rho_b = Sg.rho[b];
+                const R mw = m * spline_f(qq);
+                const R f = mw / rho_b;
+                rg += mw;
+                pj += f * (q.w * rho_b * rho_b);            // p_b / rho_b W m_b
+                vx += f * Sg.vel[0][b];
+                if (DIM > 1) vy += f * Sg.vel[1][b];
+                if (DIM > 2) vz += f * Sg.vel[2][b];
+                const R ir = r2 > R(0) ? frcp(r) : R(0);
+                const R md = m * spline_df(qq) * ir;           // m_b grad_j W / (gnorm r_vec)
+                const R rr[3] = {rx, ry, rz};
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) {
+                    gp[d] += md * q.w * rr[d];
+                    g1[d] += md * rr[d];
+                }
+            });
+            rg *= G.wnorm;
+            R alpha = R(0), beta = R(0), A[3] = {R(0), R(0), R(0)};
+            const R vj[3] = {vx * G.wnorm, vy * G.wnorm, vz * G.wnorm};
+            if (rg > R(0)) {
+                const R Pj = pj * G.wnorm / (rg * rg);
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) A[d] = -(gp[d] + Pj * g1[d]) * G.gnorm;
+                const R K = drag_coef(Ph, rg, rho_j);
+                alpha = Ph.tau * K / rg;
+                beta = Ph.tau * K / rho_j;
+            } else {
+                lonely = 1;
+            }
+            const R D = R(1) + alpha + beta;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                const R vt = vj[d] + Ph.tau * (A[d] + Ph.g[d]);
+                const R ut = uj[d] + Ph.tau * Ph.g[d];
+                un[d] = (beta * vt + (R(1) + alpha) * ut) / D;
+            }
+        }
+        bad = !store_moved<R, DIM>(G, Ph, Sd, Pd, j, un, s2);
+    }
+    publish_speed(Ph, F, s2);
+    if (bad) atomicOr(F.word, 1u);
+    if (lonely) {
+        atomicOr(F.word, 2u);
+        atomicAdd(F.one_phase, 1ull);
+    }
+}
+
+}  // namespace tfsph

@@ -36,8 +36,8 @@ __device__ __forceinline__ void load_chunk(const V *__restrict__ data, int b, in
 // so one memory wait serves several candidates; fn(b, q, rx, ry, rz, valid)
 // gets the record, r = x_a - x_b and whether b is a real candidate (false
 // past b1 in the last chunk; such records are finite but belong elsewhere).
-template <typename R, int DIM, bool Padded = true, typename Fn>
-__device__ __forceinline__ void visit_range(int b0, int b1, const R4<R> *__restrict__ data, R rx0, R ry0, R rz0,
+template <typename R, int DIM, bool Padded = true, typename T = R, typename Fn>
+__device__ __forceinline__ void visit_range(int b0, int b1, const R4<R> *__restrict__ data, T rx0, T ry0, T rz0,
                                             Fn &fn)
 {
     for (int b = b0; b < b1; b += kScanChunk) {
@@ -46,9 +46,9 @@ __device__ __forceinline__ void visit_range(int b0, int b1, const R4<R> *__restr
         const int rem = b1 - b;        // >= 1: candidate k of the chunk is real when k < rem
 #pragma unroll
         for (int k = 0; k < kScanChunk; ++k) {
-            const R rx = rx0 - q[k].x;
-            const R ry = DIM > 1 ? ry0 - q[k].y : R(0);
-            const R rz = DIM > 2 ? rz0 - q[k].z : R(0);
+            const T rx = rx0 - T(q[k].x);
+            const T ry = DIM > 1 ? ry0 - T(q[k].y) : T(0);
+            const T rz = DIM > 2 ? rz0 - T(q[k].z) : T(0);
             fn(b + k, q[k], rx, ry, rz, k == 0 || k < rem);
         }
     }
@@ -85,7 +85,7 @@ __device__ __forceinline__ void row_offsets(int l, int wy, int wz, int &dy, int 
 // pair number, the cell ranges of its two rows (bs[t], be[t] as row_ranges;
 // the centre row's partner is empty) and the y / z parts of x_a - x_b of each
 // row before the candidate's own offset is subtracted.
-template <typename R, int DIM, int WX, typename PairFn>
+template <typename R, int DIM, int WX, typename T = R, typename PairFn>
 __device__ __forceinline__ void for_window_pairs(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
                                                  const int *__restrict__ start, PairFn &&pair_fn)
 {
@@ -94,7 +94,7 @@ __device__ __forceinline__ void for_window_pairs(const Geom<R> &G, int cx, int c
     const int nrow = (2 * wy + 1) * (2 * wz + 1);
     for (int i = 0; 2 * i < nrow; ++i) {
         int bs[2][2 * WX + 1], be[2][2 * WX + 1];
-        R ry0[2], rz0[2];
+        T ry0[2], rz0[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const int l = t ? nrow - 1 - i : i;
@@ -109,8 +109,8 @@ __device__ __forceinline__ void for_window_pairs(const Geom<R> &G, int cx, int c
             row_offsets(l, wy, wz, dy, dz);
             const int z = DIM > 2 ? wrap_index(cz + dz, G.nc[2]) : 0;
             const int y = DIM > 1 ? wrap_index(cy + dy, G.nc[1]) : 0;
-            rz0[t] = DIM > 2 ? oa[2] - R(dz) * G.delta[2] : R(0);
-            ry0[t] = DIM > 1 ? oa[1] - R(dy) * G.delta[1] : R(0);
+            rz0[t] = DIM > 2 ? T(oa[2]) - T(dz) * T(G.delta[2]) : T(0);
+            ry0[t] = DIM > 1 ? T(oa[1]) - T(dy) * T(G.delta[1]) : T(0);
             row_ranges<WX>(G, cx, G.nc[0] * (y + G.nc[1] * z), start, bs[t], be[t]);
         }
         pair_fn(i, bs, be, ry0, rz0);
@@ -139,19 +139,20 @@ __device__ __forceinline__ bool with_row_width(int wx, F &&f)
 // offsets oa[] in cell (cx, cy, cz).  Order: rows in the pair order of
 // for_window_pairs(), inside a row x offsets ascending, then cell order.  The
 // cell ranges of a pair of rows are loaded together before it is walked.
-template <typename R, int DIM, typename Fn>
+template <typename R, int DIM, typename T = R, typename Fn>
 __device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
                                            const int *__restrict__ start, const R4<R> *__restrict__ data, Fn &&fn)
 {
     const bool rows = with_row_width(G.win[0], [&](auto W) {
         constexpr int WX = decltype(W)::value;
-        for_window_pairs<R, DIM, WX>(G, cx, cy, cz, oa, start, [&](int, auto &bs, auto &be, const R *ry0, const R *rz0) {
+        for_window_pairs<R, DIM, WX, T>(G, cx, cy, cz, oa, start, [&](int, auto &bs, auto &be, const T *ry0,
+                                                                       const T *rz0) {
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
 #pragma unroll
                 for (int k = 0; k <= 2 * WX; ++k) {
-                    const R rx0 = oa[0] - R(k - WX) * G.delta[0];
-                    visit_range<R, DIM>(bs[t][k], be[t][k], data, rx0, ry0[t], rz0[t], fn);
+                    const T rx0 = T(oa[0]) - T(k - WX) * T(G.delta[0]);
+                    visit_range<R, DIM, true, T>(bs[t][k], be[t][k], data, rx0, ry0[t], rz0[t], fn);
                 }
             }
         });
@@ -168,14 +169,14 @@ __device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int
             int dy, dz;
             row_offsets(l, wy, wz, dy, dz);
             const int z = DIM > 2 ? wrap_index(cz + dz, G.nc[2]) : 0;
-            const R rz0 = DIM > 2 ? oa[2] - R(dz) * G.delta[2] : R(0);
+            const T rz0 = DIM > 2 ? T(oa[2]) - T(dz) * T(G.delta[2]) : T(0);
             const int y = DIM > 1 ? wrap_index(cy + dy, G.nc[1]) : 0;
-            const R ry0 = DIM > 1 ? oa[1] - R(dy) * G.delta[1] : R(0);
+            const T ry0 = DIM > 1 ? T(oa[1]) - T(dy) * T(G.delta[1]) : T(0);
             const int row = G.nc[0] * (y + G.nc[1] * z);
             for (int dx = -wx; dx <= wx; ++dx) {
                 const int lin = wrap_index(cx + dx, G.nc[0]) + row;
-                const R rx0 = oa[0] - R(dx) * G.delta[0];
-                visit_range<R, DIM>(start[lin], start[lin + 1], data, rx0, ry0, rz0, fn);
+                const T rx0 = T(oa[0]) - T(dx) * T(G.delta[0]);
+                visit_range<R, DIM, true, T>(start[lin], start[lin + 1], data, rx0, ry0, rz0, fn);
             }
         }
     }
@@ -258,7 +259,7 @@ __device__ __forceinline__ void for_window_recording(const Geom<R> &G, int cx, i
 // whose segment starts at or before p.  When no lane's window wraps around
 // the box along x, the cells of every row are consecutive in the sorted
 // order, so one index shift serves the whole row.
-template <typename R, int DIM, typename Fn>
+template <typename R, int DIM, typename T = R, typename Fn>
 __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
                                                const int *__restrict__ start, const R4<R> *__restrict__ data,
                                                const unsigned long long *__restrict__ mask, int stride, Fn &&fn)
@@ -267,12 +268,12 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
         constexpr int WX = decltype(W)::value;
         constexpr int NC = 2 * WX + 1;          // cells per row
         constexpr int NS = 2 * NC;              // segments per pair
-        R rx0[NC];
+        T rx0[NC];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) rx0[k] = oa[0] - R(k - WX) * G.delta[0];
+        for (int k = 0; k < NC; ++k) rx0[k] = T(oa[0]) - T(k - WX) * T(G.delta[0]);
         const bool wave_rows_contiguous = __ballot(cx < WX || cx + WX >= G.nc[0]) == 0ull;
-        for_window_pairs<R, DIM, WX>(G, cx, cy, cz, oa, start, [&](int i, auto &bs, auto &be, const R *ry0,
-                                                                    const R *rz0) {
+        for_window_pairs<R, DIM, WX, T>(G, cx, cy, cz, oa, start, [&](int i, auto &bs, auto &be, const T *ry0,
+                                                                       const T *rz0) {
             // first walking position of each segment and its index shift
             int P[NS], shift[NS];
             int len = 0;
@@ -287,7 +288,8 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
 #pragma unroll
                 for (int t = 0; t < 2; ++t)
 #pragma unroll
-                    for (int k = 0; k < NC; ++k) visit_range<R, DIM>(bs[t][k], be[t][k], data, rx0[k], ry0[t], rz0[t], fn);
+                    for (int k = 0; k < NC; ++k)
+                        visit_range<R, DIM, true, T>(bs[t][k], be[t][k], data, rx0[k], ry0[t], rz0[t], fn);
                 return;
             }
             const unsigned long long m0 = mask[size_t(i) * stride];
@@ -297,7 +299,7 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
                 int p = 0;
                 while (m) {
                     int b[kWalk];
-                    R x0[kWalk], y0[kWalk], z0[kWalk];
+                    T x0[kWalk], y0[kWalk], z0[kWalk];
                     bool ok[kWalk];
 #pragma unroll
                     for (int j = 0; j < kWalk; ++j) {
@@ -308,7 +310,7 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
                         m &= m - 1;
                         const bool t1 = p >= P[NC];
                         int sh = t1 ? shift[NC] : shift[0];
-                        R xx = rx0[0];
+                        T xx = rx0[0];
 #pragma unroll
                         for (int k = 1; k < NC; ++k) {
                             const bool ge = p >= (t1 ? P[NC + k] : P[k]);
@@ -325,9 +327,9 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
                     for (int j = 0; j < kWalk; ++j) q[j] = data[b[j]];
 #pragma unroll
                     for (int j = 0; j < kWalk; ++j) {
-                        const R rx = x0[j] - q[j].x;
-                        const R ry = DIM > 1 ? y0[j] - q[j].y : R(0);
-                        const R rz = DIM > 2 ? z0[j] - q[j].z : R(0);
+                        const T rx = x0[j] - T(q[j].x);
+                        const T ry = DIM > 1 ? y0[j] - T(q[j].y) : T(0);
+                        const T rz = DIM > 2 ? z0[j] - T(q[j].z) : T(0);
                         fn(b[j], q[j], rx, ry, rz, ok[j]);
                     }
                 }
@@ -433,72 +435,110 @@ __device__ __forceinline__ int force_kind(const Phys<R> &Ph, const Sorted<R> &S)
     return S.has_mass ? kForceIsoMass : kForceIsoUniform;
 }
 
+// s -= f x, with the product rounded to the term type first when the sum is
+// wider (same-type operands keep the contraction into one fused multiply-add)
+template <typename A, typename T>
+__device__ __forceinline__ void sub_prod(A &s, T f, T x)
+{
+    if constexpr (std::is_same<A, T>::value)
+        s -= f * x;
+    else
+        s -= A(f * x);
+}
+
 template <typename R, int DIM, int KIND>
 __device__ __forceinline__ void gas_force_at(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &S, int a,
                                              R acc[3], R &dedt)
 {
+    using SS = typename ForceArith<R>::S;
+    using T = typename ForceArith<R>::T;
+    using A = typename ForceArith<R>::A;
     int cx, cy, cz;
     split_cell(G, S.cell[a], cx, cy, cz);
     const R4<R> me = S.frc[a];
     const R oa[3] = {me.x, me.y, me.z};
-    const R Pa = me.w;
+    const T Pa = me.w;
     const R4<R> *pos = S.pos;
-    const R mu_m = S.pos[a].w;        // uniform mass (kForceIsoUniform)
-    R ax = R(0), ay = R(0), az = R(0), de = R(0);
+    const T mu_m = S.pos[a].w;        // uniform mass (kForceIsoUniform)
+    const T inv_h = G.inv_h;
+    A ax = A(0), ay = A(0), az = A(0), de = A(0);
     // neighbours from the masks of the density pass when present, else the window
-    auto visit = [&](auto &&fn) {
+    auto visit = [&](auto &&fn0) {
+        // separations in SS, rounded once to the term type
+        auto fn = [&](int b, const R4<R> &q, SS rx, SS ry, SS rz, bool ok) { fn0(b, q, T(rx), T(ry), T(rz), ok); };
         if (S.nmask)
-            for_neighbours<R, DIM>(G, cx, cy, cz, oa, S.start, S.frc, S.nmask + a, S.n, fn);
+            for_neighbours<R, DIM, SS>(G, cx, cy, cz, oa, S.start, S.frc, S.nmask + a, S.n, fn);
         else
-            for_window<R, DIM>(G, cx, cy, cz, oa, S.start, S.frc, fn);
+            for_window<R, DIM, SS>(G, cx, cy, cz, oa, S.start, S.frc, fn);
     };
     if constexpr (KIND != kForceGeneral) {
-        visit([&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
-            const R r2 = rx * rx + ry * ry + rz * rz;
-            const R r = fsqrt(r2);
-            const R ir = (ok && r2 > R(0)) ? frcp(r) : R(0);    // self pair and padding contribute 0
-            const R mb = KIND == kForceIsoMass ? pos[b].w : mu_m;
-            const R fac = mb * (Pa + q.w) * spline_df(r * G.inv_h) * ir;
-            ax -= fac * rx;
-            ay -= fac * ry;
-            az -= fac * rz;
+        visit([&](int b, const R4<R> &q, T rx, T ry, T rz, bool ok) {
+            const T r2 = rx * rx + ry * ry + rz * rz;
+            T r, ir;
+            if constexpr (std::is_same<T, double>::value && std::is_same<R, float>::value) {
+                // FP64 terms of an FP32 state: 1/r from the hardware FP32 reciprocal square root
+                // and one Newton step in FP64 (relative error about 1e-14)
+                const double y0 = double(frsq(float(r2)));
+                const double y = y0 * (1.5 - 0.5 * r2 * (y0 * y0));
+                const bool live = ok && r2 > 0.0;
+                ir = live ? y : 0.0;              // self pair and padding contribute 0
+                r = live ? r2 * y : 0.0;
+            } else {
+                r = fsqrt(r2);
+                ir = (ok && r2 > T(0)) ? frcp(r) : T(0);    // self pair and padding contribute 0
+            }
+            const T mb = KIND == kForceIsoMass ? T(pos[b].w) : mu_m;
+            const T fac = mb * (Pa + T(q.w)) * spline_df(r * inv_h) * ir;
+            sub_prod(ax, fac, rx);
+            sub_prod(ay, fac, ry);
+            sub_prod(az, fac, rz);
         });
     } else {
         const bool per_mass = S.has_mass != 0;
-        const R va[3] = {S.vel[0][a], DIM > 1 ? S.vel[1][a] : R(0), DIM > 2 ? S.vel[2][a] : R(0)};
-        const R rhoa = S.rho[a];
-        const R ca = sound_of(Ph, S.energy ? S.energy[a] : R(0));
-        visit([&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
-            const R r2 = rx * rx + ry * ry + rz * rz;
-            const R r = fsqrt(r2);
-            const R qq = r * G.inv_h;
-            if (ok && qq < R(2) && r2 > R(0)) {
-                const R gfac = spline_df(qq) * frcp(r);   // grad_a W = gfac * gnorm * r_vec
-                const R vx = va[0] - S.vel[0][b];
-                const R vy = DIM > 1 ? va[1] - S.vel[1][b] : R(0);
-                const R vz = DIM > 2 ? va[2] - S.vel[2][b] : R(0);
-                const R vr = vx * rx + vy * ry + vz * rz;
-                R Pi = R(0);
-                if (Ph.av && vr < R(0)) {
-                    const R mu = Ph.h * vr / (r2 + Ph.eta2);
-                    const R cb = sound_of(Ph, S.energy ? S.energy[b] : R(0));
-                    const R cbar = R(0.5) * (ca + cb);
-                    const R rbar = R(0.5) * (rhoa + S.rho[b]);
-                    Pi = (-Ph.av_alpha * cbar * mu + Ph.av_beta * mu * mu) / rbar;
+        const T va[3] = {S.vel[0][a], DIM > 1 ? S.vel[1][a] : R(0), DIM > 2 ? S.vel[2][a] : R(0)};
+        const T rhoa = S.rho[a];
+        const T ca = sound_of(Ph, S.energy ? S.energy[a] : R(0));
+        visit([&](int b, const R4<R> &q, T rx, T ry, T rz, bool ok) {
+            const T r2 = rx * rx + ry * ry + rz * rz;
+            const T r = fsqrt(r2);
+            const T qq = r * inv_h;
+            if (ok && qq < T(2) && r2 > T(0)) {
+                const T gfac = spline_df(qq) * frcp(r);   // grad_a W = gfac * gnorm * r_vec
+                const T vx = va[0] - T(S.vel[0][b]);
+                const T vy = DIM > 1 ? va[1] - T(S.vel[1][b]) : T(0);
+                const T vz = DIM > 2 ? va[2] - T(S.vel[2][b]) : T(0);
+                const T vr = vx * rx + vy * ry + vz * rz;
+                T Pi = T(0);
+                if (Ph.av && vr < T(0)) {
+                    const T mu = T(Ph.h) * vr / (r2 + T(Ph.eta2));
+                    const T cb = sound_of(Ph, S.energy ? S.energy[b] : R(0));
+                    const T cbar = T(0.5) * (ca + cb);
+                    const T rbar = T(0.5) * (rhoa + T(S.rho[b]));
+                    Pi = (-T(Ph.av_alpha) * cbar * mu + T(Ph.av_beta) * mu * mu) / rbar;
                 }
-                const R mb = per_mass ? pos[b].w : mu_m;
-                const R fac = mb * (Pa + q.w + Pi) * gfac;
-                ax -= fac * rx;
-                ay -= fac * ry;
-                az -= fac * rz;
-                de += mb * (Pa + R(0.5) * Pi) * gfac * vr;
+                const T mb = per_mass ? T(pos[b].w) : mu_m;
+                const T fac = mb * (Pa + T(q.w) + Pi) * gfac;
+                sub_prod(ax, fac, rx);
+                sub_prod(ay, fac, ry);
+                sub_prod(az, fac, rz);
+                if constexpr (std::is_same<A, T>::value)
+                    de += mb * (Pa + T(0.5) * Pi) * gfac * vr;
+                else
+                    de += A(mb * (Pa + T(0.5) * Pi) * gfac * vr);
             }
         });
     }
-    acc[0] = ax * G.gnorm;
-    acc[1] = ay * G.gnorm;
-    acc[2] = az * G.gnorm;
-    dedt = de * G.gnorm;
+    if constexpr (std::is_same<A, R>::value) {
+        acc[0] = ax * G.gnorm;
+        acc[1] = ay * G.gnorm;
+        acc[2] = az * G.gnorm;
+        dedt = de * G.gnorm;
+    } else {
+        acc[0] = R(ax * A(G.gnorm));
+        acc[1] = R(ay * A(G.gnorm));
+        acc[2] = R(az * A(G.gnorm));
+        dedt = R(de * A(G.gnorm));
+    }
 }
 
 // gas force of particle a with the loop kind picked at run time

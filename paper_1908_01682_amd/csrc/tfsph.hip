@@ -18,6 +18,7 @@
 #include "sph.hpp"
 #include "enqueue.hpp"
 #include "imex.hpp"
+#include "pairdrag.hpp"
 
 using namespace tfsph;
 using namespace tfsph_host;
@@ -79,8 +80,8 @@ extern "C" tfsph_status tfsph_validate(const tfsph_params *p)
     if (p->K == 0.0 && p->t_stop_epstein == 0.0 && !finite_pos(p->t_stop))
         return fail(TFSPH_E_INVALID_ARG, "t_stop must be positive (or K or t_stop_epstein > 0)");
     if (!finite_pos(p->dt)) return fail(TFSPH_E_INVALID_ARG, "dt must be positive");
-    if (p->scheme != TFSPH_SCHEME_IDIC && p->scheme != TFSPH_SCHEME_IMEX2)
-        return fail(TFSPH_E_INVALID_ARG, "scheme must be TFSPH_SCHEME_IDIC or TFSPH_SCHEME_IMEX2");
+    if (p->scheme < TFSPH_SCHEME_IDIC || p->scheme > TFSPH_SCHEME_ISPH)
+        return fail(TFSPH_E_INVALID_ARG, "scheme must be TFSPH_SCHEME_IDIC, _IMEX2, _MK or _ISPH (got %d)", p->scheme);
     if (p->eos == TFSPH_ISOTHERMAL && !finite_pos(p->c_s)) return fail(TFSPH_E_INVALID_ARG, "c_s must be positive");
     if (p->eos == TFSPH_ADIABATIC && !(std::isfinite(p->gamma) && p->gamma > 1.0))
         return fail(TFSPH_E_INVALID_ARG, "gamma must be > 1");
@@ -497,6 +498,52 @@ __global__ void k_export_flags(const unsigned int *word, const unsigned long lon
     if (one_phase_out) *one_phase_out = (int64_t)one_phase[0];
 }
 
+// One step of the comparison schemes (MK or ISPH): binning, both summation
+// densities, then one thread per gas particle and one per dust particle.
+template <typename R, int DIM, int SCHEME>
+tfsph_status enqueue_step_pair(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
+{
+    const Geom<R> G = make_geom<R>(&c->p);
+    const Phys<R> Ph = make_phys<R>(&c->p);
+    Phase<R> Pg = make_phase<R>(s->gas, DIM), Pd = make_phase<R>(s->dust, DIM);
+    Sorted<R> Sg, Sd;
+    int *partial;
+    Flags F;
+    carve_all<R>(c, Sg, Sd, partial, F);
+    if (c->variant != TFSPH_VARIANT_AUTO) Sg.nmask = nullptr;
+    MARK(TFSPH_KERNEL_BIN);
+    tfsph_status r = enqueue_bin<R>(c->ng, c->nd, G, Pg, Pd, Sg, Sd, partial, F, st);
+    if (r != TFSPH_OK) return r;
+    MARK(TFSPH_KERNEL_BIN);
+    MARK(TFSPH_KERNEL_DENSITY);
+    if (c->ng > 0) {
+        r = enqueue_density<R, DIM>(G, Ph, Sg, 1, st, c->variant == TFSPH_VARIANT_LDS_BRICKS ? 0 : c->variant);
+        if (r != TFSPH_OK) return r;
+    }
+    if (c->nd > 0) {
+        r = enqueue_density<R, DIM>(G, Ph, Sd, 0, st, 0);
+        if (r != TFSPH_OK) return r;
+    }
+    MARK(TFSPH_KERNEL_DENSITY);
+    MARK(TFSPH_KERNEL_FORCE);
+    if (c->ng > 0) {
+        launch_by_kind<R, DIM>(Ph, Sg, [&](auto K) {
+            hipLaunchKernelGGL((k_pair_gas<R, DIM, decltype(K)::value, SCHEME>), dim3(blocks_for(c->ng)), dim3(kBlock),
+                               0, st, G, Ph, Sg, Sd, Pg, F);
+        });
+        LAUNCH_CHECK("pair_gas");
+    }
+    MARK(TFSPH_KERNEL_FORCE);
+    MARK(TFSPH_KERNEL_UPDATE);
+    if (c->nd > 0) {
+        hipLaunchKernelGGL((k_pair_dust<R, DIM, SCHEME>), dim3(blocks_for(c->nd)), dim3(kBlock), 0, st, G, Ph, Sg, Sd,
+                           Pd, F);
+        LAUNCH_CHECK("pair_dust");
+    }
+    MARK(TFSPH_KERNEL_UPDATE);
+    return TFSPH_OK;
+}
+
 template <typename R>
 tfsph_status enqueue_init(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
 {
@@ -583,6 +630,14 @@ tfsph_status dispatch_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
     if (c->profiling) {
         const long long i = c->prof_steps++;
         c->prof_kind = i % c->prof_every == 0 ? int((i / c->prof_every) % 4) : -1;
+    }
+    if (c->p.scheme == TFSPH_SCHEME_MK || c->p.scheme == TFSPH_SCHEME_ISPH) {
+        const bool mk = c->p.scheme == TFSPH_SCHEME_MK;
+        switch (c->p.dim) {
+        case 1: return mk ? enqueue_step_pair<R, 1, kPairMK>(c, s, st) : enqueue_step_pair<R, 1, kPairISPH>(c, s, st);
+        case 2: return mk ? enqueue_step_pair<R, 2, kPairMK>(c, s, st) : enqueue_step_pair<R, 2, kPairISPH>(c, s, st);
+        default: return mk ? enqueue_step_pair<R, 3, kPairMK>(c, s, st) : enqueue_step_pair<R, 3, kPairISPH>(c, s, st);
+        }
     }
     switch (c->p.dim) {
     case 1: return imex ? enqueue_step_imex<R, 1>(c, s, st) : enqueue_step<R, 1>(c, s, st);

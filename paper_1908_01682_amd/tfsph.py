@@ -26,7 +26,7 @@ TFSPH_FLAG_EMPTY_PHASE_CELL = 2
 TFSPH_FLAG_BAD_CELL = 4
 TFSPH_FLAG_CELL_OVERFLOW = 8
 TFSPH_FLAG_CFL = 16
-TFSPH_SCHEME_IDIC, TFSPH_SCHEME_IMEX2 = 0, 1
+TFSPH_SCHEME_IDIC, TFSPH_SCHEME_IMEX2, TFSPH_SCHEME_MK, TFSPH_SCHEME_ISPH = 0, 1, 2, 3
 
 STATUS = {0: "TFSPH_OK", -1: "TFSPH_E_INVALID_ARG", -2: "TFSPH_E_WORKSPACE", -3: "TFSPH_E_HIP",
           -4: "TFSPH_E_UNSUPPORTED", -5: "TFSPH_E_STATE"}

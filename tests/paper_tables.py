@@ -30,6 +30,18 @@ def printed(name):
     return rows
 
 
+def stored_oracle_errors():
+    """{(kind, h, tau, method): error} from tests/golden/tables_oracle.txt (written by
+    tests/golden/make_tables_oracle.py from the oracle alone)."""
+    out = {}
+    for line in open(os.path.join(HERE, "golden", "tables_oracle.txt")):
+        line = line.split("#")[0].split()
+        if line:
+            kind, h, tau, m, err = line
+            out[(kind, float(h), float(tau), m)] = float(err)
+    return out
+
+
 def wave_problem(h, tau, method):
     return I.paper_dustywave(h=h, dt=tau, scheme=SCHEMES[method])
 

@@ -159,13 +159,13 @@ def test_validate_drag_coefficient_mode(lib):
 
 
 def test_validate_scheme(lib):
-    """scheme selects the first-order step (0) or the second-order IMEX step (1); anything else
-    is rejected on the host."""
+    """scheme selects the first-order IDIC step (0), the second-order IMEX step (1), or one of
+    the paper's comparison schemes, MK (2) and ISPH (3); anything else is rejected on the host."""
     p = _good()
-    for ok in (T.TFSPH_SCHEME_IDIC, T.TFSPH_SCHEME_IMEX2):
+    for ok in (T.TFSPH_SCHEME_IDIC, T.TFSPH_SCHEME_IMEX2, T.TFSPH_SCHEME_MK, T.TFSPH_SCHEME_ISPH):
         p.scheme = ok
         assert _status(p) == 0, T.lib().tfsph_last_error()
-    for bad in (-1, 2, 7):
+    for bad in (-1, 4, 7):
         p.scheme = bad
         assert _status(p) == -1
 

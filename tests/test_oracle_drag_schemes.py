@@ -51,6 +51,9 @@ def test_table1_dustywave_errors_are_the_papers(orc, row):
     for m, rel in (("MK", 0.04), ("ISPH", 0.04), ("IDIC", 0.3)):
         assert _close_to_printed(got[m], want[m], rel), (m, got, want)
     assert got["IDIC"] < got["ISPH"] / 50 and got["ISPH"] < got["MK"], got
+    stored = PT.stored_oracle_errors()
+    for m in got:
+        assert abs(got[m] - stored[("wave", h, tau, m)]) <= 1e-9 * got[m], (m, got[m])
 
 
 @pytest.mark.parametrize("row", PT.printed("table2_dustyshock.txt"), ids=["h0.01", "h0.02"])
@@ -67,6 +70,9 @@ def test_table2_dustyshock_ranking_and_size(orc, row):
     assert got["IDIC"] < got["MK"] < got["ISPH"], got
     for m, rel in (("IDIC", 0.1), ("MK", 0.1), ("ISPH", 0.3)):
         assert abs(got[m] - want[m]) <= rel * want[m], (m, got, want)
+    stored = PT.stored_oracle_errors()
+    for m in got:
+        assert abs(got[m] - stored[("shock", h, tau, m)]) <= 1e-9 * got[m], (m, got[m])
 
 
 # ---------------------------------------------------------------------------
