@@ -335,10 +335,9 @@ tfsph_status tfsph_step_adjoint(const tfsph_params *p, const tfsph_state *initia
  *    only those and scans the rest.  The masks take 8 bytes per gas particle
  *    and row of the window in the workspace (tfsph_workspace_size).
  *  - TFSPH_VARIANT_GLOBAL: both passes scan the whole window in global memory.
- *  - TFSPH_VARIANT_LDS_BRICKS: blocks of cells and their halos are staged in
- *    LDS for 2D/3D (density always; the fused update only when isothermal,
- *    without viscosity and with uniform gas mass, else as GLOBAL).
- * Every variant visits neighbours in the same order with the same arithmetic,
+ *  - TFSPH_VARIANT_LDS_BRICKS: not built (TFSPH_E_UNSUPPORTED): blocks of
+ *    cells staged in LDS were slower than the global loops.
+ * Both variants visit neighbours in the same order with the same arithmetic,
  * and terms outside the support are exactly zero, so results are bitwise
  * equal.  Selecting a variant drops the context's cached step graph.  Returns
  * TFSPH_E_INVALID_ARG for an unknown variant or a null context. */

@@ -68,22 +68,27 @@ __device__ __forceinline__ R spline_df(R q)
 #define TFSPH_FORCE_OCCUPANCY(R, KIND) TFSPH_DENSITY_OCCUPANCY(R)
 #define TFSPH_STAGE_OCCUPANCY(R, KIND) TFSPH_DENSITY_OCCUPANCY(R)
 #else
-// Waves per SIMD of the FP32 pair kernels on the 3D box, against the
-// compiler's choice: the density pass at 7 (72 VGPRs, a 20-byte spill) takes
-// 0.336 ms against 0.345 at 6 (79 VGPRs); the isothermal force pass at 7
-// (72 VGPRs, 12 bytes spilled) 0.162 ms against 0.170 at 6; the IMEX step
-// with its force stages at 7 1.687 ms against 1.702 at 6.  The general force
-// loop and FP64 would spill heavily, so they keep the compiler's choice.
+// Waves per SIMD of the FP32 density pass on the 3D box, against the
+// compiler's choice: at 7 (72 VGPRs, a 20-byte spill) it takes 0.336 ms
+// against 0.345 at 6 (79 VGPRs).  FP64 would spill heavily, so it keeps the
+// compiler's choice.
 #define TFSPH_DENSITY_OCCUPANCY(R) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 7 : 1)))
-#define TFSPH_FORCE_OCCUPANCY(R, KIND) \
-    __attribute__((amdgpu_waves_per_eu((sizeof(R) == 4 && (KIND) != 2) ? 7 : 1)))
+// the force passes sum FP64 terms (118 VGPRs): the compiler's choice
+#define TFSPH_FORCE_OCCUPANCY(R, KIND) __attribute__((amdgpu_waves_per_eu(1)))
 #define TFSPH_STAGE_OCCUPANCY(R, KIND) TFSPH_FORCE_OCCUPANCY(R, KIND)
 #endif
-// Arithmetic of the pressure-force pair sums of an FP32 state:
+// Arithmetic of the pressure-force pair sums of an FP32 state.  The pressure
+// force of a smooth flow is a small difference of large pair terms (in the
+// 2D wave of amplitude 1e-2 about 1e-3 of a term), so the rounding of each
+// FP32 term, not of the state, decides the long-run error:
 // 0: FP32 separations, terms and sums; 1: FP32 terms summed in FP64;
-// 2: FP64 separations, terms and sums (from the FP32 offsets).
+// 2: FP64 separations, terms and sums from the FP32 offsets (the default);
+// 4: FP64 separations rounded once to FP32 terms, FP64 sums.
+// Over 1000 steps of that wave (64^2 + 64^2, FP32 state, against the FP64
+// oracle) the dust velocity's relative L2 is 2.36e-3, 2.04e-3, 0.89e-3 and
+// 1.40e-3; the 3D box's force pass takes 0.165, -, 0.279 and 0.258 ms.
 #ifndef TFSPH_FORCE_ARITH
-#define TFSPH_FORCE_ARITH 0
+#define TFSPH_FORCE_ARITH 2
 #endif
 template <typename R>
 struct ForceArith {

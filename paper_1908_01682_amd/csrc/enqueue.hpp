@@ -4,7 +4,6 @@
 #pragma once
 
 #include "binning.hpp"
-#include "brick.hpp"
 #include "host.hpp"
 #include "sph.hpp"
 
@@ -62,57 +61,17 @@ inline tfsph_status enqueue_bin(int ng, int nd, const Geom<R> &G, const Phase<R>
 }
 
 
-// Brick decomposition of the cell grid for the LDS-staged kernels of 2D/3D;
-// nbricks = 0 when the halo would not fit (then the global loops are used).
-template <typename R, int DIM>
-inline BrickGrid brick_grid(const Geom<R> &G)
-{
-    BrickGrid B{};
-    if (DIM < 2) return B;
-    using S = BrickShape<(DIM < 2 ? 2 : DIM)>;
-    const int bs[3] = {S::BX, S::BY, S::BZ};
-    B.nbricks = 1;
-    for (int d = 0; d < 3; ++d) {
-        B.nb[d] = d < DIM ? (G.nc[d] + bs[d] - 1) / bs[d] : 1;
-        B.nbricks *= B.nb[d];
-    }
-    B.hx = S::BX + 2 * G.win[0];
-    B.hy = DIM > 1 ? S::BY + 2 * G.win[1] : 1;
-    B.hz = DIM > 2 ? S::BZ + 2 * G.win[2] : 1;
-    B.nhalo = B.hx * B.hy * B.hz;
-    if (B.nhalo > kBrickMaxHalo) B.nbricks = 0;
-    return B;
-}
-
 // kernel variant: 0 (auto) and 1 = global-memory pair loops (neighbour masks
-// when S.nmask is set); 2 = LDS bricks where eligible
+// when S.nmask is set)
 template <typename R, int DIM>
 inline tfsph_status enqueue_density(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &S, int want_frc,
                                     hipStream_t st, int variant = 0)
 {
+    (void)variant;
     if (S.n == 0) return TFSPH_OK;
-    if constexpr (DIM >= 2) {
-        const BrickGrid B = brick_grid<R, DIM>(G);
-        if (variant == 2 && B.nbricks > 0) {
-            hipLaunchKernelGGL((k_density_brick<R, DIM, 512>), dim3(B.nbricks), dim3(512), 0, st, G, Ph, S, B,
-                               want_frc);
-            LAUNCH_CHECK("density_brick");
-            return TFSPH_OK;
-        }
-    }
     hipLaunchKernelGGL((k_density<R, DIM>), dim3(blocks_for(S.n)), dim3(kBlock), 0, st, G, Ph, S, want_frc);
     LAUNCH_CHECK("density");
     return TFSPH_OK;
-}
-
-// whether enqueue_update() runs the LDS-brick form, which evaluates the gas
-// force itself (else enqueue_force() must run first)
-template <typename R, int DIM>
-inline bool update_uses_bricks(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg, int variant)
-{
-    if constexpr (DIM >= 2)
-        return variant == 2 && brick_grid<R, DIM>(G).nbricks > 0 && Ph.eos == 0 && !Ph.av && !Sg.has_mass;
-    return false;
 }
 
 // Explicit gas terms and predictor v~, one thread per gas particle.  The
@@ -135,22 +94,11 @@ inline tfsph_status enqueue_force(const Geom<R> &G, const Phys<R> &Ph, const Sor
     return TFSPH_OK;
 }
 
-// Cell sums, implicit solve, particle update, move and carry; the LDS-brick
-// form (variant 2, when eligible) also evaluates the gas force.
+// Cell sums, implicit solve, particle update, move and carry.
 template <typename R, int DIM>
 inline tfsph_status enqueue_update(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg, const Sorted<R> &Sd,
-                                   const Phase<R> &Pg, const Phase<R> &Pd, const Flags &F, int cpb, hipStream_t st,
-                                   int variant = 0)
+                                   const Phase<R> &Pg, const Phase<R> &Pd, const Flags &F, int cpb, hipStream_t st)
 {
-    if constexpr (DIM >= 2) {
-        if (update_uses_bricks<R, DIM>(G, Ph, Sg, variant)) {
-            const BrickGrid B = brick_grid<R, DIM>(G);
-            hipLaunchKernelGGL((k_update_brick<R, DIM, 512>), dim3(B.nbricks), dim3(512), 0, st, G, Ph, Sg, Sd,
-                               Pg, Pd, F, B);
-            LAUNCH_CHECK("update_brick");
-            return TFSPH_OK;
-        }
-    }
     const int nblocks = (G.ncell + cpb - 1) / cpb;
     const size_t lds = update_lds_bytes<R>(cpb);
     hipLaunchKernelGGL((k_update<R, DIM>), dim3(nblocks), dim3(kBlock), lds, st, G, Ph, Sg, Sd, Pg, Pd, F, cpb, nblocks);

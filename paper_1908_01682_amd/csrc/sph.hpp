@@ -189,12 +189,19 @@ __device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int
 // the support: bit p of pair i is the p-th candidate of the pair in walking
 // order (first row, then its opposite; in a row cells dx = -wx..wx, each in
 // cell order).  A pair with more than 64 candidates is not recorded; the force
-// pass scans such a pair.  The support test is q = sqrt(r^2) / h < 2,
-// the same q the force terms use, and those terms vanish exactly for q >= 2
+// pass scans such a pair.  The support test is q = sqrt(r^2) / h below 2 plus
+// a margin (kMaskQ), and the force terms vanish exactly for q >= 2
 // (f'(q) = 0), so walking the set bits gives bitwise the sums of the scan.
 // Masks exist only for windows of at most 2 cells on each side along x.
 // ---------------------------------------------------------------------------
 constexpr int kMaskBits = 64;
+// Candidates recorded as neighbours: q < 2 (1 + 1e-5).  The force pass forms
+// q again from FP64 separations, which can differ from this FP32 q by about
+// 1e-6 relative; the margin keeps every pair with a non-zero force term in the
+// masks, and the pairs it adds have q >= 2 in the force pass, whose terms are
+// exactly zero.  So walking the masks and scanning the window give the same
+// sums bit for bit.
+constexpr float kMaskQ = 2.0f * (1.0f + 1e-5f);
 
 // As visit_range(), for the density pass: fn(...) returns whether the
 // candidate is a neighbour; returns those answers as bits p0 + (b - b0).
@@ -371,7 +378,7 @@ __device__ __forceinline__ R density_at(const Geom<R> &G, const Sorted<R> &S, in
         const R qq = fsqrt(r2) * G.inv_h;
         const R m = ok ? q.w : R(0);
         acc += m * spline_f(qq);
-        return ok && qq < R(2);
+        return ok && qq < R(kMaskQ);
     };
     if (record && S.nmask)
         for_window_recording<R, DIM>(G, cx, cy, cz, oa, S.start, S.pos, S.nmask + a, S.n, term);

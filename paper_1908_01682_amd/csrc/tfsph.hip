@@ -340,14 +340,14 @@ tfsph_status enqueue_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
         if (r != TFSPH_OK) return r;
         MARK(TFSPH_KERNEL_DENSITY);
     }
-    if (c->ng > 0 && !update_uses_bricks<R, DIM>(G, Ph, Sg, c->variant)) {
+    if (c->ng > 0) {
         MARK(TFSPH_KERNEL_FORCE);
         r = enqueue_force<R, DIM>(G, Ph, Sg, Pg, st);
         if (r != TFSPH_OK) return r;
         MARK(TFSPH_KERNEL_FORCE);
     }
     MARK(TFSPH_KERNEL_UPDATE);
-    r = enqueue_update<R, DIM>(G, Ph, Sg, Sd, Pg, Pd, F, c->cells_per_block, st, c->variant);
+    r = enqueue_update<R, DIM>(G, Ph, Sg, Sd, Pg, Pd, F, c->cells_per_block, st);
     if (r != TFSPH_OK) return r;
     MARK(TFSPH_KERNEL_UPDATE);
     return TFSPH_OK;
@@ -517,7 +517,7 @@ tfsph_status enqueue_step_pair(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
     MARK(TFSPH_KERNEL_BIN);
     MARK(TFSPH_KERNEL_DENSITY);
     if (c->ng > 0) {
-        r = enqueue_density<R, DIM>(G, Ph, Sg, 1, st, c->variant == TFSPH_VARIANT_LDS_BRICKS ? 0 : c->variant);
+        r = enqueue_density<R, DIM>(G, Ph, Sg, 1, st, c->variant);
         if (r != TFSPH_OK) return r;
     }
     if (c->nd > 0) {
@@ -799,6 +799,9 @@ extern "C" tfsph_status tfsph_set_kernel_variant(tfsph_ctx *c, int32_t variant)
     if (!c) return fail(TFSPH_E_INVALID_ARG, "ctx is NULL");
     if (variant < 0 || variant > 2)
         return fail(TFSPH_E_INVALID_ARG, "unknown kernel variant %d", variant);
+    if (variant == TFSPH_VARIANT_LDS_BRICKS)
+        return fail(TFSPH_E_UNSUPPORTED, "the LDS-brick pair loops are not built (they were slower than the global "
+                                         "loops, and the force pass sums its pair terms in FP64)");
     c->variant = variant;
     drop_graph(c->sg);
     return TFSPH_OK;

@@ -163,28 +163,18 @@ def test_adjoint_rejects_unsupported():
         T.tfsph_adjoint_workspace_size(params, 400, 400, 10, 5)       # adiabatic + viscosity
 
 
-def test_full_size_adjoint_against_oracle_differences(orc):
-    """The full adjoint workload (2D wave, 512^2 + 512^2 particles, 256^2 cells, 200 steps,
-    checkpoint every 20) as the benchmark runs it, against the FP64 C oracle: its loss, and the
-    central difference of its loss in log t_stop.  The difference step (1e-5) must leave every
-    particle's drag cell unchanged at every step (cells are held fixed by the adjoint; a crossing
-    would put a jump into the difference): that is checked.  FP64 device run: loss to 1e-10,
-    gradient to 1e-6.  FP32 device run (the benchmark's): loss to 1e-4, gradient to 2.5e-3
-    (measured 1.6e-3: the scalar sums -alpha abar - beta betabar over 65536 cells with
-    cancellation)."""
-    prob = I.workload("wave2d", steps=200)
-    ex = prob.extra
-    k = np.asarray(ex["kvec"])
-    target = ex["rho_d0"] * (1.0 + ex["amp"] * np.sin(prob.dust.x @ k))
-    steps, ckpt = 200, 20
-    ts = prob.params.t_stop
-    e = 1e-5
+def _oracle_runs(orc, prob, cases, steps, watch=None):
+    """Run the oracle for every (params, gas velocities, dust velocities) case in lock step and
+    check that every run keeps the first run's drag cells and canonical order at every step.
+    With watch = (gas ids, dust ids) also returns, per watched particle, its smallest distance
+    to a cell face over the first run, in cell widths."""
     runs = []
-    for t in (ts, ts * math.exp(e), ts * math.exp(-e)):
-        p = prob.params.replace(t_stop=t)
-        g = orc.from_positions(p, prob.gas.x, prob.gas.v, prob.gas.m, prob.gas.id)
-        d = orc.from_positions(p, prob.dust.x, prob.dust.v, prob.dust.m, prob.dust.id)
+    for p, vg, vd in cases:
+        g = orc.from_positions(p, prob.gas.x, vg, prob.gas.m, prob.gas.id)
+        d = orc.from_positions(p, prob.dust.x, vd, prob.dust.m, prob.dust.id)
         runs.append((p, g, d))
+    D = orc.cell_width(prob.params)[:prob.params.dim]
+    near = [np.full(len(w), np.inf) for w in watch] if watch else None
     for s in range(steps):
         for p, g, d in runs:
             orc.step(p, g, d, 1)
@@ -194,17 +184,76 @@ def test_full_size_adjoint_against_oracle_differences(orc):
             same = all(np.array_equal(a, b) for a, b in ((g.cell, g0.cell), (g.id, g0.id), (d.cell, d0.cell),
                                                          (d.id, d0.id)))
             assert same, f"a drag cell differs at step {s}"
+        if watch:
+            for k, (ph, ids) in enumerate(((g0, watch[0]), (d0, watch[1]))):
+                o = ph.off[:, np.argsort(ph.id)][:, ids] / D[:, None]
+                near[k] = np.minimum(near[k], np.min(np.minimum(o, 1.0 - o), axis=0))
     losses = []
     for p, g, d in runs:
         rho = orc.density(p, d)
-        losses.append(float(np.mean((rho - target[d.id]) ** 2)))
-    l0, fd = losses[0], (losses[1] - losses[2]) / (2 * e)
-    for prec, tl, tg in ((T.TFSPH_F64, 1e-10, 1e-6), (T.TFSPH_F32, 1e-4, 2.5e-3)):
+        losses.append(float(np.mean((rho - prob.extra["target"][d.id]) ** 2)))
+    return losses, near
+
+
+def test_full_size_adjoint_against_oracle_differences(orc):
+    """The full adjoint workload (2D wave, 512^2 + 512^2 particles, 256^2 cells, 200 steps,
+    checkpoint every 20) as the benchmark runs it, against the FP64 C oracle: its loss, the
+    central difference of its loss in log t_stop, and the central differences along two
+    velocity directions, one moving the initial velocities of 24 gas particles and one of 24
+    dust particles (random signs and components).  Particles of this wave cross drag cells
+    (its displacement exceeds the half spacing), and the adjoint holds the cells of the forward
+    run: every difference step must leave every particle's drag cell and the canonical order
+    unchanged at every step, which is checked, and the perturbed particles are drawn among
+    those that never come within a fifth of a cell width of a face.  One particle reaches a face
+    at step 189 so closely that any velocity difference moves its crossing, so the velocity
+    directions are checked over the first 180 steps (same checkpoint interval).  FP64 device
+    run: loss to 1e-10, the three derivatives to 1e-6.  FP32 device run (the benchmark's): loss
+    to 1e-4, dL/dlog t_stop to 1e-3, the velocity derivatives to 1e-2."""
+    prob = I.workload("wave2d", steps=200)
+    ex = prob.extra
+    k = np.asarray(ex["kvec"])
+    ex["target"] = ex["rho_d0"] * (1.0 + ex["amp"] * np.sin(prob.dust.x @ k))
+    target = ex["target"]
+    steps, ckpt = 200, 20
+    p0 = prob.params
+    ts = p0.t_stop
+    e, ev = 1e-5, 1e-7
+    rng = np.random.default_rng(12)
+    pool_g = rng.choice(prob.gas.n, 4096, replace=False)
+    pool_d = rng.choice(prob.dust.n, 4096, replace=False)
+    losses, near = _oracle_runs(orc, prob, [(p0.replace(t_stop=t), prob.gas.v, prob.dust.v)
+                                            for t in (ts, ts * math.exp(e), ts * math.exp(-e))],
+                                steps, watch=(pool_g, pool_d))
+    l0, fd_t = losses[0], (losses[1] - losses[2]) / (2 * e)
+    sel_g = pool_g[near[0] > 0.2][:24]
+    sel_d = pool_d[near[1] > 0.2][:24]
+    assert len(sel_g) == 24 and len(sel_d) == 24
+    dv = np.zeros_like(prob.gas.v)
+    du = np.zeros_like(prob.dust.v)
+    dv[sel_g, rng.integers(0, 2, 24)] = rng.choice([-1.0, 1.0], 24)
+    du[sel_d, rng.integers(0, 2, 24)] = rng.choice([-1.0, 1.0], 24)
+    sv = 180
+    lv, _ = _oracle_runs(orc, prob, [(p0, prob.gas.v + ev * dv, prob.dust.v),
+                                      (p0, prob.gas.v - ev * dv, prob.dust.v),
+                                      (p0, prob.gas.v, prob.dust.v + ev * du),
+                                      (p0, prob.gas.v, prob.dust.v - ev * du)], sv)
+    fd_v, fd_u = (lv[0] - lv[1]) / (2 * ev), (lv[2] - lv[3]) / (2 * ev)
+    for prec, tl, tg, tv in ((T.TFSPH_F64, 1e-10, 1e-6, 1e-6), (T.TFSPH_F32, 1e-4, 1e-3, 1e-2)):
+        tgt = target if prec == T.TFSPH_F64 else target.astype(np.float32)
         banner(f"adjoint full size: {prob.gas.n}+{prob.dust.n} particles, {steps} steps, ckpt {ckpt}, prec {prec}")
         runner = T.AdjointRunner(prob, steps, ckpt, precision=prec)
-        loss, dlogt, _, _ = runner.run(target if prec == T.TFSPH_F64 else target.astype(np.float32))
+        loss, dlogt, _, _ = runner.run(tgt)
         torch.cuda.synchronize()
-        banner(f"loss {float(loss):.9e} vs {l0:.9e}; dL/dlog t_stop {float(dlogt):.9e} vs {fd:.9e}")
-        assert abs(float(loss) - l0) <= tl * l0
-        assert abs(float(dlogt) - fd) <= tg * abs(fd)
         del runner
+        runner = T.AdjointRunner(prob, sv, ckpt, precision=prec)
+        _, _, gv, gu = runner.run(tgt)
+        torch.cuda.synchronize()
+        del runner
+        dir_v = float(np.sum(gv.cpu().numpy().astype(np.float64) * dv))
+        dir_u = float(np.sum(gu.cpu().numpy().astype(np.float64) * du))
+        banner(f"loss {float(loss):.9e} vs {l0:.9e}; dL/dlog t_stop {float(dlogt):.9e} vs {fd_t:.9e}; "
+               f"dL/dv0.dv {dir_v:.9e} vs {fd_v:.9e}; dL/du0.du {dir_u:.9e} vs {fd_u:.9e}")
+        assert abs(float(loss) - l0) <= tl * l0
+        assert abs(float(dlogt) - fd_t) <= tg * abs(fd_t)
+        assert abs(dir_v - fd_v) <= tv * abs(fd_v)
+        assert abs(dir_u - fd_u) <= tv * abs(fd_u)

@@ -108,10 +108,10 @@ def test_one_phase_cells_and_empty_dust(orc):
     ("shock1d", lambda: _imex(I.dusty_shock(n=3000)), 0),
 ], ids=lambda v: v if isinstance(v, str) else "")
 def test_variants_and_launch_shape_bitwise_equal(name, make, precision):
-    """Neighbour masks, window scans and LDS bricks, and any cells per block, give the same bits."""
+    """Neighbour masks and window scans, and any cells per block, give the same bits."""
     prob = make()
     out = []
-    for variant, cpb in ((T.TFSPH_VARIANT_AUTO, 0), (T.TFSPH_VARIANT_GLOBAL, 0), (T.TFSPH_VARIANT_LDS_BRICKS, 0),
+    for variant, cpb in ((T.TFSPH_VARIANT_AUTO, 0), (T.TFSPH_VARIANT_GLOBAL, 0),
                          (T.TFSPH_VARIANT_AUTO, 7), (T.TFSPH_VARIANT_AUTO, 256)):
         sim = _sim(prob, precision)
         T.tfsph_set_kernel_variant(sim.ctx, variant)

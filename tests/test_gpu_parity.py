@@ -114,6 +114,15 @@ def test_five_step_parity(orc, name, make, precision):
     assert all(v <= tol for v in err.values()), err
 
 
+def _displacement_l2(p, x, x_ref, ids, n_side):
+    """Relative L2 of positions against the reference's displacement from the lattice sites
+    (i + 1/2) dx of the particles (periodic differences), not against the box."""
+    L = p.hi[0] - p.lo[0]
+    site = p.lo[0] + (np.asarray(ids) + 0.5) * (L / n_side)
+    wrap = lambda d: d - L * np.round(d / L)
+    return float(np.linalg.norm(wrap(x - x_ref)) / np.linalg.norm(wrap(x_ref - site)))
+
+
 def _rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b - np.mean(b)), 1e-300))
 
@@ -134,7 +143,8 @@ def test_long_run_wave1d(orc, precision, amp):
         "v": _rel_l2(G["vel"][0], og.vel[0]),
         "u": _rel_l2(D["vel"][0], od.vel[0]),
         "rho": _rel_l2(G["rho"], og.rho),
-        "x_gas": _rel_l2(sim.positions(0)[np.argsort(sim.gas.numpy()["id"]), 0], orc.positions(p, og)[:, 0]),
+        "x_gas": _displacement_l2(p, sim.positions(0)[np.argsort(sim.gas.numpy()["id"]), 0],
+                                  orc.positions(p, og)[:, 0], og.id, 200),
     }
     sim.close()
     bound = 1e-9 if precision == 1 else 1e-3
@@ -143,12 +153,12 @@ def test_long_run_wave1d(orc, precision, amp):
 
 def test_long_run_wave2d_fp32(orc):
     """1000 steps of the 2D dusty wave (64^2 + 64^2 particles, 32^2 cells, amplitude 1e-2), FP32
-    against the FP64 oracle, relative L2 of each field's deviation from its mean: gas density
-    within 1e-3, gas velocity within 1.5e-3, dust velocity within 3e-3 (measured 1.1e-4, 1.12e-3
-    and 2.36e-3).  No particle changes cell, so the differences are FP32 rounding of the pair
-    sums accumulated over 1000 steps; they depend on the summation order (1.6e-3 for the dust
-    velocity with rows visited in lexicographic order, 1.0e-3 with the pair sums accumulated in
-    FP64), and the 1D wave, whose window has a single row, stays within 1e-3."""
+    against the FP64 oracle, relative L2 of each field against its deviation from its mean:
+    every field within 1e-3 (measured: gas density 7.2e-5, gas velocity 4.2e-4, dust velocity
+    8.9e-4).  The wave decays about 16-fold over the run, so the bound is 6e-5 of the initial
+    amplitude.  It holds because the pressure-force pair terms are formed and summed in FP64
+    from the FP32 offsets: with FP32 terms the dust velocity measured 2.36e-3 (2.04e-3 with FP64
+    sums only), the force of a smooth flow being a small difference of large pair terms."""
     prob = I.wave_2d(n_side=64, amp=1e-2)
     p = prob.params
     sim = _sim(prob, 0)
@@ -163,7 +173,7 @@ def test_long_run_wave2d_fp32(orc):
     sim.close()
     banner(f"wave2d 1000 steps fp32 rel L2 {errs}")
     assert not flags & T.TFSPH_FLAG_NONFINITE
-    assert errs["v"] <= 1.5e-3 and errs["rho"] <= 1e-3 and errs["u"] <= 3e-3, errs
+    assert all(v <= 1e-3 for v in errs.values()), errs
 
 
 def test_long_run_box3d_fp64(orc):
@@ -367,13 +377,13 @@ def test_full_size_box_five_steps(orc):
 
 
 @pytest.mark.parametrize("name,make,precision", [
-    ("box3d_bricks", lambda: I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4), 0),
-    ("box3d_ragged_bricks", lambda: I.dusty_box(n_side=26, cells_per_axis=13, regions_per_axis=1), 0),
+    ("box3d", lambda: I.dusty_box(n_side=32, cells_per_axis=16, regions_per_axis=4), 0),
+    ("box3d_ragged", lambda: I.dusty_box(n_side=26, cells_per_axis=13, regions_per_axis=1), 0),
     ("box3d_overflow_fallback", lambda: I.dusty_box(n_side=24, cells_per_axis=8, regions_per_axis=2), 0),
     ("box3d_mixed_mask_rows", lambda: I.dusty_box(n_side=20, cells_per_axis=8, regions_per_axis=2), 0),
-    ("box3d_bricks_f64", lambda: I.dusty_box(n_side=20, cells_per_axis=10, regions_per_axis=2), 1),
-    ("wave2d_bricks", lambda: I.wave_2d(n_side=100, amp=1e-2), 0),
-    ("wave2d_bricks_f64", lambda: I.wave_2d(n_side=36, amp=1e-2), 1),
+    ("box3d_f64", lambda: I.dusty_box(n_side=20, cells_per_axis=10, regions_per_axis=2), 1),
+    ("wave2d", lambda: I.wave_2d(n_side=100, amp=1e-2), 0),
+    ("wave2d_f64", lambda: I.wave_2d(n_side=36, amp=1e-2), 1),
     ("shock1d_viscosity", lambda: I.dusty_shock(n=4000), 0),
     ("wave1d_f64", lambda: I.dusty_wave(n_side=400, amp=1e-2), 1),
     ("box3d_window2", lambda: I.dusty_box(n_side=24, cells_per_axis=16, regions_per_axis=2), 0),
@@ -381,16 +391,18 @@ def test_full_size_box_five_steps(orc):
     ("wave2d_window3", lambda: I.dusty_wave(n_side=60, dim=2, amp=1e-2, h_over_dx=1.5, cells_per_axis=60), 0),
 ], ids=lambda v: v if isinstance(v, str) else "")
 def test_pair_loop_variants_bitwise_equal(name, make, precision):
-    """Neighbour masks (default), full window scans and LDS-staged cell bricks visit neighbours in
-    the same order with the same arithmetic, and terms outside the support are exactly zero: every
-    step must agree bit for bit.  The cases cover bricks whose halo overflows the LDS, bricks
-    sticking out of a ragged grid, mask rows longer than 64 candidates (scanned instead) next to
-    short ones, viscosity with a per-particle mass and an adiabatic EOS (1D shock) and FP64."""
+    """Neighbour masks (default) and full window scans visit neighbours in the same order with the
+    same arithmetic, and terms outside the support are exactly zero: every step must agree bit for
+    bit.  The cases cover ragged grids, mask rows longer than 64 candidates (scanned instead) next
+    to short ones, viscosity with a per-particle mass and an adiabatic EOS (1D shock) and FP64.
+    The LDS-brick variant is refused."""
     prob = make()
     out = []
-    for variant in (T.TFSPH_VARIANT_AUTO, T.TFSPH_VARIANT_GLOBAL, T.TFSPH_VARIANT_LDS_BRICKS):
+    for variant in (T.TFSPH_VARIANT_AUTO, T.TFSPH_VARIANT_GLOBAL):
         sim = _sim(prob, precision)
         T.tfsph_set_kernel_variant(sim.ctx, variant)
+        with pytest.raises(T.TfsphError):
+            T.tfsph_set_kernel_variant(sim.ctx, T.TFSPH_VARIANT_LDS_BRICKS)
         sim.step(6)
         torch.cuda.synchronize()
         out.append((sim.gas.numpy(), sim.dust.numpy()))
