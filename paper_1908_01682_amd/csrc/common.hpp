@@ -73,35 +73,46 @@ __device__ __forceinline__ R spline_df(R q)
 // against 0.345 at 6 (79 VGPRs).  FP64 would spill heavily, so it keeps the
 // compiler's choice.
 #define TFSPH_DENSITY_OCCUPANCY(R) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 7 : 1)))
-// the force passes sum FP64 terms (118 VGPRs): the compiler's choice
-#define TFSPH_FORCE_OCCUPANCY(R, KIND) __attribute__((amdgpu_waves_per_eu(1)))
+// The force passes sum FP64 terms (118 VGPRs, 4 waves per SIMD): the compiler's
+// choice.  On the 3D box the isothermal pass takes 0.285 ms; held to 5 waves, or
+// walking 1 or 3 neighbours per step, it is slower.
+#ifndef TFSPH_FORCE_WAVES
+#define TFSPH_FORCE_WAVES 1
+#endif
+#define TFSPH_FORCE_OCCUPANCY(R, KIND) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? TFSPH_FORCE_WAVES : 1)))
 #define TFSPH_STAGE_OCCUPANCY(R, KIND) TFSPH_FORCE_OCCUPANCY(R, KIND)
 #endif
 // Arithmetic of the pressure-force pair sums of an FP32 state.  The pressure
 // force of a smooth flow is a small difference of large pair terms (in the
 // 2D wave of amplitude 1e-2 about 1e-3 of a term), so the rounding of each
-// FP32 term, not of the state, decides the long-run error:
-// 0: FP32 separations, terms and sums; 1: FP32 terms summed in FP64;
-// 2: FP64 separations, terms and sums from the FP32 offsets (the default);
-// 4: FP64 separations rounded once to FP32 terms, FP64 sums.
+// FP32 term, not of the state, decides the long-run error.  Separations are
+// always formed in FP64 from the FP32 offsets; 2 (the default): FP64 terms
+// and sums; 4: terms rounded once to FP32, FP64 sums.
 // Over 1000 steps of that wave (64^2 + 64^2, FP32 state, against the FP64
-// oracle) the dust velocity's relative L2 is 2.36e-3, 2.04e-3, 0.89e-3 and
-// 1.40e-3; the 3D box's force pass takes 0.165, -, 0.279 and 0.258 ms.
+// oracle) the dust velocity's relative L2 is 2.36e-3 with FP32 separations,
+// terms and sums, 2.04e-3 with FP32 terms summed in FP64, 0.89e-3 with the
+// default and 1.40e-3 with 4.
 #ifndef TFSPH_FORCE_ARITH
 #define TFSPH_FORCE_ARITH 2
 #endif
+
 template <typename R>
 struct ForceArith {
-    using S = R;     // separations
     using T = R;     // pair terms
     using A = R;     // sums
 };
 template <>
 struct ForceArith<float> {
-    using S = typename std::conditional<(TFSPH_FORCE_ARITH >= 2), double, float>::type;
     using T = typename std::conditional<(TFSPH_FORCE_ARITH == 2), double, float>::type;
-    using A = typename std::conditional<(TFSPH_FORCE_ARITH >= 1), double, float>::type;
+    using A = double;
 };
+// Candidates recorded as neighbours in the masks: q < kMaskQ = 2 (1 + 1e-5).
+// The force pass forms q again from FP64 separations, which can differ from
+// the FP32 q by about 1e-6 relative; the margin keeps every pair with a
+// non-zero force term in the masks, and the pairs it adds have q >= 2, whose
+// terms are exactly zero.  So walking the masks and scanning the window give
+// the same sums bit for bit.
+constexpr float kMaskQ = 2.0f * (1.0f + 1e-5f);
 constexpr int kChunk = TFSPH_CHUNK;
 constexpr int kScanChunk = TFSPH_SCAN_CHUNK;
 constexpr int kWalk = TFSPH_WALK;

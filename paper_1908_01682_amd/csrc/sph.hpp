@@ -189,19 +189,12 @@ __device__ __forceinline__ void for_window(const Geom<R> &G, int cx, int cy, int
 // the support: bit p of pair i is the p-th candidate of the pair in walking
 // order (first row, then its opposite; in a row cells dx = -wx..wx, each in
 // cell order).  A pair with more than 64 candidates is not recorded; the force
-// pass scans such a pair.  The support test is q = sqrt(r^2) / h below 2 plus
-// a margin (kMaskQ), and the force terms vanish exactly for q >= 2
-// (f'(q) = 0), so walking the set bits gives bitwise the sums of the scan.
-// Masks exist only for windows of at most 2 cells on each side along x.
+// pass scans such a pair.  The support test is q = sqrt(r^2) / h below kMaskQ
+// = 2 (1 + 1e-5), and every force term vanishes exactly for q >= 2 (f'(q) = 0),
+// so walking the set bits gives bitwise the sums of the scan.  Masks exist only
+// for windows of at most 2 cells on each side along x.
 // ---------------------------------------------------------------------------
 constexpr int kMaskBits = 64;
-// Candidates recorded as neighbours: q < 2 (1 + 1e-5).  The force pass forms
-// q again from FP64 separations, which can differ from this FP32 q by about
-// 1e-6 relative; the margin keeps every pair with a non-zero force term in the
-// masks, and the pairs it adds have q >= 2 in the force pass, whose terms are
-// exactly zero.  So walking the masks and scanning the window give the same
-// sums bit for bit.
-constexpr float kMaskQ = 2.0f * (1.0f + 1e-5f);
 
 // As visit_range(), for the density pass: fn(...) returns whether the
 // candidate is a neighbour; returns those answers as bits p0 + (b - b0).
@@ -256,14 +249,43 @@ __device__ __forceinline__ void for_window_recording(const Geom<R> &G, int cx, i
     });
 }
 
+// Walking positions of the 2 NC cell ranges (segments) of a pair of rows:
+// segment s = t NC + k (row t, cell k) starts at position P[s]; index b of a
+// candidate at position p of segment s is p + shift[s].  Returns the pair's
+// candidate count.
+template <int NC>
+__device__ __forceinline__ int pair_segments(const int bs[2][NC], const int be[2][NC], int P[2 * NC],
+                                             int shift[2 * NC])
+{
+    int len = 0;
+#pragma unroll
+    for (int s = 0; s < 2 * NC; ++s) {
+        const int t = s / NC, k = s % NC;
+        P[s] = len;
+        shift[s] = bs[t][k] - len;
+        len += be[t][k] - bs[t][k];
+    }
+    return len;
+}
+
+// Next set bit of m (its position, kept when m is empty) and clear it.
+__device__ __forceinline__ bool pop_bit(unsigned long long &m, int &p)
+{
+    const bool ok = m != 0;
+    // m | bit 63 keeps the count defined when m is empty
+    const int pj = __builtin_ctzll(m | (1ull << 63));
+    p = ok ? pj : p;
+    m &= m - 1;
+    return ok;
+}
+
 // Visit the neighbours of a point recorded in mask[i * stride] (pairs of at
 // most kMaskBits candidates) or, for longer pairs, every candidate of the
 // pair; fn(b, q, rx, ry, rz, valid) as for for_window().  Neighbours are taken
 // kWalk at a time; a lane with fewer left repeats its last one with valid =
 // false.  A set bit p is decoded by the segment (row t, cell k) it falls in:
-// segment s = t (2 WX + 1) + k starts at walking position P[s]; the row is
-// the second one when p >= P[2 WX + 1], the cell the last one of that row
-// whose segment starts at or before p.  When no lane's window wraps around
+// the row is the second one when p >= P[NC], the cell the last one of that
+// row whose segment starts at or before p.  When no lane's window wraps around
 // the box along x, the cells of every row are consecutive in the sorted
 // order, so one index shift serves the whole row.
 template <typename R, int DIM, typename T = R, typename Fn>
@@ -274,24 +296,14 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
     with_row_width(G.win[0], [&](auto W) {
         constexpr int WX = decltype(W)::value;
         constexpr int NC = 2 * WX + 1;          // cells per row
-        constexpr int NS = 2 * NC;              // segments per pair
         T rx0[NC];
 #pragma unroll
         for (int k = 0; k < NC; ++k) rx0[k] = T(oa[0]) - T(k - WX) * T(G.delta[0]);
         const bool wave_rows_contiguous = __ballot(cx < WX || cx + WX >= G.nc[0]) == 0ull;
         for_window_pairs<R, DIM, WX, T>(G, cx, cy, cz, oa, start, [&](int i, auto &bs, auto &be, const T *ry0,
                                                                        const T *rz0) {
-            // first walking position of each segment and its index shift
-            int P[NS], shift[NS];
-            int len = 0;
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const int t = s / NC, k = s % NC;
-                P[s] = len;
-                shift[s] = bs[t][k] - len;
-                len += be[t][k] - bs[t][k];
-            }
-            if (len > kMaskBits) {
+            int P[2 * NC], shift[2 * NC];
+            if (pair_segments<NC>(bs, be, P, shift) > kMaskBits) {
 #pragma unroll
                 for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -310,11 +322,7 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
                     bool ok[kWalk];
 #pragma unroll
                     for (int j = 0; j < kWalk; ++j) {
-                        ok[j] = m != 0;
-                        // m | bit 63 keeps the count defined when m is empty
-                        const int pj = __builtin_ctzll(m | (1ull << 63));
-                        p = ok[j] ? pj : p;
-                        m &= m - 1;
+                        ok[j] = pop_bit(m, p);
                         const bool t1 = p >= P[NC];
                         int sh = t1 ? shift[NC] : shift[0];
                         T xx = rx0[0];
@@ -457,29 +465,30 @@ template <typename R, int DIM, int KIND>
 __device__ __forceinline__ void gas_force_at(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &S, int a,
                                              R acc[3], R &dedt)
 {
-    using SS = typename ForceArith<R>::S;
     using T = typename ForceArith<R>::T;
     using A = typename ForceArith<R>::A;
     int cx, cy, cz;
     split_cell(G, S.cell[a], cx, cy, cz);
-    const R4<R> me = S.frc[a];
-    const R oa[3] = {me.x, me.y, me.z};
-    const T Pa = me.w;
     const R4<R> *pos = S.pos;
     const T mu_m = S.pos[a].w;        // uniform mass (kForceIsoUniform)
     const T inv_h = G.inv_h;
     A ax = A(0), ay = A(0), az = A(0), de = A(0);
-    // neighbours from the masks of the density pass when present, else the window
+    // Neighbours from the masks of the density pass when present, else the window, with the
+    // separations (o_a - d Delta) - o_b formed in SS (FP64 for an FP32 state) and rounded once to
+    // the term type: fn(b, P_b, rx, ry, rz, valid).
+    using SS = typename std::conditional<sizeof(R) == 4, double, R>::type;
+    const R4<R> me = S.frc[a];
+    const T Pa = T(me.w);
+    const R oa[3] = {me.x, me.y, me.z};
     auto visit = [&](auto &&fn0) {
-        // separations in SS, rounded once to the term type
-        auto fn = [&](int b, const R4<R> &q, SS rx, SS ry, SS rz, bool ok) { fn0(b, q, T(rx), T(ry), T(rz), ok); };
+        auto fn = [&](int b, const R4<R> &q, SS rx, SS ry, SS rz, bool ok) { fn0(b, T(q.w), T(rx), T(ry), T(rz), ok); };
         if (S.nmask)
             for_neighbours<R, DIM, SS>(G, cx, cy, cz, oa, S.start, S.frc, S.nmask + a, S.n, fn);
         else
             for_window<R, DIM, SS>(G, cx, cy, cz, oa, S.start, S.frc, fn);
     };
     if constexpr (KIND != kForceGeneral) {
-        visit([&](int b, const R4<R> &q, T rx, T ry, T rz, bool ok) {
+        visit([&](int b, T Pb, T rx, T ry, T rz, bool ok) {
             const T r2 = rx * rx + ry * ry + rz * rz;
             T r, ir;
             if constexpr (std::is_same<T, double>::value && std::is_same<R, float>::value) {
@@ -495,7 +504,7 @@ __device__ __forceinline__ void gas_force_at(const Geom<R> &G, const Phys<R> &Ph
                 ir = (ok && r2 > T(0)) ? frcp(r) : T(0);    // self pair and padding contribute 0
             }
             const T mb = KIND == kForceIsoMass ? T(pos[b].w) : mu_m;
-            const T fac = mb * (Pa + T(q.w)) * spline_df(r * inv_h) * ir;
+            const T fac = mb * (Pa + Pb) * spline_df(r * inv_h) * ir;
             sub_prod(ax, fac, rx);
             sub_prod(ay, fac, ry);
             sub_prod(az, fac, rz);
@@ -505,7 +514,7 @@ __device__ __forceinline__ void gas_force_at(const Geom<R> &G, const Phys<R> &Ph
         const T va[3] = {S.vel[0][a], DIM > 1 ? S.vel[1][a] : R(0), DIM > 2 ? S.vel[2][a] : R(0)};
         const T rhoa = S.rho[a];
         const T ca = sound_of(Ph, S.energy ? S.energy[a] : R(0));
-        visit([&](int b, const R4<R> &q, T rx, T ry, T rz, bool ok) {
+        visit([&](int b, T Pb, T rx, T ry, T rz, bool ok) {
             const T r2 = rx * rx + ry * ry + rz * rz;
             const T r = fsqrt(r2);
             const T qq = r * inv_h;
@@ -524,7 +533,7 @@ __device__ __forceinline__ void gas_force_at(const Geom<R> &G, const Phys<R> &Ph
                     Pi = (-T(Ph.av_alpha) * cbar * mu + T(Ph.av_beta) * mu * mu) / rbar;
                 }
                 const T mb = per_mass ? T(pos[b].w) : mu_m;
-                const T fac = mb * (Pa + T(q.w) + Pi) * gfac;
+                const T fac = mb * (Pa + Pb + Pi) * gfac;
                 sub_prod(ax, fac, rx);
                 sub_prod(ay, fac, ry);
                 sub_prod(az, fac, rz);
