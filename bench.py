@@ -189,13 +189,14 @@ def adjoint_ratio(I, T, torch, steps=200, ckpt=20):
 
 
 def batched_throughput(I, T, torch, steps=500, plain_steps=20):
-    """256 uneven 1D dusty waves in one persistent launch (autotuned, hipGraph replay),
-    against the same instances through the plain path one at a time."""
+    """256 uneven 1D dusty waves advanced together (form and workgroup size autotuned among the
+    persistent kernel and the flattened launches, hipGraph replay), against the same instances
+    through the plain path one at a time."""
     from paper_1908_01682_amd import autotune as A
     probs = I.batched_waves(steps=steps)
     n_part = sum(p.gas.n + p.dust.n for p in probs)
     bs = T.BatchedSimulation(probs, precision=T.TFSPH_F32)
-    tune = A.tune(bs, steps=10)
+    tune = A.tune(bs, steps=10, graph=True)
     bs.step_graph(steps)           # capture + first replay
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -219,6 +220,7 @@ def batched_throughput(I, T, torch, steps=500, plain_steps=20):
     plain = plain_ps / plain_t
     return {"value": value, "unit": "particle-steps/s", "ms_per_step": 1e3 * wall / steps, "steps": steps,
             "instances": len(probs), "particles": n_part, "block": tune["block"],
+            "form": "flat" if tune["form"] == A.FLAT else "persistent", "tuner_ms_per_step": tune["ms_per_step"],
             "plain_path_value": plain, "vs_plain": value / plain, "nonfinite": bool(flags & 1)}
 
 

@@ -265,8 +265,20 @@ typedef struct {
     const double *mass_dust;        /* host [n_inst]: uniform dust mass (packed dust.mass NULL) */
 } tfsph_batch_desc;
 
+/* Forms of the batched step (results are bitwise the same):
+ *  - TFSPH_BATCH_PERSISTENT: one persistent launch per call, one workgroup per
+ *    instance for all its steps (no workgroup waits on another); the launch
+ *    lasts as long as the largest instance takes on one compute unit.
+ *  - TFSPH_BATCH_FLAT: each phase of a step (scan, scatter, rank + gather,
+ *    density, force + predictor, cell solve, update) is one launch over every
+ *    instance, with 256-thread blocks dealt out per instance (a block never
+ *    straddles two); seven launches per step, best replayed as a hipGraph. */
+enum { TFSPH_BATCH_PERSISTENT = 0, TFSPH_BATCH_FLAT = 1 };
+
 typedef struct {
-    int32_t block;                  /* threads per workgroup, multiple of 64 in 64..1024 (0 = 512) */
+    int32_t block;                  /* persistent form: threads per workgroup, multiple of 64 in
+                                       64..1024 (0 = 512); the flattened form uses 256 */
+    int32_t form;                   /* TFSPH_BATCH_PERSISTENT (0) or TFSPH_BATCH_FLAT */
 } tfsph_batch_tuning;
 
 /* Host-only: workspace bytes for a batch (256-byte aligned buffer). */
@@ -281,11 +293,12 @@ tfsph_status tfsph_batch_init(tfsph_batch **out, const tfsph_batch_desc *desc, t
 /* Change the launch shape (results do not depend on it). */
 tfsph_status tfsph_batch_set_tuning(tfsph_batch *b, const tfsph_batch_tuning *tuning);
 
-/* Advance every instance n_steps IDIC steps with one kernel launch.  The
- * packed state must be the one bound at init (TFSPH_E_STATE otherwise). */
+/* Advance every instance n_steps IDIC steps: one kernel launch (persistent
+ * form) or seven launches per step (flattened form).  The packed state must be
+ * the one bound at init (TFSPH_E_STATE otherwise). */
 tfsph_status tfsph_step_batched(tfsph_batch *b, tfsph_state *packed, int32_t n_steps, void *hip_stream);
 
-/* Same, through a hipGraph captured once per (n_steps, tuning) and replayed. */
+/* Same, through a hipGraph captured once per (n_steps, form, block) and replayed. */
 tfsph_status tfsph_step_batched_graph(tfsph_batch *b, tfsph_state *packed, int32_t n_steps, void *hip_stream);
 
 /* Flags and one-phase-cell count over all instances since the last call (syncs). */

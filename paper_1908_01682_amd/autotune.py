@@ -1,10 +1,12 @@
-"""Launch-shape autotuner for the batched persistent kernel.
+"""Launch-shape autotuner for the batched step.
 
-For a batch signature (device name, dim, precision, instance count, size
-distribution) it times every candidate workgroup size on the real batch,
-checks that every candidate leaves a bitwise-identical state (the method's
-sums are evaluated in a fixed order, so the launch shape must not change a
-single bit), and caches the fastest in a JSON file.
+The candidates are the persistent form (one workgroup per instance) at several
+workgroup sizes and the flattened form (seven launches per step over every
+instance).  For a batch signature (device name, dim, precision, instance count,
+size distribution) it times every candidate on the real batch, checks that every
+candidate leaves a bitwise-identical state (the method's sums are evaluated in a
+fixed order, so the launch shape must not change a single bit), and caches the
+fastest in a JSON file.
 
 Cache path: $TFSPH_AUTOTUNE_CACHE, else ~/.cache/tfsph/autotune.json.
 """
@@ -19,6 +21,7 @@ from typing import Iterable, Optional
 import numpy as np
 
 CANDIDATE_BLOCKS = (256, 512, 768, 1024)
+PERSISTENT, FLAT = 0, 1
 
 
 def cache_path() -> str:
@@ -75,38 +78,48 @@ def _digest(bs) -> str:
 
 
 def tune(bs, steps: int = 20, blocks: Iterable[int] = CANDIDATE_BLOCKS, use_cache: bool = True,
-         path: Optional[str] = None) -> dict:
-    """Pick the fastest workgroup size for BatchedSimulation ``bs`` and apply it.
+         path: Optional[str] = None, flat: bool = True, graph: bool = False) -> dict:
+    """Pick the fastest launch shape for BatchedSimulation ``bs`` and apply it: the persistent
+    form at each workgroup size in ``blocks`` and, with ``flat``, the flattened form.  With
+    ``graph`` every candidate is timed as a replayed hipGraph of ``steps`` steps (captured
+    before the timing), as the caller will run it.
 
-    Returns {"block": b, "ms_per_step": {...}, "bitwise_identical": True, "cached": bool}.
-    The batch state is restored to its entry value before returning.
+    Returns {"form": f, "block": b, "ms_per_step": {...}, "bitwise_identical": True,
+    "cached": bool}; the timing keys are "persistent/<block>" and "flat".  The batch state is
+    restored to its entry value before returning.
     """
     import torch
     dev = torch.cuda.get_device_name(bs.device)
     key = signature(dev, bs.probs, bs.precision)
+    cands = [(PERSISTENT, int(b)) for b in blocks] + ([(FLAT, 256)] if flat else [])
     if use_cache:
         hit = load_cache(path).get(key)
-        if hit and hit.get("block") in tuple(blocks):
-            bs.set_block(int(hit["block"]))
+        if hit and (int(hit.get("form", PERSISTENT)), int(hit.get("block", 0))) in cands:
+            bs.set_tuning(int(hit["block"]), int(hit.get("form", PERSISTENT)))
             return dict(hit, cached=True)
     snap = _snapshot(bs)
     timings, digests = {}, {}
-    for blk in blocks:
+    for form, blk in cands:
+        name = "flat" if form == FLAT else f"persistent/{blk}"
         _restore(bs, snap)
-        bs.set_block(blk)
+        bs.set_tuning(blk, form)
+        run = bs.step_graph if graph else bs.step
+        run(steps if graph else 1)  # capture, or load the code objects, outside the timing
+        _restore(bs, snap)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        bs.step(steps)
+        run(steps)
         torch.cuda.synchronize()
-        timings[int(blk)] = 1e3 * (time.perf_counter() - t0) / steps
-        digests[int(blk)] = _digest(bs)
+        timings[name] = 1e3 * (time.perf_counter() - t0) / steps
+        digests[name] = _digest(bs)
     _restore(bs, snap)
     identical = len(set(digests.values())) == 1
     if not identical:
         raise RuntimeError(f"launch shapes disagree bitwise: {digests}")
     best = min(timings, key=timings.get)
-    bs.set_block(best)
-    entry = {"block": best, "ms_per_step": timings, "bitwise_identical": identical, "device": dev,
-             "steps": steps}
+    form, blk = (FLAT, 256) if best == "flat" else (PERSISTENT, int(best.split("/")[1]))
+    bs.set_tuning(blk, form)
+    entry = {"form": form, "block": blk, "ms_per_step": timings, "bitwise_identical": identical,
+             "device": dev, "steps": steps}
     store(key, entry, path)
     return dict(entry, cached=False)

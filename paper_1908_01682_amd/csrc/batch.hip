@@ -1,5 +1,6 @@
 // Host side of the batched form (declarations and contract: include/tfsph.h):
-// instance table, largest-first launch order, one persistent kernel per call,
+// instance table, largest-first launch order, either one persistent kernel per
+// call or the flattened launches of every step (block tables per instance),
 // optional hipGraph replay.
 #include "../../include/tfsph.h"
 
@@ -9,6 +10,7 @@
 #include <map>
 #include <new>
 #include <numeric>
+#include <tuple>
 #include <vector>
 
 #include "batched.hpp"
@@ -35,7 +37,8 @@ size_t batch_bytes(const std::vector<InstLayout> &L, int dim, Carver &cv, std::v
     int *order = cv.take<int>(n);
     unsigned int *word = cv.take<unsigned int>(64);
     unsigned long long *one = cv.take<unsigned long long>(8);
-    (void)dev_table, (void)order, (void)word, (void)one;
+    int *first = cv.take<int>(size_t(3) * (n + 1));      // block tables of the flattened form
+    (void)dev_table, (void)order, (void)word, (void)one, (void)first;
     for (int i = 0; i < n; ++i) {
         PhaseFlags fg{L[i].mass_g, false, true}, fd{L[i].mass_d, false, false};
         Sorted<R> Sg = carve_phase<R>(cv, L[i].ng, dim, L[i].ncell, fg);
@@ -113,7 +116,10 @@ tfsph_status check_desc(const tfsph_batch_desc *desc, std::vector<InstLayout> &L
 }  // namespace
 
 struct tfsph_batch {
-    int n_inst = 0, dim = 1, prec = 0, block = kDefaultBatchBlock;
+    int n_inst = 0, dim = 1, prec = 0, block = kDefaultBatchBlock, form = TFSPH_BATCH_PERSISTENT;
+    FlatTable flat{};
+    int flat_blocks_g = 0, flat_blocks_d = 0, flat_blocks_c = 0;
+    std::vector<int> host_first;
     tfsph_state bound{};
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -127,7 +133,7 @@ struct tfsph_batch {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
     };
-    std::map<std::pair<int, int>, G> graphs;   // (n_steps, block) -> graph
+    std::map<std::tuple<int, int, int>, G> graphs;   // (n_steps, form, block) -> graph
 };
 
 extern "C" tfsph_status tfsph_batch_workspace_size(const tfsph_batch_desc *desc, size_t *bytes)
@@ -148,7 +154,11 @@ static tfsph_status set_tuning(tfsph_batch *b, const tfsph_batch_tuning *t)
 {
     int blk = (t && t->block) ? t->block : kDefaultBatchBlock;
     if (blk < 64 || blk > kBatchMaxBlock || blk % 64) return fail(TFSPH_E_INVALID_ARG, "block must be a multiple of 64 in 64..1024");
+    const int form = t ? t->form : TFSPH_BATCH_PERSISTENT;
+    if (form != TFSPH_BATCH_PERSISTENT && form != TFSPH_BATCH_FLAT)
+        return fail(TFSPH_E_INVALID_ARG, "form must be TFSPH_BATCH_PERSISTENT or TFSPH_BATCH_FLAT (%d)", form);
     b->block = blk;
+    b->form = form;
     return TFSPH_OK;
 }
 
@@ -167,6 +177,24 @@ static tfsph_status batch_setup(tfsph_batch *b, const tfsph_batch_desc *desc, st
     b->order = head.take<int>(L.size());
     b->F.word = head.take<unsigned int>(64);
     b->F.one_phase = head.take<unsigned long long>(8);
+    int *first = head.take<int>(size_t(3) * (L.size() + 1));
+    // block tables of the flattened form: first block of each instance over its gas particles,
+    // its dust particles and its cells
+    const int n = (int)L.size();
+    b->host_first.assign(size_t(3) * (n + 1), 0);
+    for (int i = 0; i < n; ++i) {
+        b->host_first[i + 1] = b->host_first[i] + blocks_for(L[i].ng);
+        b->host_first[(n + 1) + i + 1] = b->host_first[(n + 1) + i] + blocks_for(L[i].nd);
+        b->host_first[2 * (n + 1) + i + 1] = b->host_first[2 * (n + 1) + i] + blocks_for(L[i].ncell);
+    }
+    b->flat_blocks_g = b->host_first[n];
+    b->flat_blocks_d = b->host_first[(n + 1) + n];
+    b->flat_blocks_c = b->host_first[2 * (n + 1) + n];
+    b->flat.n_inst = n;
+    b->flat.first_g = first;
+    b->flat.first_d = first + (n + 1);
+    b->flat.first_c = first + 2 * (n + 1);
+    HIP_TRY(hipMemcpyAsync(first, b->host_first.data(), sizeof(int) * b->host_first.size(), hipMemcpyHostToDevice, st));
     // largest-first order (work ~ particles); ties by index
     b->host_order.resize(L.size());
     std::iota(b->host_order.begin(), b->host_order.end(), 0);
@@ -256,9 +284,48 @@ static bool same_state(const tfsph_state &a, const tfsph_state &b)
     return true;
 }
 
+// The flattened form: every phase of a step is one launch over all instances.  The
+// first step counts from the caller's arrays; later steps use the slots claimed by
+// the previous step's finish kernel.
+template <typename R, int DIM>
+static tfsph_status launch_flat_t(tfsph_batch *b, int n_steps, hipStream_t st)
+{
+    auto *t = static_cast<const Inst<R> *>(b->table);
+    const FlatTable T = b->flat;
+    const dim3 blk(kBlock);
+    const dim3 gd(b->flat_blocks_g + b->flat_blocks_d), gg(b->flat_blocks_g), gc(b->flat_blocks_c);
+    if (gc.x) hipLaunchKernelGGL((k_flat_zero<R>), gc, blk, 0, st, t, T);
+    if (gd.x) hipLaunchKernelGGL((k_flat_count<R>), gd, blk, 0, st, t, T);
+    LAUNCH_CHECK("flat_count");
+    for (int s = 0; s < n_steps; ++s) {
+        hipLaunchKernelGGL((k_flat_scan<R>), dim3(2 * b->n_inst), blk, 0, st, t);
+        if (gd.x) {
+            hipLaunchKernelGGL((k_flat_scatter<R>), gd, blk, 0, st, t, T);
+            hipLaunchKernelGGL((k_flat_rank_gather<R>), gd, blk, 0, st, t, T, b->F.word);
+        }
+        if (gg.x) {
+            hipLaunchKernelGGL((k_flat_density<R, DIM>), gg, blk, 0, st, t, T);
+            hipLaunchKernelGGL((k_flat_predict<R, DIM>), gg, blk, 0, st, t, T);
+        }
+        if (gc.x) hipLaunchKernelGGL((k_flat_solve<R, DIM>), gc, blk, 0, st, t, T, b->F);
+        if (gd.x) hipLaunchKernelGGL((k_flat_finish<R, DIM>), gd, blk, 0, st, t, T, b->F);
+        LAUNCH_CHECK("flat_step");
+    }
+    return TFSPH_OK;
+}
+
+static tfsph_status launch_flat(tfsph_batch *b, int n_steps, hipStream_t st)
+{
+    if (n_steps == 0) return TFSPH_OK;
+    if (b->prec == TFSPH_F64)
+        return b->dim == 1 ? launch_flat_t<double, 1>(b, n_steps, st) : launch_flat_t<double, 2>(b, n_steps, st);
+    return b->dim == 1 ? launch_flat_t<float, 1>(b, n_steps, st) : launch_flat_t<float, 2>(b, n_steps, st);
+}
+
 static tfsph_status launch_batched(tfsph_batch *b, int n_steps, hipStream_t st)
 {
     if (n_steps == 0) return TFSPH_OK;
+    if (b->form == TFSPH_BATCH_FLAT) return launch_flat(b, n_steps, st);
     const dim3 grid(b->n_inst), block(b->block);
     if (b->prec == TFSPH_F64) {
         auto *t = static_cast<const Inst<double> *>(b->table);
@@ -290,7 +357,7 @@ extern "C" tfsph_status tfsph_step_batched_graph(tfsph_batch *b, tfsph_state *pa
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     b->last_stream = st;
     if (n_steps == 0) return TFSPH_OK;
-    auto key = std::make_pair((int)n_steps, b->block);
+    auto key = std::make_tuple((int)n_steps, b->form, b->form == TFSPH_BATCH_FLAT ? 0 : b->block);
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
         if (!b->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));

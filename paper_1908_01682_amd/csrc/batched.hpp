@@ -179,4 +179,184 @@ k_batched(const Inst<R> *__restrict__ insts, const int *__restrict__ order, int 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Flattened form: one launch per phase of the step covers every instance.  The
+// blocks of a launch are dealt out per instance, so a block never straddles two
+// instances: first[i] is the first block of instance i over the launch's items
+// (gas particles, dust particles or cells, kBlock items per block) and first[n]
+// the block total.  A block finds its instance by a binary search of that table
+// (the same for every lane).  Each item calls the same device functions as the
+// single-problem kernels and the persistent kernel, so every instance evolves
+// bitwise as it does through tfsph_step.  The launch time is that of the whole
+// batch's work spread over the chip, not that of its largest instance.
+// ---------------------------------------------------------------------------
+struct FlatTable {
+    int n_inst;
+    const int *first_g;      // [n_inst + 1] blocks over gas particles
+    const int *first_d;      // [n_inst + 1] blocks over dust particles
+    const int *first_c;      // [n_inst + 1] blocks over cells
+};
+
+// instance of block b (first[0] = 0 <= b < first[n]): the largest i with first[i] <= b
+__device__ __forceinline__ int flat_instance(const int *__restrict__ first, int n, int b)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Item index of this thread inside its instance, for a launch over gas blocks
+// then dust blocks (gas = true for the first first_g[n] blocks).
+__device__ __forceinline__ int flat_item(const FlatTable &T, bool &gas, int &inst)
+{
+    const int nbg = T.first_g[T.n_inst];
+    gas = int(blockIdx.x) < nbg;
+    const int b = gas ? int(blockIdx.x) : int(blockIdx.x) - nbg;
+    const int *first = gas ? T.first_g : T.first_d;
+    inst = flat_instance(first, T.n_inst, b);
+    return (b - first[inst]) * kBlock + int(threadIdx.x);
+}
+
+__device__ __forceinline__ int flat_cell_item(const FlatTable &T, int &inst)
+{
+    inst = flat_instance(T.first_c, T.n_inst, int(blockIdx.x));
+    return (int(blockIdx.x) - T.first_c[inst]) * kBlock + int(threadIdx.x);
+}
+
+// clear both histograms (the first step of a call counts from the caller's arrays)
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_flat_zero(const Inst<R> *__restrict__ insts, FlatTable T)
+{
+    int i;
+    const int c = flat_cell_item(T, i);
+    const Inst<R> &I = insts[i];
+    if (c < I.G.ncell) {
+        I.Sg.count[c] = 0;
+        I.Sd.count[c] = 0;
+    }
+}
+
+// histogram + slot claims from the caller's arrays
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_flat_count(const Inst<R> *__restrict__ insts, FlatTable T)
+{
+    bool gas;
+    int inst;
+    const int i = flat_item(T, gas, inst);
+    const Inst<R> &I = insts[inst];
+    const Phase<R> &P = gas ? I.Pg : I.Pd;
+    const Sorted<R> &S = gas ? I.Sg : I.Sd;
+    const int key = i < S.n ? safe_cell(P.cell[i], I.G.ncell) : -1;     // every lane claims (wave shuffles)
+    const int sl = claim_slot(S.count, key);
+    if (i < S.n) S.slot[i] = sl;
+}
+
+// exclusive scan of each instance's histograms, one block per instance and phase;
+// the counts are cleared once consumed
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_flat_scan(const Inst<R> *__restrict__ insts)
+{
+    __shared__ int lds[kBatchMaxBlock / 64];
+    const Inst<R> &I = insts[blockIdx.x >> 1];
+    const Sorted<R> &S = (blockIdx.x & 1) ? I.Sd : I.Sg;
+    const int ncell = I.G.ncell;
+    block_scan_cells(S.count, S.start, ncell, lds);
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncell; c += blockDim.x) S.count[c] = 0;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_flat_scatter(const Inst<R> *__restrict__ insts, FlatTable T)
+{
+    bool gas;
+    int inst;
+    const int i = flat_item(T, gas, inst);
+    const Inst<R> &I = insts[inst];
+    const Phase<R> &P = gas ? I.Pg : I.Pd;
+    const Sorted<R> &S = gas ? I.Sg : I.Sd;
+    if (i >= S.n) return;
+    const int pos = S.start[safe_cell(P.cell[i], I.G.ncell)] + S.slot[i];
+    S.tmp_idx[pos] = i;
+    S.tmp_id[pos] = P.id[i];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_flat_rank_gather(const Inst<R> *__restrict__ insts, FlatTable T,
+                                                             unsigned int *flags)
+{
+    bool gas;
+    int inst;
+    const int j = flat_item(T, gas, inst);
+    const Inst<R> &I = insts[inst];
+    const Sorted<R> &S = gas ? I.Sg : I.Sd;
+    if (j < S.n) rank_gather_one(I.G, gas ? I.Pg : I.Pd, S, j, flags);
+}
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(kBlock) k_flat_density(const Inst<R> *__restrict__ insts, FlatTable T)
+{
+    const int inst = flat_instance(T.first_g, T.n_inst, int(blockIdx.x));
+    const Inst<R> &I = insts[inst];
+    const int a = (int(blockIdx.x) - T.first_g[inst]) * kBlock + int(threadIdx.x);
+    if (a < I.Sg.n) density_store<R, DIM>(I.G, I.Ph, I.Sg, a, 1);
+}
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(kBlock) k_flat_predict(const Inst<R> *__restrict__ insts, FlatTable T)
+{
+    const int inst = flat_instance(T.first_g, T.n_inst, int(blockIdx.x));
+    const Inst<R> &I = insts[inst];
+    const int a = (int(blockIdx.x) - T.first_g[inst]) * kBlock + int(threadIdx.x);
+    if (a < I.Sg.n) gas_predict<R, DIM>(I.G, I.Ph, I.Sg, I.Pg, a);
+}
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(kBlock) k_flat_solve(const Inst<R> *__restrict__ insts, FlatTable T, Flags F)
+{
+    __shared__ int s_one;
+    if (threadIdx.x == 0) s_one = 0;
+    __syncthreads();
+    int inst;
+    const int c = flat_cell_item(T, inst);
+    const Inst<R> &I = insts[inst];
+    if (c < I.G.ncell && solve_cell<R, DIM>(I.Ph, I.Sg, I.Sd, c, I.cs[c])) atomicAdd(&s_one, 1);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_one) {
+        atomicOr(F.word, 2u);
+        atomicAdd(F.one_phase, (unsigned long long)s_one);
+    }
+}
+
+// implicit update, move and carry, then the slot claims of the next step's
+// counting sort (the new cell is known here)
+template <typename R, int DIM>
+__global__ void __launch_bounds__(kBlock) k_flat_finish(const Inst<R> *__restrict__ insts, FlatTable T, Flags F)
+{
+    bool gas;
+    int inst;
+    const int i = flat_item(T, gas, inst);
+    const Inst<R> &I = insts[inst];
+    const Sorted<R> &S = gas ? I.Sg : I.Sd;
+    R s2 = signal_floor(I.Ph);
+    bool bad = false;
+    int key = -1;
+    if (i < S.n) {
+        if (gas) {
+            bad = !gas_finish<R, DIM>(I.G, I.Ph, I.Sg, I.Pg, i, I.cs[I.Sg.cell[i]], s2);
+            key = I.Pg.cell[i];
+        } else {
+            bad = !dust_finish<R, DIM>(I.G, I.Ph, I.Sd, I.Pd, i, I.cs[I.Sd.cell[i]], s2);
+            key = I.Pd.cell[i];
+        }
+    }
+    const int sl = claim_slot(S.count, key);
+    if (i < S.n) S.slot[i] = sl;
+    if (bad) atomicOr(F.word, 1u);
+    if (I.Ph.vlim2 > R(0) && s2 > I.Ph.vlim2) atomicOr(F.word, kFlagCfl);
+}
+
 }  // namespace tfsph

@@ -64,7 +64,10 @@ class BatchDesc(ctypes.Structure):
 
 
 class BatchTuning(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int32)]
+    _fields_ = [("block", ctypes.c_int32), ("form", ctypes.c_int32)]
+
+
+TFSPH_BATCH_PERSISTENT, TFSPH_BATCH_FLAT = 0, 1
 
 
 _lib = None
@@ -467,9 +470,11 @@ def tfsph_batch_destroy(b) -> None:
 
 class BatchedSimulation:
     """Many independent problems (same dim, isothermal) in packed device arrays,
-    advanced together by one persistent launch per call."""
+    advanced together: one persistent launch per call (form TFSPH_BATCH_PERSISTENT) or
+    seven launches per step over every instance (TFSPH_BATCH_FLAT)."""
 
-    def __init__(self, probs, precision: int = TFSPH_F32, device="cuda", block: int = 0, stream=None):
+    def __init__(self, probs, precision: int = TFSPH_F32, device="cuda", block: int = 0, stream=None,
+                 form: int = TFSPH_BATCH_PERSISTENT):
         import torch
         self.probs = list(probs)
         self.precision = precision
@@ -509,19 +514,22 @@ class BatchedSimulation:
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.workspace.data_ptr()) % 256
         self._ws = self.workspace[off:]
-        self.handle = tfsph_batch_init(self.desc, self.state, BatchTuning(block), self._ws, self.ws_bytes, stream)
+        self.block, self.form = block, form
+        self.handle = tfsph_batch_init(self.desc, self.state, BatchTuning(block, form), self._ws, self.ws_bytes,
+                                       stream)
+
+    def set_tuning(self, block: int, form: int = TFSPH_BATCH_PERSISTENT) -> None:
+        tfsph_batch_set_tuning(self.handle, BatchTuning(block, form))
+        self.block, self.form = block, form
 
     def set_block(self, block: int) -> None:
-        tfsph_batch_set_tuning(self.handle, BatchTuning(block))
+        self.set_tuning(block, TFSPH_BATCH_PERSISTENT)
 
     def step(self, n: int) -> None:
         tfsph_step_batched(self.handle, self.state, n, self.stream)
 
     def step_graph(self, n: int) -> None:
         tfsph_step_batched_graph(self.handle, self.state, n, self.stream)
-
-    def signal_speed(self) -> float:
-        return tfsph_signal_speed(self.ctx)
 
     def flags(self):
         return tfsph_batch_get_flags(self.handle)

@@ -1,8 +1,8 @@
-"""Batched persistent form and hipGraph replay.
+"""Batched forms (the persistent kernel and the flattened launches) and hipGraph replay.
 
 Every instance of a batch must evolve bitwise as it does alone through
-tfsph_step; results must not depend on the launch shape; graph replays must
-equal eager launches on every replay.
+tfsph_step, in either form; results must not depend on the launch shape or
+the form; graph replays must equal eager launches on every replay.
 """
 import numpy as np
 import pytest
@@ -54,12 +54,21 @@ def _same(a, b):
         assert np.array_equal(A[k], B[k]), k
 
 
+FORMS = {"persistent": 0, "flat": 1, "mixed": 2}
+
+
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("dim,precision,kmode", [(1, 0, False), (1, 1, False), (2, 0, False), (1, 0, True)])
-def test_batched_equals_plain_bitwise(dim, precision, kmode):
+def test_batched_equals_plain_bitwise(dim, precision, kmode, form):
+    """Both forms, and a call of each in turn (the second call counts from the arrays the first
+    left), against tfsph_step on each instance alone."""
     probs = _batch_1d_kmode() if kmode else (_batch_1d() if dim == 1 else _batch_2d())
-    banner(f"batched dim={dim} precision={precision} n_inst={len(probs)}")
-    bs = T.BatchedSimulation(probs, precision=precision)
+    banner(f"batched dim={dim} precision={precision} n_inst={len(probs)} form={form}")
+    f0 = T.TFSPH_BATCH_PERSISTENT if form == "persistent" else T.TFSPH_BATCH_FLAT
+    f1 = T.TFSPH_BATCH_PERSISTENT if form != "flat" else T.TFSPH_BATCH_FLAT
+    bs = T.BatchedSimulation(probs, precision=precision, form=f0)
     bs.step(7)
+    bs.set_tuning(256, f1)
     bs.step(13)
     torch.cuda.synchronize()
     for i, p in enumerate(probs):
@@ -109,10 +118,11 @@ def test_batched_launch_shape_invariance():
             _same(d0, d1)
 
 
-def test_batched_graph_replays_equal_eager():
+@pytest.mark.parametrize("form", [0, 1], ids=["persistent", "flat"])
+def test_batched_graph_replays_equal_eager(form):
     probs = _batch_1d(seed=9, n_inst=4)
-    eager = T.BatchedSimulation(probs, precision=0)
-    graph = T.BatchedSimulation(probs, precision=0)
+    eager = T.BatchedSimulation(probs, precision=0, form=form)
+    graph = T.BatchedSimulation(probs, precision=0, form=form)
     for rep in range(4):
         eager.step(6)
         graph.step_graph(6)
@@ -162,21 +172,26 @@ def test_autotuner_picks_a_shape_and_caches(tmp_path):
     bs = T.BatchedSimulation(probs, precision=0)
     path = str(tmp_path / "tune.json")
     before = [bs.instance(i) for i in range(len(probs))]
-    r1 = A.tune(bs, steps=4, blocks=(256, 512, 1024), path=path)
-    assert r1["block"] in (256, 512, 1024) and r1["bitwise_identical"] and not r1["cached"]
+    r1 = A.tune(bs, steps=4, blocks=(256, 512, 1024), path=path, graph=True)
+    assert r1["bitwise_identical"] and not r1["cached"]
+    assert set(r1["ms_per_step"]) == {"persistent/256", "persistent/512", "persistent/1024", "flat"}
+    assert (r1["form"], r1["block"]) in ((A.PERSISTENT, 256), (A.PERSISTENT, 512), (A.PERSISTENT, 1024),
+                                         (A.FLAT, 256))
     after = [bs.instance(i) for i in range(len(probs))]      # state restored
     for (g0, d0), (g1, d1) in zip(before, after):
         for k in ("cell", "id", "off", "vel"):
             assert np.array_equal(g0[k], g1[k]) and np.array_equal(d0[k], d1[k])
-    r2 = A.tune(bs, steps=4, blocks=(256, 512, 1024), path=path)
-    assert r2["cached"] and r2["block"] == r1["block"]
+    r2 = A.tune(bs, steps=4, blocks=(256, 512, 1024), path=path, graph=True)
+    assert r2["cached"] and (r2["form"], r2["block"]) == (r1["form"], r1["block"])
+    assert (bs.form, bs.block) == (r1["form"], r1["block"])
     bs.close()
 
 
 def test_full_size_batched_equals_plain_on_sampled_instances(tmp_path):
     """The full batched workload (256 uneven 1D waves, 5.4M particles, 500 steps) in the launch
-    configuration the benchmark times (autotuned workgroup size, hipGraph replay): sampled
-    instances, the largest and the smallest among them, are bitwise what tfsph_step gives alone."""
+    configuration the benchmark times (form and workgroup size autotuned on graph replays,
+    hipGraph replay), and in the other form: sampled instances, the largest and the smallest
+    among them, are bitwise what tfsph_step gives alone."""
     from paper_1908_01682_amd import autotune as A
     probs = I.batched_waves()
     steps = probs[0].steps
@@ -185,17 +200,24 @@ def test_full_size_batched_equals_plain_on_sampled_instances(tmp_path):
     sample = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), *rng.integers(0, len(probs), 2).tolist()})
     banner(f"batched full size: {len(probs)} instances, {sum(sizes)} particles, {steps} steps, sample {sample}")
     bs = T.BatchedSimulation(probs, precision=T.TFSPH_F32)
-    A.tune(bs, steps=4, path=str(tmp_path / "tune.json"))
+    A.tune(bs, steps=4, path=str(tmp_path / "tune.json"), graph=True)
+    other = T.BatchedSimulation(probs, precision=T.TFSPH_F32, block=512,
+                                form=T.TFSPH_BATCH_PERSISTENT if bs.form == T.TFSPH_BATCH_FLAT else T.TFSPH_BATCH_FLAT)
+    banner(f"batched full size: tuned form {bs.form} block {bs.block}, other form {other.form}")
     bs.step_graph(steps)
+    other.step_graph(steps)
     torch.cuda.synchronize()
-    flags, _ = bs.flags()
-    assert not (flags & T.TFSPH_FLAG_NONFINITE)
+    for b in (bs, other):
+        flags, _ = b.flags()
+        assert not (flags & T.TFSPH_FLAG_NONFINITE)
     for i in sample:
         sim = T.Simulation(probs[i], precision=T.TFSPH_F32)
         sim.step(steps)
         torch.cuda.synchronize()
-        g, d = bs.instance(i)
-        _same(g, sim.gas.numpy())
-        _same(d, sim.dust.numpy())
+        for b in (bs, other):
+            g, d = b.instance(i)
+            _same(g, sim.gas.numpy())
+            _same(d, sim.dust.numpy())
         sim.close()
     bs.close()
+    other.close()
