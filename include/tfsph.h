@@ -270,9 +270,9 @@ typedef struct {
  *    instance for all its steps (no workgroup waits on another); the launch
  *    lasts as long as the largest instance takes on one compute unit.
  *  - TFSPH_BATCH_FLAT: each phase of a step (scan, scatter, rank + gather,
- *    density, force + predictor, cell solve, update) is one launch over every
- *    instance, with 256-thread blocks dealt out per instance (a block never
- *    straddles two); seven launches per step, best replayed as a hipGraph. */
+ *    density, force + predictor, cell sums + solve + update) is one launch over
+ *    every instance, with blocks dealt out per instance (a block never
+ *    straddles two); six launches per step, best replayed as a hipGraph. */
 enum { TFSPH_BATCH_PERSISTENT = 0, TFSPH_BATCH_FLAT = 1 };
 
 typedef struct {
@@ -294,7 +294,7 @@ tfsph_status tfsph_batch_init(tfsph_batch **out, const tfsph_batch_desc *desc, t
 tfsph_status tfsph_batch_set_tuning(tfsph_batch *b, const tfsph_batch_tuning *tuning);
 
 /* Advance every instance n_steps IDIC steps: one kernel launch (persistent
- * form) or seven launches per step (flattened form).  The packed state must be
+ * form) or six launches per step (flattened form).  The packed state must be
  * the one bound at init (TFSPH_E_STATE otherwise). */
 tfsph_status tfsph_step_batched(tfsph_batch *b, tfsph_state *packed, int32_t n_steps, void *hip_stream);
 

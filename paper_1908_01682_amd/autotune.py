@@ -1,7 +1,7 @@
 """Launch-shape autotuner for the batched step.
 
 The candidates are the persistent form (one workgroup per instance) at several
-workgroup sizes and the flattened form (seven launches per step over every
+workgroup sizes and the flattened form (six launches per step over every
 instance).  For a batch signature (device name, dim, precision, instance count,
 size distribution) it times every candidate on the real batch, checks that every
 candidate leaves a bitwise-identical state (the method's sums are evaluated in a

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "batched.hpp"
+#include "enqueue.hpp"
 #include "host.hpp"
 
 using namespace tfsph;
@@ -22,6 +23,8 @@ using namespace tfsph_host;
 namespace {
 
 constexpr int kDefaultBatchBlock = 512;
+// cells per block of the flattened form's update launch (the single-problem default)
+inline int kFlatCells(int dim) { return default_cells_per_block(dim); }
 
 struct InstLayout {
     int ng, nd, ncell;
@@ -185,7 +188,8 @@ static tfsph_status batch_setup(tfsph_batch *b, const tfsph_batch_desc *desc, st
     for (int i = 0; i < n; ++i) {
         b->host_first[i + 1] = b->host_first[i] + blocks_for(L[i].ng);
         b->host_first[(n + 1) + i + 1] = b->host_first[(n + 1) + i] + blocks_for(L[i].nd);
-        b->host_first[2 * (n + 1) + i + 1] = b->host_first[2 * (n + 1) + i] + blocks_for(L[i].ncell);
+        b->host_first[2 * (n + 1) + i + 1] =
+            b->host_first[2 * (n + 1) + i] + (L[i].ncell + kFlatCells(b->dim) - 1) / kFlatCells(b->dim);
     }
     b->flat_blocks_g = b->host_first[n];
     b->flat_blocks_d = b->host_first[(n + 1) + n];
@@ -194,6 +198,7 @@ static tfsph_status batch_setup(tfsph_batch *b, const tfsph_batch_desc *desc, st
     b->flat.first_g = first;
     b->flat.first_d = first + (n + 1);
     b->flat.first_c = first + 2 * (n + 1);
+    b->flat.cells_per_block = kFlatCells(b->dim);
     HIP_TRY(hipMemcpyAsync(first, b->host_first.data(), sizeof(int) * b->host_first.size(), hipMemcpyHostToDevice, st));
     // largest-first order (work ~ particles); ties by index
     b->host_order.resize(L.size());
@@ -297,8 +302,9 @@ static tfsph_status launch_flat_t(tfsph_batch *b, int n_steps, hipStream_t st)
     if (gc.x) hipLaunchKernelGGL((k_flat_zero<R>), gc, blk, 0, st, t, T);
     if (gd.x) hipLaunchKernelGGL((k_flat_count<R>), gd, blk, 0, st, t, T);
     LAUNCH_CHECK("flat_count");
+    const size_t lds = update_lds_bytes<R>(T.cells_per_block);
     for (int s = 0; s < n_steps; ++s) {
-        hipLaunchKernelGGL((k_flat_scan<R>), dim3(2 * b->n_inst), blk, 0, st, t);
+        hipLaunchKernelGGL((k_flat_scan<R>), dim3(2 * b->n_inst), dim3(kBatchMaxBlock), 0, st, t);
         if (gd.x) {
             hipLaunchKernelGGL((k_flat_scatter<R>), gd, blk, 0, st, t, T);
             hipLaunchKernelGGL((k_flat_rank_gather<R>), gd, blk, 0, st, t, T, b->F.word);
@@ -307,8 +313,7 @@ static tfsph_status launch_flat_t(tfsph_batch *b, int n_steps, hipStream_t st)
             hipLaunchKernelGGL((k_flat_density<R, DIM>), gg, blk, 0, st, t, T);
             hipLaunchKernelGGL((k_flat_predict<R, DIM>), gg, blk, 0, st, t, T);
         }
-        if (gc.x) hipLaunchKernelGGL((k_flat_solve<R, DIM>), gc, blk, 0, st, t, T, b->F);
-        if (gd.x) hipLaunchKernelGGL((k_flat_finish<R, DIM>), gd, blk, 0, st, t, T, b->F);
+        if (gc.x) hipLaunchKernelGGL((k_flat_update<R, DIM>), gc, blk, lds, st, t, T, b->F);
         LAUNCH_CHECK("flat_step");
     }
     return TFSPH_OK;

@@ -54,18 +54,32 @@ __device__ __forceinline__ int block_scan_any(int v, int *lds_waves, int &total)
 
 // start[c] = sum of count[0..c), start[ncell] = total, for one instance: each
 // thread sums a contiguous run of cells, one block scan combines the runs.
+// The run's counts are loaded kRunLoad at a time with every load issued before
+// the sum uses it, so a run costs a few memory latencies, not one per cell.
+constexpr int kRunLoad = 16;
 __device__ __forceinline__ void block_scan_cells(const int *count, int *start, int ncell, int *lds)
 {
     const int per = (ncell + blockDim.x - 1) / blockDim.x;
     const int c0 = min(int(threadIdx.x) * per, ncell), c1 = min(c0 + per, ncell);
     int s = 0;
-    for (int c = c0; c < c1; ++c) s += count[c];
+    for (int c = c0; c < c1; c += kRunLoad) {
+        int v[kRunLoad];
+#pragma unroll
+        for (int u = 0; u < kRunLoad; ++u) v[u] = c + u < c1 ? count[c + u] : 0;
+#pragma unroll
+        for (int u = 0; u < kRunLoad; ++u) s += v[u];
+    }
     int total;
     int ex = block_scan_any(s, lds, total);
-    for (int c = c0; c < c1; ++c) {
-        const int v = count[c];
-        start[c] = ex;
-        ex += v;
+    for (int c = c0; c < c1; c += kRunLoad) {
+        int v[kRunLoad];
+#pragma unroll
+        for (int u = 0; u < kRunLoad; ++u) v[u] = c + u < c1 ? count[c + u] : 0;
+#pragma unroll
+        for (int u = 0; u < kRunLoad; ++u) {
+            if (c + u < c1) start[c + u] = ex;
+            ex += v[u];
+        }
     }
     if (threadIdx.x == 0) start[ncell] = total;
 }
@@ -194,7 +208,8 @@ struct FlatTable {
     int n_inst;
     const int *first_g;      // [n_inst + 1] blocks over gas particles
     const int *first_d;      // [n_inst + 1] blocks over dust particles
-    const int *first_c;      // [n_inst + 1] blocks over cells
+    const int *first_c;      // [n_inst + 1] blocks over cells, cells_per_block cells per block
+    int cells_per_block;
 };
 
 // instance of block b (first[0] = 0 <= b < first[n]): the largest i with first[i] <= b
@@ -224,7 +239,8 @@ __device__ __forceinline__ int flat_item(const FlatTable &T, bool &gas, int &ins
 __device__ __forceinline__ int flat_cell_item(const FlatTable &T, int &inst)
 {
     inst = flat_instance(T.first_c, T.n_inst, int(blockIdx.x));
-    return (int(blockIdx.x) - T.first_c[inst]) * kBlock + int(threadIdx.x);
+    const int c = int(threadIdx.x) < T.cells_per_block ? int(threadIdx.x) : 1 << 30;
+    return (int(blockIdx.x) - T.first_c[inst]) * T.cells_per_block + c;
 }
 
 // clear both histograms (the first step of a call counts from the caller's arrays)
@@ -258,7 +274,7 @@ __global__ void __launch_bounds__(kBlock) k_flat_count(const Inst<R> *__restrict
 // exclusive scan of each instance's histograms, one block per instance and phase;
 // the counts are cleared once consumed
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_flat_scan(const Inst<R> *__restrict__ insts)
+__global__ void __launch_bounds__(kBatchMaxBlock) k_flat_scan(const Inst<R> *__restrict__ insts)
 {
     __shared__ int lds[kBatchMaxBlock / 64];
     const Inst<R> &I = insts[blockIdx.x >> 1];
@@ -314,49 +330,19 @@ __global__ void __launch_bounds__(kBlock) k_flat_predict(const Inst<R> *__restri
     if (a < I.Sg.n) gas_predict<R, DIM>(I.G, I.Ph, I.Sg, I.Pg, a);
 }
 
+// cell sums, implicit solve, particle update, move and carry of a run of
+// kFlatCells cells of one instance (the single-problem update kernel's block),
+// with the slot claims of the next step's counting sort
 template <typename R, int DIM>
-__global__ void __launch_bounds__(kBlock) k_flat_solve(const Inst<R> *__restrict__ insts, FlatTable T, Flags F)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1)))
+k_flat_update(const Inst<R> *__restrict__ insts, FlatTable T, Flags F)
 {
-    __shared__ int s_one;
-    if (threadIdx.x == 0) s_one = 0;
-    __syncthreads();
-    int inst;
-    const int c = flat_cell_item(T, inst);
+    extern __shared__ unsigned char smem_raw[];
+    const int inst = flat_instance(T.first_c, T.n_inst, int(blockIdx.x));
     const Inst<R> &I = insts[inst];
-    if (c < I.G.ncell && solve_cell<R, DIM>(I.Ph, I.Sg, I.Sd, c, I.cs[c])) atomicAdd(&s_one, 1);
-    __syncthreads();
-    if (threadIdx.x == 0 && s_one) {
-        atomicOr(F.word, 2u);
-        atomicAdd(F.one_phase, (unsigned long long)s_one);
-    }
-}
-
-// implicit update, move and carry, then the slot claims of the next step's
-// counting sort (the new cell is known here)
-template <typename R, int DIM>
-__global__ void __launch_bounds__(kBlock) k_flat_finish(const Inst<R> *__restrict__ insts, FlatTable T, Flags F)
-{
-    bool gas;
-    int inst;
-    const int i = flat_item(T, gas, inst);
-    const Inst<R> &I = insts[inst];
-    const Sorted<R> &S = gas ? I.Sg : I.Sd;
-    R s2 = signal_floor(I.Ph);
-    bool bad = false;
-    int key = -1;
-    if (i < S.n) {
-        if (gas) {
-            bad = !gas_finish<R, DIM>(I.G, I.Ph, I.Sg, I.Pg, i, I.cs[I.Sg.cell[i]], s2);
-            key = I.Pg.cell[i];
-        } else {
-            bad = !dust_finish<R, DIM>(I.G, I.Ph, I.Sd, I.Pd, i, I.cs[I.Sd.cell[i]], s2);
-            key = I.Pd.cell[i];
-        }
-    }
-    const int sl = claim_slot(S.count, key);
-    if (i < S.n) S.slot[i] = sl;
-    if (bad) atomicOr(F.word, 1u);
-    if (I.Ph.vlim2 > R(0) && s2 > I.Ph.vlim2) atomicOr(F.word, kFlagCfl);
+    const int c0 = (int(blockIdx.x) - T.first_c[inst]) * T.cells_per_block;
+    const int c1 = min(c0 + T.cells_per_block, I.G.ncell);
+    update_block<R, DIM, true>(I.G, I.Ph, I.Sg, I.Sd, I.Pg, I.Pd, F, c0, c1, smem_raw);
 }
 
 }  // namespace tfsph

@@ -11,6 +11,7 @@
 //              moves it and carries its offset back into [0, Delta).
 #pragma once
 
+#include "binning.hpp"
 #include "common.hpp"
 
 namespace tfsph {
@@ -870,23 +871,21 @@ constexpr size_t update_lds_bytes(int cells_per_block)
     return sizeof(CellSolve<R>) * cells_per_block + 2 * sizeof(R4<R>) * kStage;
 }
 
-// Cell sums, implicit solve and particle updates of a contiguous run of cells
-// per block; the predictor v~ (and e) of the gas comes from k_gas_predict.
-// The block first copies mass and velocity of its particles into LDS with
-// coalesced loads, so the serial per-cell sums read LDS.
-template <typename R, int DIM>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1)))
-k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R> Pd, Flags F, int cells_per_block,
-         int nblocks)
+// Cell sums, implicit solve and particle updates of the cells [c0, c1) of one
+// block; the predictor v~ (and e) of the gas comes from k_gas_predict.  The
+// block first copies mass and velocity of its particles into LDS with
+// coalesced loads, so the serial per-cell sums read LDS.  With CLAIM the
+// finished particles also claim their slots in the next step's counting sort
+// (the new cell is known here; the histograms must be zero on entry).
+template <typename R, int DIM, bool CLAIM>
+__device__ __forceinline__ void update_block(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg,
+                                             const Sorted<R> &Sd, const Phase<R> &Pg, const Phase<R> &Pd,
+                                             const Flags &F, int c0, int c1, unsigned char *smem_raw)
 {
-    extern __shared__ unsigned char smem_raw[];
     R4<R> *stg = reinterpret_cast<R4<R> *>(smem_raw);          // [kStage] gas: m, v~
     R4<R> *std_ = stg + kStage;                                  // [kStage] dust: m, u
     CellSolve<R> *cs = reinterpret_cast<CellSolve<R> *>(std_ + kStage);
     __shared__ int s_bad, s_one;
-    const int blk = xcd_block(nblocks);
-    const int c0 = blk * cells_per_block;
-    const int c1 = min(c0 + cells_per_block, G.ncell);
     if (threadIdx.x == 0) { s_bad = 0; s_one = 0; }
 
     const int ga = Sg.start[c0], gb = Sg.start[c1];
@@ -937,10 +936,34 @@ k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R
     // (2) implicit particle update (eqs. 19-20), position update, carry
     int bad = 0;
     R s2 = signal_floor(Ph);
-    for (int a = ga + threadIdx.x; a < gb; a += kBlock)
-        bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0], s2, staged ? &stg[a - ga] : nullptr);
-    for (int j = da + threadIdx.x; j < db; j += kBlock)
-        bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[Sd.cell[j] - c0], s2, staged ? &std_[j - da] : nullptr);
+    if constexpr (CLAIM) {
+        // every lane of a wave takes part in each claim (wave shuffles)
+        for (int base = ga; base < gb; base += kBlock) {
+            const int a = base + threadIdx.x;
+            int key = -1;
+            if (a < gb) {
+                bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0], s2, staged ? &stg[a - ga] : nullptr);
+                key = Pg.cell[a];
+            }
+            const int sl = claim_slot(Sg.count, key);
+            if (a < gb) Sg.slot[a] = sl;
+        }
+        for (int base = da; base < db; base += kBlock) {
+            const int j = base + threadIdx.x;
+            int key = -1;
+            if (j < db) {
+                bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[Sd.cell[j] - c0], s2, staged ? &std_[j - da] : nullptr);
+                key = Pd.cell[j];
+            }
+            const int sl = claim_slot(Sd.count, key);
+            if (j < db) Sd.slot[j] = sl;
+        }
+    } else {
+        for (int a = ga + threadIdx.x; a < gb; a += kBlock)
+            bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0], s2, staged ? &stg[a - ga] : nullptr);
+        for (int j = da + threadIdx.x; j < db; j += kBlock)
+            bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[Sd.cell[j] - c0], s2, staged ? &std_[j - da] : nullptr);
+    }
     publish_speed(Ph, F, s2);
     if (bad) atomicOr(&s_bad, 1);
     __syncthreads();
@@ -951,6 +974,19 @@ k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R
             atomicAdd(F.one_phase, (unsigned long long)s_one);
         }
     }
+}
+
+// One block per contiguous run of cells_per_block cells.
+template <typename R, int DIM>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1)))
+k_update(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Phase<R> Pd, Flags F, int cells_per_block,
+         int nblocks)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int blk = xcd_block(nblocks);
+    const int c0 = blk * cells_per_block;
+    const int c1 = min(c0 + cells_per_block, G.ncell);
+    update_block<R, DIM, false>(G, Ph, Sg, Sd, Pg, Pd, F, c0, c1, smem_raw);
 }
 
 }  // namespace tfsph

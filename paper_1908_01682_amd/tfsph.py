@@ -471,7 +471,7 @@ def tfsph_batch_destroy(b) -> None:
 class BatchedSimulation:
     """Many independent problems (same dim, isothermal) in packed device arrays,
     advanced together: one persistent launch per call (form TFSPH_BATCH_PERSISTENT) or
-    seven launches per step over every instance (TFSPH_BATCH_FLAT)."""
+    six launches per step over every instance (TFSPH_BATCH_FLAT)."""
 
     def __init__(self, probs, precision: int = TFSPH_F32, device="cuda", block: int = 0, stream=None,
                  form: int = TFSPH_BATCH_PERSISTENT):
