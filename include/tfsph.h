@@ -244,15 +244,17 @@ tfsph_status tfsph_step_graph(tfsph_ctx *ctx, tfsph_state *s, int32_t n_steps, i
 
 /* ---------------------------------------------------------------------------
  * Batched form: many independent problems (instances) with their own
- * parameters, advanced together by ONE persistent kernel launch per call.
- * The packed state holds every instance's particles back to back: instance i
+ * parameters, advanced together, either by one persistent kernel launch per
+ * call or by six launches per step over every instance (the form is chosen
+ * with tfsph_batch_tuning, below).  The packed state holds every instance's particles back to back: instance i
  * owns gas particles [gas_offset[i], gas_offset[i+1]) and dust particles
  * [dust_offset[i], dust_offset[i+1]) of the packed arrays; its cell indices
  * are local to its own grid.  Each instance's offsets must already be in
  * [0, Delta_i) (tfsph_positions_to_cells with that instance's params).
- * One workgroup advances one instance for all n_steps (block barriers only,
- * no inter-workgroup waiting); instances start largest first.  Every
- * instance evolves bitwise as it would alone through tfsph_step.
+ * In the persistent form one workgroup advances one instance for all n_steps
+ * (block barriers only, no inter-workgroup waiting); instances start largest
+ * first.  In either form every instance evolves bitwise as it would alone
+ * through tfsph_step.
  * ------------------------------------------------------------------------- */
 typedef struct tfsph_batch tfsph_batch;
 
