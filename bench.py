@@ -10,7 +10,9 @@ kinds in turn, inside the timed steps; the pair kernels are bound by vector
 ALU work, priced in algorithmic flops against the FP32 vector peak, the update
 kernel by HBM bytes); the whole step's algorithmic HBM bytes against the HBM
 peak; and the FP64 CPU oracle timed on the host cores on a bounded sample of
-the same workload.
+the same workload.  Extras (skipped with --no-extras): the adjoint / forward
+time ratio, the batched 1D waves, the second-order IMEX step, and the paper's
+three drag schemes (IDIC, ISPH, MK) side by side on the same workload.
 """
 from __future__ import annotations
 
@@ -43,34 +45,43 @@ FLOPS_PER_DENSITY_PAIR = 13   # q = sqrt(r^2)/h (2), f(q) (9), m f accumulated (
 FLOPS_PER_FORCE_PAIR = 28     # r^2 (8), r and 1/r (2), q (1), f'(q) (7), m (P_a+P_b) f'/r (4), 3 fma (6)
 
 
-def window_candidates(prob) -> int:
-    """Sum over gas particles of the gas population of their neighbour-cell window (the
-    candidates a cell-list search must test), from the initial cell counts."""
+def _cell_counts(prob, x):
     p = prob.params
     d = p.dim
     nc = np.array(p.n_cells[:d])
     lo, hi = np.array(p.lo[:d]), np.array(p.hi[:d])
     delta = (hi - lo) / nc
-    win = np.ceil(2.0 * p.h / delta - 1e-12).astype(int)
-    cell = np.floor((np.mod(prob.gas.x - lo, hi - lo)) / delta).astype(np.int64)
+    cell = np.floor((np.mod(x - lo, hi - lo)) / delta).astype(np.int64)
     cell = np.minimum(cell, nc - 1)
     counts = np.zeros(tuple(nc), dtype=np.int64)
     np.add.at(counts, tuple(cell.T), 1)
-    wsum = np.zeros_like(counts)
+    return counts, np.ceil(2.0 * p.h / delta - 1e-12).astype(int)
+
+
+def window_candidates(prob, phase: str = "gas", other: str = "gas") -> int:
+    """Sum over the particles of ``phase`` of the population of ``other`` in their
+    neighbour-cell window (the candidates a cell-list search must test), from the initial
+    cell counts."""
     import itertools
+    d = prob.params.dim
+    counts, win = _cell_counts(prob, getattr(prob, phase).x)
+    others = counts if other == phase else _cell_counts(prob, getattr(prob, other).x)[0]
+    wsum = np.zeros_like(others)
     for off in itertools.product(*[range(-w, w + 1) for w in win]):
-        wsum += np.roll(counts, shift=tuple(-o for o in off), axis=tuple(range(d)))
+        wsum += np.roll(others, shift=tuple(-o for o in off), axis=tuple(range(d)))
     return int((counts * wsum).sum())
 
 
-def support_pairs(prob) -> int:
-    """Sum over gas particles of the gas particles within 2h (self included), periodic."""
+def support_pairs(prob, phase: str = "gas", other: str = "gas") -> int:
+    """Sum over the particles of ``phase`` of the particles of ``other`` within 2h (a particle
+    counts itself when both are the same phase), periodic."""
     from scipy.spatial import cKDTree
     p = prob.params
     d = p.dim
     lo, hi = np.array(p.lo[:d]), np.array(p.hi[:d])
-    x = np.mod(prob.gas.x - lo, hi - lo)
-    tree = cKDTree(x, boxsize=hi - lo)
+    x = np.mod(getattr(prob, phase).x - lo, hi - lo)
+    y = x if other == phase else np.mod(getattr(prob, other).x - lo, hi - lo)
+    tree = cKDTree(y, boxsize=hi - lo)
     n = tree.query_ball_point(x, r=2.0 * p.h * (1.0 - 1e-12), return_length=True, workers=-1)
     return int(np.sum(n))
 
@@ -188,6 +199,90 @@ def adjoint_ratio(I, T, torch, steps=200, ckpt=20):
             "workspace_MiB": runner.ws_bytes / 2 ** 20}
 
 
+# per gas-dust pair within 2h of the comparison schemes' pair kernels (Sections 2.1-2.2)
+FLOPS_MK_PAIR = 33            # q (2), W(q) (9), (v_a - u_j).r (8), m K / (rho_a rho_j) (v.r) / (r^2 + eta^2) W (8), 3 fma (6)
+FLOPS_ISPH_GAS_PAIR = 20      # q (2), W(q) (9), m W and m W / rho (2), density sum (1), velocity sums (6)
+FLOPS_ISPH_DUST_PAIR = 47     # r, q (2), m W, m W / rho, density sum (12), pressure sum (4), velocity sums (6),
+#                               1/r and m W'(q) / r (10), the two gradient sums (13)
+SCHEME_T_STOP = 0.05          # about 25 steps of the 3D box: the explicit MK drag is stable there
+
+
+def drag_schemes(prob, I, T, torch, steps=100, warmup=50, cpu_steps=0, counts=None):
+    """The paper's three drag schemes on the same workload with t_stop = SCHEME_T_STOP: IDIC, and
+    the comparison schemes MK (explicit pairwise drag, eqs. 8-10) and ISPH (interpolated
+    two-velocity solve, eqs. 11-16), whose step replaces the cell solve by one thread per gas
+    particle (pressure terms plus the dust window) and one per dust particle (the gas window).
+    Per scheme: whole-step time, per-kind launch times, the pair kernels priced in algorithmic
+    flops against the FP32 vector peak, and (cpu_steps > 0) the oracle on the host cores."""
+    counts = dict(counts or {})
+    if "cross_candidates" not in counts:
+        counts["cross_candidates"] = window_candidates(prob, "gas", "dust")
+        counts["cross_pairs"] = support_pairs(prob, "gas", "dust")
+    if "gas_pairs" not in counts:
+        counts["gas_pairs"] = support_pairs(prob)
+    cand, cross = counts["cross_candidates"], counts["cross_pairs"]
+    press = FLOPS_PER_FORCE_PAIR * (counts["gas_pairs"] - prob.gas.n)
+    work = {
+        "MK": {"k_pair_gas": press + FLOPS_PER_CANDIDATE * cand + FLOPS_MK_PAIR * cross,
+               "k_pair_dust": FLOPS_PER_CANDIDATE * cand + FLOPS_MK_PAIR * cross},
+        "ISPH": {"k_pair_gas": press + FLOPS_PER_CANDIDATE * cand + FLOPS_ISPH_GAS_PAIR * cross,
+                 "k_pair_dust": FLOPS_PER_CANDIDATE * cand + FLOPS_ISPH_DUST_PAIR * cross},
+    }
+    kinds = (T.TFSPH_KERNEL_BIN, T.TFSPH_KERNEL_DENSITY, T.TFSPH_KERNEL_FORCE, T.TFSPH_KERNEL_UPDATE)
+    n_part = prob.gas.n + prob.dust.n
+    out = {"t_stop": SCHEME_T_STOP, "steps": steps, "warmup": warmup, **counts}
+    for name, scheme in (("IDIC", T.TFSPH_SCHEME_IDIC), ("ISPH", T.TFSPH_SCHEME_ISPH), ("MK", T.TFSPH_SCHEME_MK)):
+        q = prob.copy()
+        q.params = q.params.replace(t_stop=SCHEME_T_STOP, scheme=scheme)
+        sim = T.Simulation(q, precision=T.TFSPH_F32)
+        sim.step(warmup)
+        T.tfsph_profile(sim.ctx, True, rotate=steps >= 4, every=max(1, steps // 48))
+        torch.cuda.synchronize()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        T.tfsph_profile(sim.ctx, False)
+        names = (("binning", "k_density", "k_gas_predict", "k_update") if name == "IDIC" else
+                 ("binning", "k_density_gas_and_dust", "k_pair_gas", "k_pair_dust"))
+        kms = {}
+        for k, kind in zip(names, kinds):
+            ms, n = T.tfsph_profile_read(sim.ctx, kind)
+            kms[k] = ms / n if n else 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        flags, _ = sim.flags()
+        sim.close()
+        rec = {"ms_per_step": 1e3 * wall / steps, "value": n_part * steps / wall, "unit": "particle-steps/s",
+               "kernel_ms_per_step": kms, "nonfinite": bool(flags & T.TFSPH_FLAG_NONFINITE)}
+        if name in work:
+            per = {}
+            for k, flops in work[name].items():
+                t = kms[k] * 1e-3
+                ach = flops / t / 1e12 if t > 0 else 0.0
+                per[k] = {"bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": ach / FP32_PEAK_TFLOPS, "avg_launch_ms": kms[k],
+                          "algorithmic_flops_per_launch": flops}
+            rec["roofline"] = per[max(per, key=lambda k: kms[k])] | {"kernel": max(per, key=lambda k: kms[k])}
+            rec["kernels"] = per
+        if cpu_steps > 0:
+            from oracle import oracle as O
+            O.build()
+            g, d = O.from_problem(q)
+            t0 = time.perf_counter()
+            O.step(q.params, g, d, cpu_steps)
+            dt = time.perf_counter() - t0
+            rec["cpu_baseline"] = {"value": n_part * cpu_steps / dt, "unit": "particle-steps/s",
+                                   "cores": O.num_threads(), "kind": "oracle",
+                                   "sample": f"{cpu_steps} steps of the same workload, FP64, {dt:.2f} s wall"}
+        out[name] = rec
+    base = out["IDIC"]["ms_per_step"]
+    for name in ("ISPH", "MK"):
+        out[name]["time_vs_idic"] = out[name]["ms_per_step"] / base
+    return out
+
+
 def batched_throughput(I, T, torch, steps=500, plain_steps=20):
     """256 uneven 1D dusty waves advanced together (form and workgroup size autotuned among the
     persistent kernel and the flattened launches, hipGraph replay), against the same instances
@@ -274,12 +369,15 @@ def main(argv=None):
     ap.add_argument("--workload", default="box3d", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint, batched and IMEX measurements")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint, batched, IMEX and drag-scheme measurements")
     ap.add_argument("--scheme", default="idic", choices=("idic", "imex"),
                     help="time step timed: the paper's first-order step (default) or the second-order IMEX step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times (reference for HBM byte counters)")
-    ap.add_argument("--only", choices=("adjoint", "batched"),
+    ap.add_argument("--scheme-cpu-steps", type=int, default=1,
+                    help="oracle steps timed per drag scheme in the scheme comparison")
+    ap.add_argument("--only", choices=("adjoint", "batched", "schemes"),
                     help="run only that extra measurement and print its record as the JSON line "
                          "(for profiling it on its own; not the benchmark line)")
     a = ap.parse_args(argv)
@@ -295,9 +393,12 @@ def main(argv=None):
     from paper_1908_01682_amd import tfsph as T
 
     if a.only:
-        run = adjoint_ratio if a.only == "adjoint" else batched_throughput
         print(f"[bench] {a.only} only", file=sys.stderr, flush=True)
-        print(json.dumps({"only": a.only, **run(I, T, torch)}), flush=True)
+        if a.only == "schemes":
+            rec = drag_schemes(I.workload(a.workload), I, T, torch, cpu_steps=0)
+        else:
+            rec = (adjoint_ratio if a.only == "adjoint" else batched_throughput)(I, T, torch)
+        print(json.dumps({"only": a.only, **rec}), flush=True)
         return 0
 
     if a.copy_calibration:
@@ -415,6 +516,9 @@ def main(argv=None):
             imex = imex_throughput(prob, T, torch)
             imex["cost_vs_first_order"] = imex["ms_per_step"] / result["uninstrumented"]["ms_per_step"]
             result["imex"] = imex
+            print(f"[bench] the three drag schemes at t_stop {SCHEME_T_STOP}", file=sys.stderr, flush=True)
+            result["drag_schemes"] = drag_schemes(prob, I, T, torch, counts={"gas_pairs": pairs},
+                                                  cpu_steps=0 if a.no_cpu_baseline else a.scheme_cpu_steps)
     if not a.no_cpu_baseline:
         print(f"[bench] oracle on host cores, {a.cpu_steps} steps", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(prob, a.cpu_steps)

@@ -54,6 +54,34 @@ def test_support_pairs_brute_force(make):
     assert bench.support_pairs(prob) == int((dist < 2.0 * p.h * (1.0 - 1e-12)).sum())
 
 
+@pytest.mark.parametrize("make", [
+    lambda: I.dusty_box(n_side=10, cells_per_axis=5, regions_per_axis=1),
+    lambda: I.wave_2d(n_side=24, amp=1e-2),
+    lambda: I.dusty_shock(n=400),
+])
+def test_cross_phase_counts_brute_force(make):
+    """Gas-dust candidates and pairs (the comparison schemes' pair kernels): every gas particle
+    against every dust particle, in both directions."""
+    prob = make()
+    p = prob.params
+    d = p.dim
+    lo, hi = np.array(p.lo[:d]), np.array(p.hi[:d])
+    L = hi - lo
+    nc = np.array(p.n_cells[:d])
+    delta = L / nc
+    win = np.ceil(2.0 * p.h / delta - 1e-12).astype(int)
+    cell = lambda x: np.minimum(np.floor(np.mod(x - lo, L) / delta).astype(int), nc - 1)
+    cg, cd = cell(prob.gas.x), cell(prob.dust.x)
+    off = (cd[None, :, :] - cg[:, None, :]) % nc
+    off = np.where(off > nc // 2, off - nc, off)
+    cand = int(np.all(np.abs(off) <= win, axis=-1).sum())
+    r = prob.gas.x[:, None, :] - prob.dust.x[None, :, :]
+    r -= L * np.round(r / L)
+    pairs = int((np.sqrt((r ** 2).sum(-1)) < 2.0 * p.h * (1.0 - 1e-12)).sum())
+    assert bench.window_candidates(prob, "gas", "dust") == cand == bench.window_candidates(prob, "dust", "gas")
+    assert bench.support_pairs(prob, "gas", "dust") == pairs == bench.support_pairs(prob, "dust", "gas")
+
+
 def test_step_bytes_counts_state_keys_density_and_cells():
     prob = I.dusty_box(n_side=8, cells_per_axis=4, regions_per_axis=1)
     g, s = prob.gas, prob.dust

@@ -101,6 +101,19 @@ def test_five_step_parity(orc, name, make, precision, scheme):
     assert one == lonely
 
 
+@pytest.mark.parametrize("scheme", [MK, ISPH], ids=["MK", "ISPH"])
+def test_full_size_box_one_step(orc, scheme):
+    """The 3D box at its full size (128^3 + 128^3 particles, 64^3 cells) with t_stop = 0.05, the
+    configuration the benchmark compares the three schemes on: one step, the whole state
+    against the oracle."""
+    prob = I.dusty_box()
+    prob.params = prob.params.replace(t_stop=0.05)
+    err, flags, one, lonely = _parity(orc, prob, 0, scheme, 1)
+    assert all(v <= TOL32 for v in err.values()), err
+    assert not flags & T.TFSPH_FLAG_NONFINITE
+    assert one == lonely
+
+
 def test_isph_counts_particles_without_partners(orc):
     """Dust on the left half only: gas particles beyond 2h of any dust get no drag; the GPU
     counts them as the oracle does."""
