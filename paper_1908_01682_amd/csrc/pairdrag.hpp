@@ -22,7 +22,10 @@
 // All sums are gathers over the other phase's window in the sorted
 // workspace (no atomics), so results are bitwise reproducible.  One thread
 // per particle; each writes its particle's new state to the caller's arrays
-// at its sorted index, as k_update does.
+// at its sorted index, as k_update does.  The other phase has no neighbour
+// masks from a density pass, so for_support() finds each point's partners
+// row pair by row pair from positions alone before the pair terms (with their
+// gathers of density and velocity) are evaluated for those only.
 #pragma once
 
 #include "sph.hpp"
@@ -30,6 +33,57 @@
 namespace tfsph {
 
 enum { kPairMK = 0, kPairISPH = 1 };
+
+// Visit the particles of another phase inside the support of a point, in the
+// order of for_window(), with the same fn(b, q, rx, ry, rz, valid): each pair
+// of rows of the window is first scanned for candidates with r^2 below
+// (kMaskQ h)^2, a little beyond the support q < 2, and only those are handed
+// to fn (walk_bits()); a pair of rows with more than kMaskBits candidates is
+// handed over whole.  Every pair term vanishes exactly for q >= 2 (W = W' =
+// 0), so the sums are those of for_window().  Windows wider than 2 cells
+// along x use for_window().
+template <typename R, int DIM, typename Fn>
+__device__ __forceinline__ void for_support(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
+                                            const int *__restrict__ start, const R4<R> *__restrict__ data, Fn &&fn)
+{
+    const R cut = R(kMaskQ) * G.h;
+    const R cut2 = cut * cut;
+    auto inside = [&](int, const R4<R> &, R rx, R ry, R rz, bool ok) {
+        return ok && rx * rx + ry * ry + rz * rz < cut2;
+    };
+    const bool rows = with_row_width(G.win[0], [&](auto W) {
+        constexpr int WX = decltype(W)::value;
+        constexpr int NC = 2 * WX + 1;
+        R rx0[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) rx0[k] = oa[0] - R(k - WX) * G.delta[0];
+        const bool wave_rows_contiguous = __ballot(cx < WX || cx + WX >= G.nc[0]) == 0ull;
+        for_window_pairs<R, DIM, WX>(G, cx, cy, cz, oa, start, [&](int, auto &bs, auto &be, const R *ry0,
+                                                                   const R *rz0) {
+            int P[2 * NC], shift[2 * NC];
+            if (pair_segments<NC>(bs, be, P, shift) > kMaskBits) {
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int k = 0; k < NC; ++k)
+                        visit_range<R, DIM>(bs[t][k], be[t][k], data, rx0[k], ry0[t], rz0[t], fn);
+                return;
+            }
+            unsigned long long m = 0;
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int k = 0; k < NC; ++k)
+                    m |= visit_range_bits<R, DIM>(bs[t][k], be[t][k], data, rx0[k], ry0[t], rz0[t],
+                                                  t ? P[NC + k] : P[k], inside);
+            if (wave_rows_contiguous)
+                walk_bits<R, DIM, NC, true, R>(m, P, shift, rx0, ry0, rz0, data, fn);
+            else
+                walk_bits<R, DIM, NC, false, R>(m, P, shift, rx0, ry0, rz0, data, fn);
+        });
+    });
+    if (!rows) for_window<R, DIM>(G, cx, cy, cz, oa, start, data, fn);
+}
 
 // K / (rho_g rho_d) and K of eq. (7) at a point or a pair, by drag law
 template <typename R>
@@ -90,7 +144,7 @@ k_pair_gas(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Flags
         if constexpr (SCHEME == kPairMK) {
             const R eta2 = R(0.001) * G.h * G.h;
             R dx = R(0), dy = R(0), dz = R(0);
-            for_window<R, DIM>(G, cx, cy, cz, oa, Sd.start, Sd.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
+            for_support<R, DIM>(G, cx, cy, cz, oa, Sd.start, Sd.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
                 if (!ok) return;
                 const R r2 = rx * rx + ry * ry + rz * rz;
                 const R w = spline_f(fsqrt(r2) * G.inv_h);
@@ -108,7 +162,7 @@ k_pair_gas(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Flags
             for (int d = 0; d < DIM; ++d) vn[d] = va[d] + Ph.tau * (acc[d] + Ph.g[d] + dr[d]);
         } else {
             R rd = R(0), ux = R(0), uy = R(0), uz = R(0);
-            for_window<R, DIM>(G, cx, cy, cz, oa, Sd.start, Sd.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
+            for_support<R, DIM>(G, cx, cy, cz, oa, Sd.start, Sd.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
                 if (!ok) return;
                 const R r2 = rx * rx + ry * ry + rz * rz;
                 const R mw = q.w * spline_f(fsqrt(r2) * G.inv_h);
@@ -172,7 +226,7 @@ k_pair_dust(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pd, Flag
         if constexpr (SCHEME == kPairMK) {
             const R eta2 = R(0.001) * G.h * G.h;
             R dx = R(0), dy = R(0), dz = R(0);
-            for_window<R, DIM>(G, cx, cy, cz, oj, Sg.start, Sg.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
+            for_support<R, DIM>(G, cx, cy, cz, oj, Sg.start, Sg.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
                 if (!ok) return;
                 const R r2 = rx * rx + ry * ry + rz * rz;
                 const R w = spline_f(fsqrt(r2) * G.inv_h);
@@ -191,7 +245,7 @@ k_pair_dust(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pd, Flag
         } else {
             R rg = R(0), pj = R(0), vx = R(0), vy = R(0), vz = R(0);
             R gp[3] = {R(0), R(0), R(0)}, g1[3] = {R(0), R(0), R(0)};
-            for_window<R, DIM>(G, cx, cy, cz, oj, Sg.start, Sg.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
+            for_support<R, DIM>(G, cx, cy, cz, oj, Sg.start, Sg.frc, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
                 if (!ok) return;
                 const R r2 = rx * rx + ry * ry + rz * rz;
                 const R r = fsqrt(r2);

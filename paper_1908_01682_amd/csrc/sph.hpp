@@ -280,15 +280,67 @@ __device__ __forceinline__ bool pop_bit(unsigned long long &m, int &p)
     return ok;
 }
 
+// Visit the candidates of one pair of rows whose bits are set in m (bit p =
+// the p-th candidate in walking order; segments P, shift as pair_segments(),
+// rx0[k] the x part of x_a - x_b for cell k of a row before the candidate's
+// own offset, ry0 / rz0 per row as for_window_pairs()); fn(b, q, rx, ry, rz,
+// valid) as for for_window().  Candidates are taken kWalk at a time; a lane
+// with fewer left repeats its last one with valid = false.  A set bit p is
+// decoded by the segment (row t, cell k) it falls in: the row is the second
+// one when p >= P[NC], the cell the last one of that row whose segment starts
+// at or before p.  With RowRuns (no lane's window wraps around the box along
+// x) the cells of every row are consecutive in the sorted order, so one index
+// shift serves the whole row.
+template <typename R, int DIM, int NC, bool RowRuns, typename T, typename Fn>
+__device__ __forceinline__ void walk_bits(unsigned long long m, const int (&P)[2 * NC], const int (&shift)[2 * NC],
+                                          const T (&rx0)[NC], const T *ry0, const T *rz0,
+                                          const R4<R> *__restrict__ data, Fn &fn)
+{
+    int p = 0;
+    while (m) {
+        int b[kWalk];
+        T x0[kWalk], y0[kWalk], z0[kWalk];
+        bool ok[kWalk];
+#pragma unroll
+        for (int j = 0; j < kWalk; ++j) {
+            ok[j] = pop_bit(m, p);
+            const bool t1 = p >= P[NC];
+            const int sh0 = shift[0], sh1 = shift[NC];
+            int sh = t1 ? sh1 : sh0;
+            T xx = rx0[0];
+#pragma unroll
+            for (int k = 1; k < NC; ++k) {
+                const int p0 = P[k], p1 = P[NC + k];
+                const bool ge = p >= (t1 ? p1 : p0);
+                if constexpr (!RowRuns) {
+                    const int s0 = shift[k], s1 = shift[NC + k];
+                    sh = ge ? (t1 ? s1 : s0) : sh;
+                }
+                const T x = rx0[k];
+                xx = ge ? x : xx;
+            }
+            b[j] = p + sh;
+            x0[j] = xx;
+            y0[j] = DIM > 1 ? (t1 ? ry0[1] : ry0[0]) : ry0[0];
+            z0[j] = DIM > 2 ? (t1 ? rz0[1] : rz0[0]) : rz0[0];
+        }
+        R4<R> q[kWalk];
+#pragma unroll
+        for (int j = 0; j < kWalk; ++j) q[j] = data[b[j]];
+#pragma unroll
+        for (int j = 0; j < kWalk; ++j) {
+            const T rx = x0[j] - T(q[j].x);
+            const T ry = DIM > 1 ? y0[j] - T(q[j].y) : T(0);
+            const T rz = DIM > 2 ? z0[j] - T(q[j].z) : T(0);
+            fn(b[j], q[j], rx, ry, rz, ok[j]);
+        }
+    }
+}
+
 // Visit the neighbours of a point recorded in mask[i * stride] (pairs of at
 // most kMaskBits candidates) or, for longer pairs, every candidate of the
-// pair; fn(b, q, rx, ry, rz, valid) as for for_window().  Neighbours are taken
-// kWalk at a time; a lane with fewer left repeats its last one with valid =
-// false.  A set bit p is decoded by the segment (row t, cell k) it falls in:
-// the row is the second one when p >= P[NC], the cell the last one of that
-// row whose segment starts at or before p.  When no lane's window wraps around
-// the box along x, the cells of every row are consecutive in the sorted
-// order, so one index shift serves the whole row.
+// pair; fn(b, q, rx, ry, rz, valid) as for for_window(), neighbours walked by
+// walk_bits().
 template <typename R, int DIM, typename T = R, typename Fn>
 __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy, int cz, const R oa[3],
                                                const int *__restrict__ start, const R4<R> *__restrict__ data,
@@ -313,47 +365,10 @@ __device__ __forceinline__ void for_neighbours(const Geom<R> &G, int cx, int cy,
                 return;
             }
             const unsigned long long m0 = mask[size_t(i) * stride];
-            auto walk = [&](auto RowRuns) {
-                constexpr bool kRowRuns = decltype(RowRuns)::value != 0;
-                unsigned long long m = m0;
-                int p = 0;
-                while (m) {
-                    int b[kWalk];
-                    T x0[kWalk], y0[kWalk], z0[kWalk];
-                    bool ok[kWalk];
-#pragma unroll
-                    for (int j = 0; j < kWalk; ++j) {
-                        ok[j] = pop_bit(m, p);
-                        const bool t1 = p >= P[NC];
-                        int sh = t1 ? shift[NC] : shift[0];
-                        T xx = rx0[0];
-#pragma unroll
-                        for (int k = 1; k < NC; ++k) {
-                            const bool ge = p >= (t1 ? P[NC + k] : P[k]);
-                            if constexpr (!kRowRuns) sh = ge ? (t1 ? shift[NC + k] : shift[k]) : sh;
-                            xx = ge ? rx0[k] : xx;
-                        }
-                        b[j] = p + sh;
-                        x0[j] = xx;
-                        y0[j] = DIM > 1 ? (t1 ? ry0[1] : ry0[0]) : ry0[0];
-                        z0[j] = DIM > 2 ? (t1 ? rz0[1] : rz0[0]) : rz0[0];
-                    }
-                    R4<R> q[kWalk];
-#pragma unroll
-                    for (int j = 0; j < kWalk; ++j) q[j] = data[b[j]];
-#pragma unroll
-                    for (int j = 0; j < kWalk; ++j) {
-                        const T rx = x0[j] - T(q[j].x);
-                        const T ry = DIM > 1 ? y0[j] - T(q[j].y) : T(0);
-                        const T rz = DIM > 2 ? z0[j] - T(q[j].z) : T(0);
-                        fn(b[j], q[j], rx, ry, rz, ok[j]);
-                    }
-                }
-            };
             if (wave_rows_contiguous)
-                walk(IntC<1>{});
+                walk_bits<R, DIM, NC, true, T>(m0, P, shift, rx0, ry0, rz0, data, fn);
             else
-                walk(IntC<0>{});
+                walk_bits<R, DIM, NC, false, T>(m0, P, shift, rx0, ry0, rz0, data, fn);
         });
     });
 }
