@@ -24,8 +24,9 @@
 // per particle; each writes its particle's new state to the caller's arrays
 // at its sorted index, as k_update does.  The other phase has no neighbour
 // masks from a density pass, so for_support() finds each point's partners
-// row pair by row pair from positions alone before the pair terms (with their
-// gathers of density and velocity) are evaluated for those only.
+// row pair by row pair from positions alone before the pair terms are
+// evaluated for those only, each reading its partner's velocity and density
+// from one packed record (k_pack_vel_rho).
 #pragma once
 
 #include "sph.hpp"
@@ -33,6 +34,23 @@
 namespace tfsph {
 
 enum { kPairMK = 0, kPairISPH = 1 };
+
+// Each phase's velocity and summation density packed per sorted particle,
+// (vx, vy, vz, rho), so that a partner costs one 16-byte load instead of four
+// scattered ones; written after the density pass of the phase.
+template <typename R>
+struct VelRho {
+    R4<R> *gas;
+    R4<R> *dust;
+};
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__(kBlock) k_pack_vel_rho(Sorted<R> S, R4<R> *vr)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= S.n) return;
+    vr[i] = mk4<R>(S.vel[0][i], DIM > 1 ? S.vel[1][i] : R(0), DIM > 2 ? S.vel[2][i] : R(0), S.rho[i]);
+}
 
 // Visit the particles of another phase inside the support of a point, in the
 // order of for_window(), with the same fn(b, q, rx, ry, rz, valid): each pair
@@ -122,35 +140,38 @@ __device__ __forceinline__ bool store_moved(const Geom<R> &G, const Phys<R> &Ph,
     return ok;
 }
 
-// One gas particle of MK or ISPH: pressure terms (masks of the density pass
-// when present), the drag from the dust window, update, move.
-template <typename R, int DIM, int KIND, int SCHEME>
+// One gas particle of MK or ISPH after the explicit gas pass of the IDIC
+// step (k_gas_predict: the predictor v~ = v + tau (A + g) in Sg.vt, the new
+// energy in the caller's array): the drag from the dust window, update, move.
+template <typename R, int DIM, int SCHEME>
 __global__ void __launch_bounds__(kBlock)
-k_pair_gas(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Flags F)
+k_pair_gas(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, const R4<R> *__restrict__ vrd, Phase<R> Pg,
+           Flags F)
 {
     const int a = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     R s2 = signal_floor(Ph);
     int bad = 0, lonely = 0;
     if (a < Sg.n) {
-        R acc[3], dedt;
-        gas_force_at<R, DIM, KIND>(G, Ph, Sg, a, acc, dedt);
+        const R vt[3] = {Sg.vt[0][a], DIM > 1 ? Sg.vt[1][a] : R(0), DIM > 2 ? Sg.vt[2][a] : R(0)};
         int cx, cy, cz;
         split_cell(G, Sg.cell[a], cx, cy, cz);
         const R4<R> me = Sg.pos[a];
         const R oa[3] = {me.x, me.y, me.z};
-        const R va[3] = {Sg.vel[0][a], DIM > 1 ? Sg.vel[1][a] : R(0), DIM > 2 ? Sg.vel[2][a] : R(0)};
         const R rho_a = Sg.rho[a];
         R vn[3];
         if constexpr (SCHEME == kPairMK) {
+            // the drag of eq. (8) takes the velocities of level n
+            const R va[3] = {Sg.vel[0][a], DIM > 1 ? Sg.vel[1][a] : R(0), DIM > 2 ? Sg.vel[2][a] : R(0)};
             const R eta2 = R(0.001) * G.h * G.h;
             R dx = R(0), dy = R(0), dz = R(0);
             for_support<R, DIM>(G, cx, cy, cz, oa, Sd.start, Sd.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
                 if (!ok) return;
                 const R r2 = rx * rx + ry * ry + rz * rz;
                 const R w = spline_f(fsqrt(r2) * G.inv_h);
-                const R rho_b = Sd.rho[b];
-                const R vr = (va[0] - Sd.vel[0][b]) * rx + (DIM > 1 ? (va[1] - Sd.vel[1][b]) * ry : R(0)) +
-                             (DIM > 2 ? (va[2] - Sd.vel[2][b]) * rz : R(0));
+                const R4<R> ub = vrd[b];
+                const R rho_b = ub.w;
+                const R vr = (va[0] - ub.x) * rx + (DIM > 1 ? (va[1] - ub.y) * ry : R(0)) +
+                             (DIM > 2 ? (va[2] - ub.z) * rz : R(0));
                 const R X = q.w * drag_coef(Ph, rho_a, rho_b) / (rho_a * rho_b) * vr / (r2 + eta2) * w;
                 dx -= X * rx;
                 dy -= X * ry;
@@ -159,18 +180,19 @@ k_pair_gas(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Flags
             const R sw = R(DIM) * G.wnorm;
             const R dr[3] = {dx * sw, dy * sw, dz * sw};
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) vn[d] = va[d] + Ph.tau * (acc[d] + Ph.g[d] + dr[d]);
+            for (int d = 0; d < DIM; ++d) vn[d] = vt[d] + Ph.tau * dr[d];
         } else {
             R rd = R(0), ux = R(0), uy = R(0), uz = R(0);
             for_support<R, DIM>(G, cx, cy, cz, oa, Sd.start, Sd.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
                 if (!ok) return;
                 const R r2 = rx * rx + ry * ry + rz * rz;
                 const R mw = q.w * spline_f(fsqrt(r2) * G.inv_h);
-                const R f = mw / Sd.rho[b];
+                const R4<R> ub = vrd[b];
+                const R f = mw / ub.w;
                 rd += mw;
-                ux += f * Sd.vel[0][b];
-                if (DIM > 1) uy += f * Sd.vel[1][b];
-                if (DIM > 2) uz += f * Sd.vel[2][b];
+                ux += f * ub.x;
+                if (DIM > 1) uy += f * ub.y;
+                if (DIM > 2) uz += f * ub.z;
             });
             rd *= G.wnorm;
             const R ua[3] = {ux * G.wnorm, uy * G.wnorm, uz * G.wnorm};
@@ -185,16 +207,11 @@ k_pair_gas(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Flags
             const R D = R(1) + alpha + beta;
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
-                const R vt = va[d] + Ph.tau * (acc[d] + Ph.g[d]);
                 const R ut = (rd > R(0) ? ua[d] : R(0)) + Ph.tau * Ph.g[d];
-                vn[d] = ((R(1) + beta) * vt + alpha * ut) / D;
+                vn[d] = ((R(1) + beta) * vt[d] + alpha * ut) / D;
             }
         }
-        if (Sg.energy) {
-            const R e = Sg.energy[a] + Ph.tau * dedt;
-            Pg.energy[a] = e;
-            if (Ph.eos != 0) s2 = fmax(s2, Ph.ggm1 * e);
-        }
+        if (Sg.energy && Ph.eos != 0) s2 = fmax(s2, Ph.ggm1 * Pg.energy[a]);
         bad = !store_moved<R, DIM>(G, Ph, Sg, Pg, a, vn, s2);
     }
     publish_speed(Ph, F, s2);
@@ -210,7 +227,8 @@ k_pair_gas(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pg, Flags
 // records read are frc = (ox, oy, oz, P = p / rho^2) of the density pass.
 template <typename R, int DIM, int SCHEME>
 __global__ void __launch_bounds__(kBlock)
-k_pair_dust(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pd, Flags F)
+k_pair_dust(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, const R4<R> *__restrict__ vrg, Phase<R> Pd,
+            Flags F)
 {
     const int j = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     R s2 = signal_floor(Ph);
@@ -230,9 +248,10 @@ k_pair_dust(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pd, Flag
                 if (!ok) return;
                 const R r2 = rx * rx + ry * ry + rz * rz;
                 const R w = spline_f(fsqrt(r2) * G.inv_h);
-                const R rho_b = Sg.rho[b];
-                const R vr = (Sg.vel[0][b] - uj[0]) * rx + (DIM > 1 ? (Sg.vel[1][b] - uj[1]) * ry : R(0)) +
-                             (DIM > 2 ? (Sg.vel[2][b] - uj[2]) * rz : R(0));
+                const R4<R> vb = vrg[b];
+                const R rho_b = vb.w;
+                const R vr = (vb.x - uj[0]) * rx + (DIM > 1 ? (vb.y - uj[1]) * ry : R(0)) +
+                             (DIM > 2 ? (vb.z - uj[2]) * rz : R(0));
                 const R X = q.w * drag_coef(Ph, rho_b, rho_j) / (rho_b * rho_j) * vr / (r2 + eta2) * w;
                 dx += X * rx;
                 dy += X * ry;
@@ -251,14 +270,15 @@ k_pair_dust(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Phase<R> Pd, Flag
                 const R r = fsqrt(r2);
                 const R qq = r * G.inv_h;
                 const R m = Sg.pos[b].w;
-                const R rho_b = Sg.rho[b];
+                const R4<R> vb = vrg[b];
+                const R rho_b = vb.w;
                 const R mw = m * spline_f(qq);
                 const R f = mw / rho_b;
                 rg += mw;
                 pj += f * (q.w * rho_b * rho_b);            // p_b / rho_b W m_b
-                vx += f * Sg.vel[0][b];
-                if (DIM > 1) vy += f * Sg.vel[1][b];
-                if (DIM > 2) vz += f * Sg.vel[2][b];
+                vx += f * vb.x;
+                if (DIM > 1) vy += f * vb.y;
+                if (DIM > 2) vz += f * vb.z;
                 const R ir = r2 > R(0) ? frcp(r) : R(0);
                 const R md = m * spline_df(qq) * ir;           // m_b grad_j W / (gnorm r_vec)
                 const R rr[3] = {rx, ry, rz};

@@ -189,6 +189,10 @@ size_t plan_bytes(const tfsph_params *p, int ng, int nd, PhaseFlags fg, PhaseFla
         ImexViews<R> V;
         carve_imex<R>(cv, p, ng, nd, fg, fd, 0.0, 0.0, V);
     }
+    if (p->scheme == TFSPH_SCHEME_MK || p->scheme == TFSPH_SCHEME_ISPH) {
+        cv.take<R4<R>>(size_t(ng) + kPad);
+        cv.take<R4<R>>(size_t(nd) + kPad);
+    }
     return cv.off + 256;
 }
 
@@ -275,7 +279,7 @@ namespace {
 
 template <typename R>
 void carve_all(const tfsph_ctx *c, Sorted<R> &Sg, Sorted<R> &Sd, int *&partial, Flags &F,
-               ImexViews<R> *imex = nullptr)
+               ImexViews<R> *imex = nullptr, VelRho<R> *vr = nullptr)
 {
     Carver cv;
     cv.base = c->ws;
@@ -286,6 +290,10 @@ void carve_all(const tfsph_ctx *c, Sorted<R> &Sg, Sorted<R> &Sd, int *&partial, 
     F.word = cv.take<unsigned int>(64);
     F.one_phase = cv.take<unsigned long long>(8);
     if (imex) carve_imex<R>(cv, &c->p, c->ng, c->nd, c->fg, c->fd, c->mg_uniform, c->md_uniform, *imex);
+    if (vr) {
+        vr->gas = cv.take<R4<R>>(size_t(c->ng) + kPad);
+        vr->dust = cv.take<R4<R>>(size_t(c->nd) + kPad);
+    }
 }
 
 }  // namespace
@@ -499,7 +507,8 @@ __global__ void k_export_flags(const unsigned int *word, const unsigned long lon
 }
 
 // One step of the comparison schemes (MK or ISPH): binning, both summation
-// densities, then one thread per gas particle and one per dust particle.
+// densities, the explicit gas pass of the IDIC step, then one thread per gas
+// particle and one per dust particle for the drag and the update.
 template <typename R, int DIM, int SCHEME>
 tfsph_status enqueue_step_pair(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
 {
@@ -509,7 +518,8 @@ tfsph_status enqueue_step_pair(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
     Sorted<R> Sg, Sd;
     int *partial;
     Flags F;
-    carve_all<R>(c, Sg, Sd, partial, F);
+    VelRho<R> VR;
+    carve_all<R>(c, Sg, Sd, partial, F, nullptr, &VR);
     if (c->variant != TFSPH_VARIANT_AUTO) Sg.nmask = nullptr;
     MARK(TFSPH_KERNEL_BIN);
     tfsph_status r = enqueue_bin<R>(c->ng, c->nd, G, Pg, Pd, Sg, Sd, partial, F, st);
@@ -519,25 +529,29 @@ tfsph_status enqueue_step_pair(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
     if (c->ng > 0) {
         r = enqueue_density<R, DIM>(G, Ph, Sg, 1, st, c->variant);
         if (r != TFSPH_OK) return r;
+        hipLaunchKernelGGL((k_pack_vel_rho<R, DIM>), dim3(blocks_for(c->ng)), dim3(kBlock), 0, st, Sg, VR.gas);
+        LAUNCH_CHECK("pack_vel_rho");
     }
     if (c->nd > 0) {
         r = enqueue_density<R, DIM>(G, Ph, Sd, 0, st, 0);
         if (r != TFSPH_OK) return r;
+        hipLaunchKernelGGL((k_pack_vel_rho<R, DIM>), dim3(blocks_for(c->nd)), dim3(kBlock), 0, st, Sd, VR.dust);
+        LAUNCH_CHECK("pack_vel_rho");
     }
     MARK(TFSPH_KERNEL_DENSITY);
     MARK(TFSPH_KERNEL_FORCE);
-    if (c->ng > 0) {
-        launch_by_kind<R, DIM>(Ph, Sg, [&](auto K) {
-            hipLaunchKernelGGL((k_pair_gas<R, DIM, decltype(K)::value, SCHEME>), dim3(blocks_for(c->ng)), dim3(kBlock),
-                               0, st, G, Ph, Sg, Sd, Pg, F);
-        });
-        LAUNCH_CHECK("pair_gas");
-    }
+    r = enqueue_force<R, DIM>(G, Ph, Sg, Pg, st);
+    if (r != TFSPH_OK) return r;
     MARK(TFSPH_KERNEL_FORCE);
     MARK(TFSPH_KERNEL_UPDATE);
+    if (c->ng > 0) {
+        hipLaunchKernelGGL((k_pair_gas<R, DIM, SCHEME>), dim3(blocks_for(c->ng)), dim3(kBlock), 0, st, G, Ph, Sg, Sd,
+                           VR.dust, Pg, F);
+        LAUNCH_CHECK("pair_gas");
+    }
     if (c->nd > 0) {
         hipLaunchKernelGGL((k_pair_dust<R, DIM, SCHEME>), dim3(blocks_for(c->nd)), dim3(kBlock), 0, st, G, Ph, Sg, Sd,
-                           Pd, F);
+                           VR.gas, Pd, F);
         LAUNCH_CHECK("pair_dust");
     }
     MARK(TFSPH_KERNEL_UPDATE);
