@@ -223,8 +223,8 @@ k_pair_gas(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, const R4<R> *__res
 }
 
 // One dust particle of MK or ISPH: the drag (MK) or the interpolated gas state
-// and pressure gradient (ISPH) from the gas window, update, move.  The gas
-// records read are frc = (ox, oy, oz, P = p / rho^2) of the density pass.
+// and pressure gradient (ISPH) from the gas window, update, move.  ISPH walks
+// the gas records frc = (ox, oy, oz, P = p / rho^2) of the density pass.
 template <typename R, int DIM, int SCHEME>
 __global__ void __launch_bounds__(kBlock)
 k_pair_dust(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, const R4<R> *__restrict__ vrg, Phase<R> Pd,
