@@ -422,6 +422,10 @@ def main(argv=None):
     n_part = prob.gas.n + prob.dust.n
     sim = T.Simulation(prob, precision=T.TFSPH_F32)
     stream = torch.cuda.current_stream()
+    # cells per block of the update kernel, timed on this problem (the results do not depend on it)
+    from paper_1908_01682_amd import autotune as A
+    tuning = A.tune_plain(sim, steps=20, use_cache=False)
+    print(f"[bench] update kernel: {tuning['cells_per_block']} cells per block", file=sys.stderr, flush=True)
     sim.step(a.warmup)
     torch.cuda.synchronize()
     print(f"[bench] warmup done, timing {a.steps} steps", file=sys.stderr, flush=True)
@@ -506,6 +510,7 @@ def main(argv=None):
             "frac": sbytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "kernels": per_kernel,
         "kernel_ms_per_step": kernel_ms,
+        "tuning": {"cells_per_block": tuning["cells_per_block"], "ms_per_step": tuning["ms_per_step"]},
         "valu_issue_share": measured_valu_share(a.workload),
         "window_candidates": cand,
         "support_pairs": pairs,

@@ -1,12 +1,17 @@
-"""Launch-shape autotuner for the batched step.
+"""Launch-shape autotuners.
 
-The candidates are the persistent form (one workgroup per instance) at several
-workgroup sizes and the flattened form (six launches per step over every
-instance).  For a batch signature (device name, dim, precision, instance count,
-size distribution) it times every candidate on the real batch, checks that every
-candidate leaves a bitwise-identical state (the method's sums are evaluated in a
-fixed order, so the launch shape must not change a single bit), and caches the
-fastest in a JSON file.
+Batched step (``tune``): the candidates are the persistent form (one workgroup per
+instance) at several workgroup sizes and the flattened form (six launches per step over
+every instance).  For a batch signature (device name, dim, precision, instance count,
+size distribution) it times every candidate on the real batch.
+
+Plain step (``tune_plain``): the candidates are the cells owned by one block of the
+update kernel (cell sums, 2x2 solve, particle update), for a problem signature (device
+name, dim, precision, particle and cell counts).
+
+Both check that every candidate leaves a bitwise-identical state (the method's sums are
+evaluated in a fixed order, so the launch shape must not change a single bit) and cache
+the fastest in a JSON file.
 
 Cache path: $TFSPH_AUTOTUNE_CACHE, else ~/.cache/tfsph/autotune.json.
 """
@@ -21,6 +26,7 @@ from typing import Iterable, Optional
 import numpy as np
 
 CANDIDATE_BLOCKS = (256, 512, 768, 1024)
+CANDIDATE_CELLS_PER_BLOCK = (16, 32, 64, 128, 256)
 PERSISTENT, FLAT = 0, 1
 
 
@@ -121,5 +127,72 @@ def tune(bs, steps: int = 20, blocks: Iterable[int] = CANDIDATE_BLOCKS, use_cach
     bs.set_tuning(blk, form)
     entry = {"form": form, "block": blk, "ms_per_step": timings, "bitwise_identical": identical,
              "device": dev, "steps": steps}
+    store(key, entry, path)
+    return dict(entry, cached=False)
+
+
+def plain_signature(device_name: str, sim) -> str:
+    """Key of a single problem: device, dim, precision, particle and cell counts, scheme."""
+    p = sim.prob.params
+    raw = json.dumps(dict(dev=device_name, dim=int(p.dim), prec=int(sim.precision), ng=int(sim.gas.n),
+                          nd=int(sim.dust.n), cells=[int(c) for c in p.n_cells[:p.dim]],
+                          scheme=int(getattr(p, "scheme", 0)), kind="plain"), sort_keys=True)
+    return hashlib.sha1(raw.encode()).hexdigest()[:16]
+
+
+def _plain_tensors(sim):
+    out = []
+    for ph in (sim.gas, sim.dust):
+        out += [ph.cell, ph.id] + list(ph.off) + list(ph.vel)
+        out += [t for t in (ph.mass, ph.energy, ph.rho) if t is not None]
+    return out
+
+
+def tune_plain(sim, steps: int = 20, cells: Iterable[int] = CANDIDATE_CELLS_PER_BLOCK, use_cache: bool = True,
+               path: Optional[str] = None) -> dict:
+    """Pick the fastest cells-per-block of the update kernel for Simulation ``sim`` and apply it
+    (``tfsph_set_cells_per_block``).  Every candidate runs ``steps`` steps from the same state and
+    must leave it bitwise identical.  Returns {"cells_per_block": c, "ms_per_step": {c: ms},
+    "bitwise_identical": True, "cached": bool}; the state is restored to its entry value."""
+    import torch
+    from . import tfsph as T
+    dev = torch.cuda.get_device_name(sim.device)
+    key = plain_signature(dev, sim)
+    cands = [int(c) for c in cells]
+    if use_cache:
+        hit = load_cache(path).get(key)
+        if hit and int(hit.get("cells_per_block", 0)) in cands:
+            T.tfsph_set_cells_per_block(sim.ctx, int(hit["cells_per_block"]))
+            return dict(hit, cached=True)
+    live = _plain_tensors(sim)
+    snap = [t.clone() for t in live]
+
+    def restore():
+        for dst, src in zip(live, snap):
+            dst.copy_(src)
+
+    timings, digests = {}, {}
+    for c in cands:
+        T.tfsph_set_cells_per_block(sim.ctx, c)
+        restore()
+        sim.step(1)                 # loads the code objects outside the timing
+        restore()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        timings[str(c)] = 1e3 * (time.perf_counter() - t0) / steps
+        h = hashlib.sha1()
+        for t in live:
+            h.update(t.cpu().numpy().tobytes())
+        digests[str(c)] = h.hexdigest()
+    restore()
+    identical = len(set(digests.values())) == 1
+    if not identical:
+        raise RuntimeError(f"cells per block change the state: {digests}")
+    best = int(min(timings, key=timings.get))
+    T.tfsph_set_cells_per_block(sim.ctx, best)
+    entry = {"cells_per_block": best, "ms_per_step": timings, "bitwise_identical": identical, "device": dev,
+             "steps": steps}
     store(key, entry, path)
     return dict(entry, cached=False)
