@@ -321,7 +321,8 @@ def batched_throughput(I, T, torch, steps=500, plain_steps=20):
     plain = plain_ps / plain_t
     return {"value": value, "unit": "particle-steps/s", "ms_per_step": 1e3 * wall / steps, "steps": steps,
             "instances": len(probs), "particles": n_part, "block": tune["block"],
-            "form": "flat" if tune["form"] == A.FLAT else "persistent", "tuner_ms_per_step": tune["ms_per_step"],
+            "form": "flat" if tune["form"] == A.FLAT else "persistent", "cells_per_block": tune["cells_per_block"],
+            "tuner_ms_per_step": tune["ms_per_step"],
             "plain_path_value": plain, "vs_plain": value / plain, "nonfinite": bool(flags & 1)}
 
 

@@ -281,6 +281,8 @@ typedef struct {
     int32_t block;                  /* persistent form: threads per workgroup, multiple of 64 in
                                        64..1024 (0 = 512); the flattened form uses 256 */
     int32_t form;                   /* TFSPH_BATCH_PERSISTENT (0) or TFSPH_BATCH_FLAT */
+    int32_t cells_per_block;        /* flattened form: cells per workgroup of its update launch,
+                                       1..256 (0 = the single-problem default for the dimension) */
 } tfsph_batch_tuning;
 
 /* Host-only: workspace bytes for a batch (256-byte aligned buffer). */
@@ -292,7 +294,9 @@ tfsph_status tfsph_batch_workspace_size(const tfsph_batch_desc *desc, size_t *by
 tfsph_status tfsph_batch_init(tfsph_batch **out, const tfsph_batch_desc *desc, tfsph_state *packed,
                               const tfsph_batch_tuning *tuning, void *workspace, size_t ws_bytes, void *hip_stream);
 
-/* Change the launch shape (results do not depend on it). */
+/* Change the launch shape (results do not depend on it).  A new cells_per_block
+ * rewrites the flattened form's block table on the stream of the batch's last
+ * call (or of init) and drops the flattened form's captured graphs. */
 tfsph_status tfsph_batch_set_tuning(tfsph_batch *b, const tfsph_batch_tuning *tuning);
 
 /* Advance every instance n_steps IDIC steps: one kernel launch (persistent

@@ -2,7 +2,7 @@
 
 Batched step (``tune``): the candidates are the persistent form (one workgroup per
 instance) at several workgroup sizes and the flattened form (six launches per step over
-every instance).  For a batch signature (device name, dim, precision, instance count,
+every instance) at several cells per workgroup of its update launch.  For a batch signature (device name, dim, precision, instance count,
 size distribution) it times every candidate on the real batch.
 
 Plain step (``tune_plain``): the candidates are the cells owned by one block of the
@@ -27,6 +27,7 @@ import numpy as np
 
 CANDIDATE_BLOCKS = (256, 512, 768, 1024)
 CANDIDATE_CELLS_PER_BLOCK = (16, 32, 64, 128, 256)
+CANDIDATE_FLAT_CELLS = (64, 128, 256)
 PERSISTENT, FLAT = 0, 1
 
 
@@ -84,31 +85,34 @@ def _digest(bs) -> str:
 
 
 def tune(bs, steps: int = 20, blocks: Iterable[int] = CANDIDATE_BLOCKS, use_cache: bool = True,
-         path: Optional[str] = None, flat: bool = True, graph: bool = False) -> dict:
+         path: Optional[str] = None, flat: bool = True, graph: bool = False,
+         flat_cells: Iterable[int] = CANDIDATE_FLAT_CELLS) -> dict:
     """Pick the fastest launch shape for BatchedSimulation ``bs`` and apply it: the persistent
-    form at each workgroup size in ``blocks`` and, with ``flat``, the flattened form.  With
-    ``graph`` every candidate is timed as a replayed hipGraph of ``steps`` steps (captured
-    before the timing), as the caller will run it.
+    form at each workgroup size in ``blocks`` and, with ``flat``, the flattened form at each
+    number of cells per update workgroup in ``flat_cells``.  With ``graph`` every candidate is
+    timed as a replayed hipGraph of ``steps`` steps (captured before the timing), as the caller
+    will run it.
 
-    Returns {"form": f, "block": b, "ms_per_step": {...}, "bitwise_identical": True,
-    "cached": bool}; the timing keys are "persistent/<block>" and "flat".  The batch state is
-    restored to its entry value before returning.
+    Returns {"form": f, "block": b, "cells_per_block": c, "ms_per_step": {...},
+    "bitwise_identical": True, "cached": bool}; the timing keys are "persistent/<block>" and
+    "flat/<cells>".  The batch state is restored to its entry value before returning.
     """
     import torch
     dev = torch.cuda.get_device_name(bs.device)
     key = signature(dev, bs.probs, bs.precision)
-    cands = [(PERSISTENT, int(b)) for b in blocks] + ([(FLAT, 256)] if flat else [])
+    cands = [(PERSISTENT, int(b), 0) for b in blocks] + ([(FLAT, 256, int(c)) for c in flat_cells] if flat else [])
     if use_cache:
         hit = load_cache(path).get(key)
-        if hit and (int(hit.get("form", PERSISTENT)), int(hit.get("block", 0))) in cands:
-            bs.set_tuning(int(hit["block"]), int(hit.get("form", PERSISTENT)))
+        if hit and (int(hit.get("form", PERSISTENT)), int(hit.get("block", 0)),
+                    int(hit.get("cells_per_block", 0))) in cands:
+            bs.set_tuning(int(hit["block"]), int(hit.get("form", PERSISTENT)), int(hit.get("cells_per_block", 0)))
             return dict(hit, cached=True)
     snap = _snapshot(bs)
     timings, digests = {}, {}
-    for form, blk in cands:
-        name = "flat" if form == FLAT else f"persistent/{blk}"
+    for form, blk, cpb in cands:
+        name = f"flat/{cpb}" if form == FLAT else f"persistent/{blk}"
         _restore(bs, snap)
-        bs.set_tuning(blk, form)
+        bs.set_tuning(blk, form, cpb)
         run = bs.step_graph if graph else bs.step
         run(steps if graph else 1)  # capture, or load the code objects, outside the timing
         _restore(bs, snap)
@@ -123,10 +127,13 @@ def tune(bs, steps: int = 20, blocks: Iterable[int] = CANDIDATE_BLOCKS, use_cach
     if not identical:
         raise RuntimeError(f"launch shapes disagree bitwise: {digests}")
     best = min(timings, key=timings.get)
-    form, blk = (FLAT, 256) if best == "flat" else (PERSISTENT, int(best.split("/")[1]))
-    bs.set_tuning(blk, form)
-    entry = {"form": form, "block": blk, "ms_per_step": timings, "bitwise_identical": identical,
-             "device": dev, "steps": steps}
+    if best.startswith("flat/"):
+        form, blk, cpb = FLAT, 256, int(best.split("/")[1])
+    else:
+        form, blk, cpb = PERSISTENT, int(best.split("/")[1]), 0
+    bs.set_tuning(blk, form, cpb)
+    entry = {"form": form, "block": blk, "cells_per_block": cpb, "ms_per_step": timings,
+             "bitwise_identical": identical, "device": dev, "steps": steps}
     store(key, entry, path)
     return dict(entry, cached=False)
 

@@ -120,9 +120,12 @@ tfsph_status check_desc(const tfsph_batch_desc *desc, std::vector<InstLayout> &L
 
 struct tfsph_batch {
     int n_inst = 0, dim = 1, prec = 0, block = kDefaultBatchBlock, form = TFSPH_BATCH_PERSISTENT;
+    int flat_cpb = 0;              // cells per block of the flattened form's update launch
     FlatTable flat{};
     int flat_blocks_g = 0, flat_blocks_d = 0, flat_blocks_c = 0;
     std::vector<int> host_first;
+    std::vector<int> host_ncell;   // cells of each instance
+    int *dev_first = nullptr;      // device copy of host_first (in the workspace)
     tfsph_state bound{};
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -138,6 +141,30 @@ struct tfsph_batch {
     };
     std::map<std::tuple<int, int, int>, G> graphs;   // (n_steps, form, block) -> graph
 };
+
+// Block table of the flattened form over cells (first block of each instance at
+// b->flat_cpb cells per block), uploaded on st; flattened-form graphs captured
+// with another table are dropped.
+static tfsph_status upload_flat_cells(tfsph_batch *b, hipStream_t st)
+{
+    const int n = b->n_inst;
+    int *h = b->host_first.data() + 2 * (n + 1);
+    h[0] = 0;
+    for (int i = 0; i < n; ++i) h[i + 1] = h[i] + (b->host_ncell[i] + b->flat_cpb - 1) / b->flat_cpb;
+    b->flat_blocks_c = h[n];
+    b->flat.cells_per_block = b->flat_cpb;
+    for (auto it = b->graphs.begin(); it != b->graphs.end();) {
+        if (std::get<1>(it->first) == TFSPH_BATCH_FLAT) {
+            if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+            if (it->second.graph) (void)hipGraphDestroy(it->second.graph);
+            it = b->graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(b->dev_first + 2 * (n + 1), h, sizeof(int) * (n + 1), hipMemcpyHostToDevice, st));
+    return TFSPH_OK;
+}
 
 extern "C" tfsph_status tfsph_batch_workspace_size(const tfsph_batch_desc *desc, size_t *bytes)
 {
@@ -160,8 +187,15 @@ static tfsph_status set_tuning(tfsph_batch *b, const tfsph_batch_tuning *t)
     const int form = t ? t->form : TFSPH_BATCH_PERSISTENT;
     if (form != TFSPH_BATCH_PERSISTENT && form != TFSPH_BATCH_FLAT)
         return fail(TFSPH_E_INVALID_ARG, "form must be TFSPH_BATCH_PERSISTENT or TFSPH_BATCH_FLAT (%d)", form);
+    const int cpb = (t && t->cells_per_block) ? t->cells_per_block : kFlatCells(b->dim);
+    if (cpb < 1 || cpb > kMaxCellsPerBlock)
+        return fail(TFSPH_E_INVALID_ARG, "cells_per_block must be in 1..%d (0 = default), got %d", kMaxCellsPerBlock, cpb);
     b->block = blk;
     b->form = form;
+    if (cpb != b->flat_cpb) {
+        b->flat_cpb = cpb;
+        if (b->dev_first) return upload_flat_cells(b, b->last_stream);
+    }
     return TFSPH_OK;
 }
 
@@ -185,21 +219,22 @@ static tfsph_status batch_setup(tfsph_batch *b, const tfsph_batch_desc *desc, st
     // its dust particles and its cells
     const int n = (int)L.size();
     b->host_first.assign(size_t(3) * (n + 1), 0);
+    b->host_ncell.resize(n);
     for (int i = 0; i < n; ++i) {
         b->host_first[i + 1] = b->host_first[i] + blocks_for(L[i].ng);
         b->host_first[(n + 1) + i + 1] = b->host_first[(n + 1) + i] + blocks_for(L[i].nd);
-        b->host_first[2 * (n + 1) + i + 1] =
-            b->host_first[2 * (n + 1) + i] + (L[i].ncell + kFlatCells(b->dim) - 1) / kFlatCells(b->dim);
+        b->host_ncell[i] = L[i].ncell;
     }
     b->flat_blocks_g = b->host_first[n];
     b->flat_blocks_d = b->host_first[(n + 1) + n];
-    b->flat_blocks_c = b->host_first[2 * (n + 1) + n];
     b->flat.n_inst = n;
     b->flat.first_g = first;
     b->flat.first_d = first + (n + 1);
     b->flat.first_c = first + 2 * (n + 1);
-    b->flat.cells_per_block = kFlatCells(b->dim);
-    HIP_TRY(hipMemcpyAsync(first, b->host_first.data(), sizeof(int) * b->host_first.size(), hipMemcpyHostToDevice, st));
+    b->dev_first = first;
+    HIP_TRY(hipMemcpyAsync(first, b->host_first.data(), sizeof(int) * 2 * (n + 1), hipMemcpyHostToDevice, st));
+    tfsph_status rc = upload_flat_cells(b, st);
+    if (rc != TFSPH_OK) return rc;
     // largest-first order (work ~ particles); ties by index
     b->host_order.resize(L.size());
     std::iota(b->host_order.begin(), b->host_order.end(), 0);

@@ -64,7 +64,7 @@ class BatchDesc(ctypes.Structure):
 
 
 class BatchTuning(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int32), ("form", ctypes.c_int32)]
+    _fields_ = [("block", ctypes.c_int32), ("form", ctypes.c_int32), ("cells_per_block", ctypes.c_int32)]
 
 
 TFSPH_BATCH_PERSISTENT, TFSPH_BATCH_FLAT = 0, 1
@@ -474,7 +474,7 @@ class BatchedSimulation:
     six launches per step over every instance (TFSPH_BATCH_FLAT)."""
 
     def __init__(self, probs, precision: int = TFSPH_F32, device="cuda", block: int = 0, stream=None,
-                 form: int = TFSPH_BATCH_PERSISTENT):
+                 form: int = TFSPH_BATCH_PERSISTENT, cells_per_block: int = 0):
         import torch
         self.probs = list(probs)
         self.precision = precision
@@ -514,13 +514,15 @@ class BatchedSimulation:
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.workspace.data_ptr()) % 256
         self._ws = self.workspace[off:]
-        self.block, self.form = block, form
-        self.handle = tfsph_batch_init(self.desc, self.state, BatchTuning(block, form), self._ws, self.ws_bytes,
-                                       stream)
+        self.block, self.form, self.cells_per_block = block, form, cells_per_block
+        self.handle = tfsph_batch_init(self.desc, self.state, BatchTuning(block, form, cells_per_block), self._ws,
+                                       self.ws_bytes, stream)
 
-    def set_tuning(self, block: int, form: int = TFSPH_BATCH_PERSISTENT) -> None:
-        tfsph_batch_set_tuning(self.handle, BatchTuning(block, form))
-        self.block, self.form = block, form
+    def set_tuning(self, block: int, form: int = TFSPH_BATCH_PERSISTENT, cells_per_block: int = 0) -> None:
+        """Launch shape: workgroup size of the persistent form, the form, and the cells per
+        workgroup of the flattened form's update launch (0 = default).  Results do not change."""
+        tfsph_batch_set_tuning(self.handle, BatchTuning(block, form, cells_per_block))
+        self.block, self.form, self.cells_per_block = block, form, cells_per_block
 
     def set_block(self, block: int) -> None:
         self.set_tuning(block, TFSPH_BATCH_PERSISTENT)

@@ -174,16 +174,46 @@ def test_autotuner_picks_a_shape_and_caches(tmp_path):
     before = [bs.instance(i) for i in range(len(probs))]
     r1 = A.tune(bs, steps=4, blocks=(256, 512, 1024), path=path, graph=True)
     assert r1["bitwise_identical"] and not r1["cached"]
-    assert set(r1["ms_per_step"]) == {"persistent/256", "persistent/512", "persistent/1024", "flat"}
-    assert (r1["form"], r1["block"]) in ((A.PERSISTENT, 256), (A.PERSISTENT, 512), (A.PERSISTENT, 1024),
-                                         (A.FLAT, 256))
+    assert set(r1["ms_per_step"]) == {"persistent/256", "persistent/512", "persistent/1024",
+                                      *(f"flat/{c}" for c in A.CANDIDATE_FLAT_CELLS)}
+    assert (r1["form"], r1["block"], r1["cells_per_block"]) in (
+        [(A.PERSISTENT, b, 0) for b in (256, 512, 1024)] + [(A.FLAT, 256, c) for c in A.CANDIDATE_FLAT_CELLS])
     after = [bs.instance(i) for i in range(len(probs))]      # state restored
     for (g0, d0), (g1, d1) in zip(before, after):
         for k in ("cell", "id", "off", "vel"):
             assert np.array_equal(g0[k], g1[k]) and np.array_equal(d0[k], d1[k])
     r2 = A.tune(bs, steps=4, blocks=(256, 512, 1024), path=path, graph=True)
-    assert r2["cached"] and (r2["form"], r2["block"]) == (r1["form"], r1["block"])
-    assert (bs.form, bs.block) == (r1["form"], r1["block"])
+    assert r2["cached"] and (r2["form"], r2["block"], r2["cells_per_block"]) == \
+        (r1["form"], r1["block"], r1["cells_per_block"])
+    assert (bs.form, bs.block, bs.cells_per_block) == (r1["form"], r1["block"], r1["cells_per_block"])
+    bs.close()
+
+
+def test_flat_cells_per_block_invariance():
+    """The flattened form at several cells per update workgroup, changed between calls and
+    across graph replays (a graph captured with another block table is dropped), gives
+    bitwise the state of the default shape."""
+    probs = _batch_1d(seed=9, n_inst=5)
+    ref = T.BatchedSimulation(probs, precision=0, form=T.TFSPH_BATCH_FLAT)
+    ref.step(12)
+    torch.cuda.synchronize()
+    want = [ref.instance(i) for i in range(len(probs))]
+    ref.close()
+    bs = T.BatchedSimulation(probs, precision=0, form=T.TFSPH_BATCH_FLAT, cells_per_block=16)
+    bs.step_graph(3)
+    bs.set_tuning(256, T.TFSPH_BATCH_FLAT, 200)
+    bs.step_graph(3)
+    bs.set_tuning(256, T.TFSPH_BATCH_FLAT, 16)
+    bs.step_graph(3)                 # the same key as the first capture, with the table rebuilt
+    bs.set_tuning(256, T.TFSPH_BATCH_FLAT, 1)
+    bs.step(3)
+    torch.cuda.synchronize()
+    for i, (g, d) in enumerate(want):
+        g1, d1 = bs.instance(i)
+        _same(g, g1)
+        _same(d, d1)
+    with pytest.raises(T.TfsphError):
+        bs.set_tuning(256, T.TFSPH_BATCH_FLAT, 257)
     bs.close()
 
 
