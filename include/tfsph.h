@@ -54,7 +54,7 @@ enum {
     TFSPH_FLAG_NONFINITE = 1u,         /* a velocity, offset or density became NaN/Inf */
     TFSPH_FLAG_EMPTY_PHASE_CELL = 2u,  /* some cell held particles of one phase only */
     TFSPH_FLAG_BAD_CELL = 4u,          /* a state cell index was out of range (treated as cell 0) */
-    TFSPH_FLAG_CELL_OVERFLOW = 8u,     /* a cell held more than 4096 particles of one phase: its
+    TFSPH_FLAG_CELL_OVERFLOW = 8u,     /* a cell held more than 65536 particles of one phase: its
                                           in-cell order fell back to arrival order (not reproducible) */
     TFSPH_FLAG_CFL = 16u               /* with tfsph_params.cfl > 0: after some step the Courant
                                           bound of eq. (4), tau < CFL h / max(|v|, c), no longer

@@ -238,7 +238,10 @@ __device__ __forceinline__ int safe_cell(int c, int ncell)
     return (c >= 0 && c < ncell) ? c : 0;
 }
 
-constexpr int kMaxRankCell = 1 << 12;    // cells above this size are ordered by slot, and flagged
+// Cells up to this size are ranked by id (each particle counts the smaller ids
+// of its cell, so a crowded cell costs the square of its population); above
+// it a cell keeps the order of its slot claims and is flagged.
+constexpr int kMaxRankCell = 1 << 16;
 
 __device__ __forceinline__ int wrap_index(int c, int n)
 {

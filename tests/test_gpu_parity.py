@@ -443,17 +443,53 @@ def test_cells_per_block_bitwise_invariant(name, make, precision):
                 assert np.array_equal(out[0][1][k], other[1][k]), k
 
 
+def _crowded(n_side, per_cell, phases, seed=5):
+    """A 1D wave (200 cells) with per_cell particles of each named phase moved into cell 7."""
+    prob = I.dusty_wave(n_side=n_side, amp=0.0, cells_per_axis=200)
+    rng = np.random.default_rng(seed)
+    D = 1.0 / 200
+    for name in phases:
+        ph = getattr(prob, name)
+        pick = rng.choice(ph.n, per_cell, replace=False)
+        ph.x[pick, 0] = 7 * D + rng.uniform(0.05, 0.95, per_cell) * D
+    for ph in (prob.gas, prob.dust):
+        ph.v[:, 0] = 1e-2 * rng.standard_normal(ph.n)
+    return prob
+
+
+def test_crowded_cell_is_ranked_by_id(orc):
+    """A drag cell holding 4200 particles of each phase: ranked by id like any other cell (no
+    flag), the state in canonical (cell, id) order, bitwise the same on a second run, and the
+    step matches the oracle (sums over the crowded cell in another order: rounding only)."""
+    prob = _crowded(6000, 4200, ("gas", "dust"))
+    p = prob.params
+    runs = []
+    for _ in range(2):
+        sim = _sim(prob, 0)
+        if not runs:
+            og, od = oracle_phase(orc, sim.gas.numpy(), 1), oracle_phase(orc, sim.dust.numpy(), 1)
+        sim.step(1)
+        torch.cuda.synchronize()
+        runs.append((sim.gas.numpy(), sim.dust.numpy(), sim.flags()[0]))
+        sim.close()
+    orc.step(p, og, od, 1)
+    G, D, flags = runs[0]
+    err = compare_states(p, G, D, og, od, p.c_s)
+    assert not flags & (T.TFSPH_FLAG_CELL_OVERFLOW | T.TFSPH_FLAG_NONFINITE)
+    assert all(v <= TOL32 for v in err.values()), err
+    for ph in (G, D):
+        key = ph["cell"].astype(np.int64) * (1 << 32) + ph["id"]
+        assert np.all(np.diff(key) > 0)
+    for a, b in zip(runs[0][:2], runs[1][:2]):
+        for k in ("cell", "id", "off", "vel"):
+            assert np.array_equal(a[k], b[k]), k
+
+
 def test_cell_over_the_rank_limit(orc):
-    """A drag cell holding more than 4096 particles of a phase: flagged TFSPH_FLAG_CELL_OVERFLOW
+    """A drag cell holding more than 65536 dust particles: flagged TFSPH_FLAG_CELL_OVERFLOW
     (the order inside that cell then follows the slot claims), and the step still matches the
     oracle (sums over the crowded cell in another order: rounding only)."""
-    prob = I.dusty_wave(n_side=6000, amp=0.0, cells_per_axis=200)
-    rng = np.random.default_rng(5)
-    D = 1.0 / 200
-    for ph in (prob.gas, prob.dust):
-        pick = rng.choice(ph.n, 4200, replace=False)
-        ph.x[pick, 0] = 7 * D + rng.uniform(0.05, 0.95, 4200) * D
-        ph.v[:, 0] = 1e-2 * rng.standard_normal(ph.n)
+    prob = _crowded(70000, 66000, ("dust",))
     p = prob.params
     sim = _sim(prob, 0)
     og, od = oracle_phase(orc, sim.gas.numpy(), 1), oracle_phase(orc, sim.dust.numpy(), 1)
