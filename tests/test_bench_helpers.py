@@ -88,3 +88,9 @@ def test_step_bytes_counts_state_keys_density_and_cells():
     per_gas = 16 * 3 + 8 + 8 + (8 if g.uniform_mass() is None else 0)
     per_dust = 16 * 3 + 8 + (8 if s.uniform_mass() is None else 0)
     assert bench.step_bytes(prob) == g.n * per_gas + s.n * per_dust + 32 * 4 ** 3
+
+
+def test_more_than_one_gpu_is_refused(capsys):
+    """bench.py measures one GPU: --gpus above 1 exits with a message before touching a device."""
+    assert bench.main(["--gpus", "2"]) == 2
+    assert "one GPU only" in capsys.readouterr().err
