@@ -289,10 +289,11 @@ def drag_schemes(prob, I, T, torch, steps=100, warmup=50, cpu_steps=0, counts=No
     return out
 
 
-def batched_throughput(I, T, torch, steps=500, plain_steps=20):
+def batched_throughput(I, T, torch, steps=500, plain_steps=20, cpu_steps=0):
     """256 uneven 1D dusty waves advanced together (form and workgroup size autotuned among the
     persistent kernel and the flattened launches, hipGraph replay), against the same instances
-    through the plain path one at a time."""
+    through the plain path one at a time; with cpu_steps > 0 also the oracle on every instance,
+    one after the other, on the host cores."""
     from paper_1908_01682_amd import autotune as A
     probs = I.batched_waves(steps=steps)
     n_part = sum(p.gas.n + p.dust.n for p in probs)
@@ -319,16 +320,29 @@ def batched_throughput(I, T, torch, steps=500, plain_steps=20):
         sim.close()
     value = n_part * steps / wall
     plain = plain_ps / plain_t
-    return {"value": value, "unit": "particle-steps/s", "ms_per_step": 1e3 * wall / steps, "steps": steps,
+    cpu = None
+    if cpu_steps > 0:
+        from oracle import oracle as O
+        O.build()
+        states = [O.from_problem(p) for p in probs]
+        t0 = time.perf_counter()
+        for p, (g, d) in zip(probs, states):
+            O.step(p.params, g, d, cpu_steps)
+        dt = time.perf_counter() - t0
+        cpu = {"value": n_part * cpu_steps / dt, "unit": "particle-steps/s", "cores": O.num_threads(),
+               "kind": "oracle", "sample": f"{cpu_steps} step(s) of every instance, FP64, {dt:.2f} s wall"}
+    return {"cpu_baseline": cpu, "value": value, "unit": "particle-steps/s", "ms_per_step": 1e3 * wall / steps,
+            "steps": steps,
             "instances": len(probs), "particles": n_part, "block": tune["block"],
             "form": "flat" if tune["form"] == A.FLAT else "persistent", "cells_per_block": tune["cells_per_block"],
             "tuner_ms_per_step": tune["ms_per_step"],
             "plain_path_value": plain, "vs_plain": value / plain, "nonfinite": bool(flags & 1)}
 
 
-def imex_throughput(prob, T, torch, steps=100, warmup=100):
+def imex_throughput(prob, T, torch, steps=100, warmup=100, cpu_steps=0):
     """The same workload with the second-order IMEX step (three binnings, two density and force
-    passes, two drag solves per step)."""
+    passes, two drag solves per step); with cpu_steps > 0 also the oracle's IMEX step on the host
+    cores."""
     q = prob.copy()
     q.params = q.params.replace(scheme=T.TFSPH_SCHEME_IMEX2)
     sim = T.Simulation(q, precision=T.TFSPH_F32)
@@ -341,8 +355,19 @@ def imex_throughput(prob, T, torch, steps=100, warmup=100):
     flags, _ = sim.flags()
     sim.close()
     n = q.gas.n + q.dust.n
-    return {"ms_per_step": 1e3 * wall / steps, "value": n * steps / wall, "unit": "particle-steps/s",
-            "steps": steps, "nonfinite": bool(flags & T.TFSPH_FLAG_NONFINITE)}
+    rec = {"ms_per_step": 1e3 * wall / steps, "value": n * steps / wall, "unit": "particle-steps/s",
+           "steps": steps, "nonfinite": bool(flags & T.TFSPH_FLAG_NONFINITE)}
+    if cpu_steps > 0:
+        from oracle import oracle as O
+        O.build()
+        g, d = O.from_problem(q)
+        t0 = time.perf_counter()
+        O.step(q.params, g, d, cpu_steps)
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": n * cpu_steps / dt, "unit": "particle-steps/s", "cores": O.num_threads(),
+                               "kind": "oracle", "sample": f"{cpu_steps} IMEX step(s) of the same workload, FP64, "
+                                                           f"{dt:.2f} s wall"}
+    return rec
 
 
 def cpu_baseline(prob, steps: int, steps_1t: int = 1):
@@ -383,7 +408,7 @@ def main(argv=None):
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 256 MiB device buffer 3 times (reference for HBM byte counters)")
     ap.add_argument("--scheme-cpu-steps", type=int, default=1,
-                    help="oracle steps timed per drag scheme in the scheme comparison")
+                    help="oracle steps timed per drag scheme in the scheme comparison, and for the IMEX step")
     ap.add_argument("--only", choices=("adjoint", "batched", "schemes"),
                     help="run only that extra measurement and print its record as the JSON line "
                          "(for profiling it on its own; not the benchmark line)")
@@ -524,10 +549,10 @@ def main(argv=None):
         result["adjoint_forward_ratio"] = adj["ratio"]
         result["adjoint"] = adj
         print("[bench] batched 1D waves", file=sys.stderr, flush=True)
-        result["batched"] = batched_throughput(I, T, torch)
+        result["batched"] = batched_throughput(I, T, torch, cpu_steps=0 if a.no_cpu_baseline else 1)
         if not imex_main:
             print("[bench] second-order IMEX step on the same workload", file=sys.stderr, flush=True)
-            imex = imex_throughput(prob, T, torch)
+            imex = imex_throughput(prob, T, torch, cpu_steps=0 if a.no_cpu_baseline else a.scheme_cpu_steps)
             imex["cost_vs_first_order"] = imex["ms_per_step"] / result["uninstrumented"]["ms_per_step"]
             result["imex"] = imex
             print(f"[bench] the three drag schemes at t_stop {SCHEME_T_STOP}", file=sys.stderr, flush=True)
