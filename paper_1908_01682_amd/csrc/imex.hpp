@@ -173,6 +173,37 @@ k_imex_stage3(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, Stage<R> Xg, St
     set_flag<R>(F, !ok);
 }
 
+// Stage-1 binning of an IMEX step that follows another one in the same call.
+// The final drag solve of that step wrote the caller's arrays at the sorted
+// index of its last binning, with the positions that binning used, so they are
+// already in canonical (cell, id) order with those cells: a counting sort would
+// leave every particle in place.  This copies them into the sorted layout (the
+// same values k_rank_gather would gather) and takes that binning's cell
+// offsets.  One thread per particle of either phase (gas blocks first); the
+// first ncell + 1 threads of each phase also copy its offsets.
+template <typename R>
+__global__ void __launch_bounds__(kBlock)
+k_imex_rebin(Geom<R> G, Phase<R> Pg, Sorted<R> Sg, const int *__restrict__ start_g, Phase<R> Pd, Sorted<R> Sd,
+             const int *__restrict__ start_d, int blocks_g)
+{
+    const bool gas = int(blockIdx.x) < blocks_g;
+    const int t = (gas ? int(blockIdx.x) : int(blockIdx.x) - blocks_g) * kBlock + int(threadIdx.x);
+    const Phase<R> &P = gas ? Pg : Pd;
+    const Sorted<R> &S = gas ? Sg : Sd;
+    if (t <= G.ncell) S.start[t] = (gas ? start_g : start_d)[t];
+    if (t >= S.n) return;
+    S.cell[t] = P.cell[t];
+    S.id[t] = P.id[t];
+    R o[3] = {R(0), R(0), R(0)};
+    for (int d = 0; d < G.dim; ++d) {
+        o[d] = P.off[d][t];
+        S.vel[d][t] = P.vel[d][t];
+    }
+    S.pos[t] = mk4<R>(o[0], o[1], o[2], P.mass ? P.mass[t] : P.m_uniform);
+    if (S.energy) S.energy[t] = P.energy[t];
+    if (S.src) S.src[t] = t;
+}
+
 // Implicit drag over gamma tau on the binning (Sg, Sd) whose velocities are the
 // stage predictors (Ph carries tau = gamma tau and g = 0, so the cell sums
 // take the predictors as they are).  Cell sums and solve as in k_update.

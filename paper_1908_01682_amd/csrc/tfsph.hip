@@ -401,8 +401,10 @@ void launch_by_kind(const Phys<R> &Ph, const Sorted<R> &S, L &&launch)
 }
 
 // One second-order IMEX step: see imex.hpp for the stages.
+// reuse: this step follows an IMEX step of the same call on the same stream, so
+// its stage-1 binning is that step's last one (k_imex_rebin)
 template <typename R, int DIM>
-tfsph_status enqueue_step_imex(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
+tfsph_status enqueue_step_imex(tfsph_ctx *c, tfsph_state *s, hipStream_t st, bool reuse)
 {
     const Geom<R> G = make_geom<R>(&c->p);
     const Phys<R> Ph = make_phys<R>(&c->p);
@@ -425,8 +427,15 @@ tfsph_status enqueue_step_imex(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
 
     // stage 1: volumes and explicit terms at level n, stage-2 predictors
     MARK(TFSPH_KERNEL_BIN);
-    r = enqueue_bin<R>(ng, nd, G, Pg, Pd, Sg, Sd, partial, F, st);
-    if (r != TFSPH_OK) return r;
+    if (reuse) {
+        const int nb = std::max(std::max(bg, bd), blocks_for(G.ncell + 1));
+        hipLaunchKernelGGL((k_imex_rebin<R>), dim3(2 * nb), dim3(kBlock), 0, st, G, Pg, Sg, V.Sg.start, Pd, Sd,
+                           V.Sd.start, nb);
+        LAUNCH_CHECK("imex_rebin");
+    } else {
+        r = enqueue_bin<R>(ng, nd, G, Pg, Pd, Sg, Sd, partial, F, st);
+        if (r != TFSPH_OK) return r;
+    }
     MARK(TFSPH_KERNEL_BIN);
     if (ng > 0) {
         MARK(TFSPH_KERNEL_DENSITY);
@@ -637,8 +646,9 @@ tfsph_status enqueue_density(tfsph_ctx *c, tfsph_state *s, int phase, hipStream_
     return TFSPH_OK;
 }
 
+// follows: the previous step of the same call was enqueued just before on st
 template <typename R>
-tfsph_status dispatch_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
+tfsph_status dispatch_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st, bool follows = false)
 {
     const bool imex = c->p.scheme == TFSPH_SCHEME_IMEX2;
     if (c->profiling) {
@@ -654,9 +664,9 @@ tfsph_status dispatch_step(tfsph_ctx *c, tfsph_state *s, hipStream_t st)
         }
     }
     switch (c->p.dim) {
-    case 1: return imex ? enqueue_step_imex<R, 1>(c, s, st) : enqueue_step<R, 1>(c, s, st);
-    case 2: return imex ? enqueue_step_imex<R, 2>(c, s, st) : enqueue_step<R, 2>(c, s, st);
-    default: return imex ? enqueue_step_imex<R, 3>(c, s, st) : enqueue_step<R, 3>(c, s, st);
+    case 1: return imex ? enqueue_step_imex<R, 1>(c, s, st, follows) : enqueue_step<R, 1>(c, s, st);
+    case 2: return imex ? enqueue_step_imex<R, 2>(c, s, st, follows) : enqueue_step<R, 2>(c, s, st);
+    default: return imex ? enqueue_step_imex<R, 3>(c, s, st, follows) : enqueue_step<R, 3>(c, s, st);
     }
 }
 
@@ -725,7 +735,7 @@ extern "C" tfsph_status tfsph_step(tfsph_ctx *c, tfsph_state *s, int32_t n_steps
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     c->last_stream = st;
     for (int i = 0; i < n_steps; ++i) {
-        r = c->p.precision == TFSPH_F64 ? dispatch_step<double>(c, s, st) : dispatch_step<float>(c, s, st);
+        r = c->p.precision == TFSPH_F64 ? dispatch_step<double>(c, s, st, i > 0) : dispatch_step<float>(c, s, st, i > 0);
         if (r != TFSPH_OK) return r;
     }
     return TFSPH_OK;
@@ -903,8 +913,8 @@ extern "C" tfsph_status tfsph_step_graph(tfsph_ctx *c, tfsph_state *s, int32_t n
             c->profiling = false;
             HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
             for (int i = 0; i < chunk && r == TFSPH_OK; ++i)
-                r = c->p.precision == TFSPH_F64 ? dispatch_step<double>(c, s, c->capture_stream)
-                                                : dispatch_step<float>(c, s, c->capture_stream);
+                r = c->p.precision == TFSPH_F64 ? dispatch_step<double>(c, s, c->capture_stream, i > 0)
+                                                : dispatch_step<float>(c, s, c->capture_stream, i > 0);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
             c->profiling = prof;
@@ -920,7 +930,7 @@ extern "C" tfsph_status tfsph_step_graph(tfsph_ctx *c, tfsph_state *s, int32_t n
         for (int k = 0; k < n_full; ++k) HIP_TRY(hipGraphLaunch(c->sg.exec, st));
     }
     for (int i = 0; i < rem; ++i) {
-        r = c->p.precision == TFSPH_F64 ? dispatch_step<double>(c, s, st) : dispatch_step<float>(c, s, st);
+        r = c->p.precision == TFSPH_F64 ? dispatch_step<double>(c, s, st, i > 0) : dispatch_step<float>(c, s, st, i > 0);
         if (r != TFSPH_OK) return r;
     }
     return TFSPH_OK;
@@ -1008,7 +1018,7 @@ extern "C" tfsph_status tfsph_step_noalloc(const tfsph_params *p, tfsph_state *s
     r = p->precision == TFSPH_F64 ? enqueue_init<double>(&c, s, st) : enqueue_init<float>(&c, s, st);
     if (r != TFSPH_OK) return r;
     for (int i = 0; i < n_steps; ++i) {
-        r = p->precision == TFSPH_F64 ? dispatch_step<double>(&c, s, st) : dispatch_step<float>(&c, s, st);
+        r = p->precision == TFSPH_F64 ? dispatch_step<double>(&c, s, st, i > 0) : dispatch_step<float>(&c, s, st, i > 0);
         if (r != TFSPH_OK) return r;
     }
     if (flags_out || one_phase_out) {
