@@ -103,13 +103,23 @@ __device__ __forceinline__ void for_support(const Geom<R> &G, int cx, int cy, in
     if (!rows) for_window<R, DIM>(G, cx, cy, cz, oa, start, data, fn);
 }
 
-// K / (rho_g rho_d) and K of eq. (7) at a point or a pair, by drag law
+// K of eq. (7) at a point or a pair, by drag law
 template <typename R>
 __device__ __forceinline__ R drag_coef(const Phys<R> &Ph, R rho_g, R rho_d)
 {
     if (Ph.drag_law == 1) return Ph.Kc;
     if (Ph.drag_law == 2) return rho_g * rho_d * Ph.inv_te;
     return rho_d * Ph.inv_tstop;
+}
+
+// K / (rho_g rho_d) of the MK pair term from the inverse densities: the
+// t_stop law needs 1/rho_g only, the Epstein law neither
+template <typename R>
+__device__ __forceinline__ R drag_over_rhos(const Phys<R> &Ph, R inv_rho_g, R inv_rho_d)
+{
+    if (Ph.drag_law == 1) return Ph.Kc * inv_rho_g * inv_rho_d;
+    if (Ph.drag_law == 2) return Ph.inv_te;
+    return Ph.inv_tstop * inv_rho_g;
 }
 
 // x^{n+1} = x^n + tau v^{n+1}, carry, and the caller's arrays at sorted index i
@@ -163,16 +173,17 @@ k_pair_gas(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, const R4<R> *__res
             // the drag of eq. (8) takes the velocities of level n
             const R va[3] = {Sg.vel[0][a], DIM > 1 ? Sg.vel[1][a] : R(0), DIM > 2 ? Sg.vel[2][a] : R(0)};
             const R eta2 = R(0.001) * G.h * G.h;
+            const R inv_rho_a = R(1) / rho_a;
             R dx = R(0), dy = R(0), dz = R(0);
             for_support<R, DIM>(G, cx, cy, cz, oa, Sd.start, Sd.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
                 if (!ok) return;
                 const R r2 = rx * rx + ry * ry + rz * rz;
                 const R w = spline_f(fsqrt(r2) * G.inv_h);
                 const R4<R> ub = vrd[b];
-                const R rho_b = ub.w;
+                const R inv_rho_b = Ph.drag_law == 1 ? frcp(ub.w) : R(0);   // the K law only
                 const R vr = (va[0] - ub.x) * rx + (DIM > 1 ? (va[1] - ub.y) * ry : R(0)) +
                              (DIM > 2 ? (va[2] - ub.z) * rz : R(0));
-                const R X = q.w * drag_coef(Ph, rho_a, rho_b) / (rho_a * rho_b) * vr / (r2 + eta2) * w;
+                const R X = q.w * drag_over_rhos(Ph, inv_rho_a, inv_rho_b) * vr * frcp(r2 + eta2) * w;
                 dx -= X * rx;
                 dy -= X * ry;
                 dz -= X * rz;
@@ -188,7 +199,7 @@ k_pair_gas(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, const R4<R> *__res
                 const R r2 = rx * rx + ry * ry + rz * rz;
                 const R mw = q.w * spline_f(fsqrt(r2) * G.inv_h);
                 const R4<R> ub = vrd[b];
-                const R f = mw / ub.w;
+                const R f = mw * frcp(ub.w);
                 rd += mw;
                 ux += f * ub.x;
                 if (DIM > 1) uy += f * ub.y;
@@ -243,16 +254,17 @@ k_pair_dust(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, const R4<R> *__re
         R un[3];
         if constexpr (SCHEME == kPairMK) {
             const R eta2 = R(0.001) * G.h * G.h;
+            const R inv_rho_j = R(1) / rho_j;
             R dx = R(0), dy = R(0), dz = R(0);
             for_support<R, DIM>(G, cx, cy, cz, oj, Sg.start, Sg.pos, [&](int b, const R4<R> &q, R rx, R ry, R rz, bool ok) {
                 if (!ok) return;
                 const R r2 = rx * rx + ry * ry + rz * rz;
                 const R w = spline_f(fsqrt(r2) * G.inv_h);
                 const R4<R> vb = vrg[b];
-                const R rho_b = vb.w;
+                const R inv_rho_b = Ph.drag_law == 2 ? R(0) : frcp(vb.w);   // not needed by the Epstein law
                 const R vr = (vb.x - uj[0]) * rx + (DIM > 1 ? (vb.y - uj[1]) * ry : R(0)) +
                              (DIM > 2 ? (vb.z - uj[2]) * rz : R(0));
-                const R X = q.w * drag_coef(Ph, rho_b, rho_j) / (rho_b * rho_j) * vr / (r2 + eta2) * w;
+                const R X = q.w * drag_over_rhos(Ph, inv_rho_b, inv_rho_j) * vr * frcp(r2 + eta2) * w;
                 dx += X * rx;
                 dy += X * ry;
                 dz += X * rz;
@@ -273,9 +285,9 @@ k_pair_dust(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, const R4<R> *__re
                 const R4<R> vb = vrg[b];
                 const R rho_b = vb.w;
                 const R mw = m * spline_f(qq);
-                const R f = mw / rho_b;
+                const R f = mw * frcp(rho_b);
                 rg += mw;
-                pj += f * (q.w * rho_b * rho_b);            // p_b / rho_b W m_b
+                pj += mw * (q.w * rho_b);                   // m_b W p_b / rho_b (P_b = p_b / rho_b^2)
                 vx += f * vb.x;
                 if (DIM > 1) vy += f * vb.y;
                 if (DIM > 2) vz += f * vb.z;
