@@ -40,8 +40,13 @@ size_t batch_bytes(const std::vector<InstLayout> &L, int dim, Carver &cv, std::v
     int *order = cv.take<int>(n);
     unsigned int *word = cv.take<unsigned int>(64);
     unsigned long long *one = cv.take<unsigned long long>(8);
-    int *first = cv.take<int>(size_t(3) * (n + 1));      // block tables of the flattened form
-    (void)dev_table, (void)order, (void)word, (void)one, (void)first;
+    // block tables of the flattened form: over the particles of both phases, and over the
+    // cells at one cell per block (the most blocks any cells_per_block gives)
+    size_t part = 0, cells = 0;
+    for (const InstLayout &l : L) part += size_t(blocks_for(l.ng)) + blocks_for(l.nd), cells += l.ncell;
+    int2 *tab_part = cv.take<int2>(part);
+    int2 *tab_cells = cv.take<int2>(cells);
+    (void)dev_table, (void)order, (void)word, (void)one, (void)tab_part, (void)tab_cells;
     for (int i = 0; i < n; ++i) {
         PhaseFlags fg{L[i].mass_g, false, true}, fd{L[i].mass_d, false, false};
         Sorted<R> Sg = carve_phase<R>(cv, L[i].ng, dim, L[i].ncell, fg);
@@ -123,9 +128,10 @@ struct tfsph_batch {
     int flat_cpb = 0;              // cells per block of the flattened form's update launch
     FlatTable flat{};
     int flat_blocks_g = 0, flat_blocks_d = 0, flat_blocks_c = 0;
-    std::vector<int> host_first;
     std::vector<int> host_ncell;   // cells of each instance
-    int *dev_first = nullptr;      // device copy of host_first (in the workspace)
+    std::vector<int2> host_part;   // block table over particles (kept alive for the async upload)
+    std::vector<int2> host_cells;  // block table over cells, sized for one cell per block
+    int2 *dev_cells = nullptr;     // its device copy (in the workspace)
     tfsph_state bound{};
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -142,16 +148,19 @@ struct tfsph_batch {
     std::map<std::tuple<int, int, int>, G> graphs;   // (n_steps, form, block) -> graph
 };
 
-// Block table of the flattened form over cells (first block of each instance at
-// b->flat_cpb cells per block), uploaded on st; flattened-form graphs captured
-// with another table are dropped.
+// Block table of the flattened form over cells ((instance, block in the instance)
+// at b->flat_cpb cells per block), uploaded on st, which is then synchronized (the
+// host table is rewritten by the next call); flattened-form graphs captured with
+// another table are dropped.
 static tfsph_status upload_flat_cells(tfsph_batch *b, hipStream_t st)
 {
     const int n = b->n_inst;
-    int *h = b->host_first.data() + 2 * (n + 1);
-    h[0] = 0;
-    for (int i = 0; i < n; ++i) h[i + 1] = h[i] + (b->host_ncell[i] + b->flat_cpb - 1) / b->flat_cpb;
-    b->flat_blocks_c = h[n];
+    int k = 0;
+    for (int i = 0; i < n; ++i) {
+        const int nb = (b->host_ncell[i] + b->flat_cpb - 1) / b->flat_cpb;
+        for (int j = 0; j < nb; ++j) b->host_cells[k++] = make_int2(i, j);
+    }
+    b->flat_blocks_c = k;
     b->flat.cells_per_block = b->flat_cpb;
     for (auto it = b->graphs.begin(); it != b->graphs.end();) {
         if (std::get<1>(it->first) == TFSPH_BATCH_FLAT) {
@@ -162,7 +171,8 @@ static tfsph_status upload_flat_cells(tfsph_batch *b, hipStream_t st)
             ++it;
         }
     }
-    HIP_TRY(hipMemcpyAsync(b->dev_first + 2 * (n + 1), h, sizeof(int) * (n + 1), hipMemcpyHostToDevice, st));
+    if (k) HIP_TRY(hipMemcpyAsync(b->dev_cells, b->host_cells.data(), sizeof(int2) * k, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
     return TFSPH_OK;
 }
 
@@ -194,7 +204,7 @@ static tfsph_status set_tuning(tfsph_batch *b, const tfsph_batch_tuning *t)
     b->form = form;
     if (cpb != b->flat_cpb) {
         b->flat_cpb = cpb;
-        if (b->dev_first) return upload_flat_cells(b, b->last_stream);
+        if (b->dev_cells) return upload_flat_cells(b, b->last_stream);
     }
     return TFSPH_OK;
 }
@@ -214,25 +224,28 @@ static tfsph_status batch_setup(tfsph_batch *b, const tfsph_batch_desc *desc, st
     b->order = head.take<int>(L.size());
     b->F.word = head.take<unsigned int>(64);
     b->F.one_phase = head.take<unsigned long long>(8);
-    int *first = head.take<int>(size_t(3) * (L.size() + 1));
-    // block tables of the flattened form: first block of each instance over its gas particles,
-    // its dust particles and its cells
+    // block tables of the flattened form: (instance, block in the instance) of every block of
+    // the launches over both phases' particles (gas blocks, then dust blocks) and over the cells
     const int n = (int)L.size();
-    b->host_first.assign(size_t(3) * (n + 1), 0);
+    size_t ncell_total = 0;
+    b->host_part.clear();
     b->host_ncell.resize(n);
-    for (int i = 0; i < n; ++i) {
-        b->host_first[i + 1] = b->host_first[i] + blocks_for(L[i].ng);
-        b->host_first[(n + 1) + i + 1] = b->host_first[(n + 1) + i] + blocks_for(L[i].nd);
-        b->host_ncell[i] = L[i].ncell;
-    }
-    b->flat_blocks_g = b->host_first[n];
-    b->flat_blocks_d = b->host_first[(n + 1) + n];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < blocks_for(L[i].ng); ++j) b->host_part.push_back(make_int2(i, j));
+    b->flat_blocks_g = (int)b->host_part.size();
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < blocks_for(L[i].nd); ++j) b->host_part.push_back(make_int2(i, j));
+    b->flat_blocks_d = (int)b->host_part.size() - b->flat_blocks_g;
+    for (int i = 0; i < n; ++i) b->host_ncell[i] = L[i].ncell, ncell_total += size_t(L[i].ncell);
+    b->host_cells.assign(ncell_total, make_int2(0, 0));
+    int2 *part = head.take<int2>(b->host_part.size());
+    b->dev_cells = head.take<int2>(ncell_total);
     b->flat.n_inst = n;
-    b->flat.first_g = first;
-    b->flat.first_d = first + (n + 1);
-    b->flat.first_c = first + 2 * (n + 1);
-    b->dev_first = first;
-    HIP_TRY(hipMemcpyAsync(first, b->host_first.data(), sizeof(int) * 2 * (n + 1), hipMemcpyHostToDevice, st));
+    b->flat.blocks_g = b->flat_blocks_g;
+    b->flat.part = part;
+    b->flat.cells = b->dev_cells;
+    if (!b->host_part.empty())
+        HIP_TRY(hipMemcpyAsync(part, b->host_part.data(), sizeof(int2) * b->host_part.size(), hipMemcpyHostToDevice, st));
     tfsph_status rc = upload_flat_cells(b, st);
     if (rc != TFSPH_OK) return rc;
     // largest-first order (work ~ particles); ties by index

@@ -196,51 +196,39 @@ k_batched(const Inst<R> *__restrict__ insts, const int *__restrict__ order, int 
 // ---------------------------------------------------------------------------
 // Flattened form: one launch per phase of the step covers every instance.  The
 // blocks of a launch are dealt out per instance, so a block never straddles two
-// instances: first[i] is the first block of instance i over the launch's items
-// (gas particles, dust particles or cells, kBlock items per block) and first[n]
-// the block total.  A block finds its instance by a binary search of that table
-// (the same for every lane).  Each item calls the same device functions as the
+// instances: a table gives each block of a launch its instance and its block
+// index inside that instance's items (gas particles, dust particles or cells,
+// kBlock items per block), one 8-byte scalar load per block (a search over the
+// instances' first blocks would be a chain of dependent loads at the start of
+// every block).  Each item calls the same device functions as the
 // single-problem kernels and the persistent kernel, so every instance evolves
 // bitwise as it does through tfsph_step.  The launch time is that of the whole
 // batch's work spread over the chip, not that of its largest instance.
 // ---------------------------------------------------------------------------
 struct FlatTable {
     int n_inst;
-    const int *first_g;      // [n_inst + 1] blocks over gas particles
-    const int *first_d;      // [n_inst + 1] blocks over dust particles
-    const int *first_c;      // [n_inst + 1] blocks over cells, cells_per_block cells per block
+    int blocks_g;            // blocks over gas particles: the first blocks of a launch over both phases
+    const int2 *part;        // [blocks_g + blocks_d] (instance, block in the instance): gas, then dust
+    const int2 *cells;       // [blocks_c] the same over cells, cells_per_block cells per block
     int cells_per_block;
 };
 
-// instance of block b (first[0] = 0 <= b < first[n]): the largest i with first[i] <= b
-__device__ __forceinline__ int flat_instance(const int *__restrict__ first, int n, int b)
-{
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (first[mid] <= b) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // Item index of this thread inside its instance, for a launch over gas blocks
-// then dust blocks (gas = true for the first first_g[n] blocks).
+// then dust blocks (gas = true for the first blocks_g blocks).
 __device__ __forceinline__ int flat_item(const FlatTable &T, bool &gas, int &inst)
 {
-    const int nbg = T.first_g[T.n_inst];
-    gas = int(blockIdx.x) < nbg;
-    const int b = gas ? int(blockIdx.x) : int(blockIdx.x) - nbg;
-    const int *first = gas ? T.first_g : T.first_d;
-    inst = flat_instance(first, T.n_inst, b);
-    return (b - first[inst]) * kBlock + int(threadIdx.x);
+    const int2 e = T.part[blockIdx.x];
+    gas = int(blockIdx.x) < T.blocks_g;
+    inst = e.x;
+    return e.y * kBlock + int(threadIdx.x);
 }
 
 __device__ __forceinline__ int flat_cell_item(const FlatTable &T, int &inst)
 {
-    inst = flat_instance(T.first_c, T.n_inst, int(blockIdx.x));
+    const int2 e = T.cells[blockIdx.x];
+    inst = e.x;
     const int c = int(threadIdx.x) < T.cells_per_block ? int(threadIdx.x) : 1 << 30;
-    return (int(blockIdx.x) - T.first_c[inst]) * T.cells_per_block + c;
+    return e.y * T.cells_per_block + c;
 }
 
 // clear both histograms (the first step of a call counts from the caller's arrays)
@@ -315,18 +303,18 @@ __global__ void __launch_bounds__(kBlock) k_flat_rank_gather(const Inst<R> *__re
 template <typename R, int DIM>
 __global__ void __launch_bounds__(kBlock) k_flat_density(const Inst<R> *__restrict__ insts, FlatTable T)
 {
-    const int inst = flat_instance(T.first_g, T.n_inst, int(blockIdx.x));
-    const Inst<R> &I = insts[inst];
-    const int a = (int(blockIdx.x) - T.first_g[inst]) * kBlock + int(threadIdx.x);
+    const int2 e = T.part[blockIdx.x];
+    const Inst<R> &I = insts[e.x];
+    const int a = e.y * kBlock + int(threadIdx.x);
     if (a < I.Sg.n) density_store<R, DIM>(I.G, I.Ph, I.Sg, a, 1);
 }
 
 template <typename R, int DIM>
 __global__ void __launch_bounds__(kBlock) k_flat_predict(const Inst<R> *__restrict__ insts, FlatTable T)
 {
-    const int inst = flat_instance(T.first_g, T.n_inst, int(blockIdx.x));
-    const Inst<R> &I = insts[inst];
-    const int a = (int(blockIdx.x) - T.first_g[inst]) * kBlock + int(threadIdx.x);
+    const int2 e = T.part[blockIdx.x];
+    const Inst<R> &I = insts[e.x];
+    const int a = e.y * kBlock + int(threadIdx.x);
     if (a < I.Sg.n) gas_predict<R, DIM>(I.G, I.Ph, I.Sg, I.Pg, a);
 }
 
@@ -338,9 +326,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
 k_flat_update(const Inst<R> *__restrict__ insts, FlatTable T, Flags F)
 {
     extern __shared__ unsigned char smem_raw[];
-    const int inst = flat_instance(T.first_c, T.n_inst, int(blockIdx.x));
-    const Inst<R> &I = insts[inst];
-    const int c0 = (int(blockIdx.x) - T.first_c[inst]) * T.cells_per_block;
+    const int2 e = T.cells[blockIdx.x];
+    const Inst<R> &I = insts[e.x];
+    const int c0 = e.y * T.cells_per_block;
     const int c1 = min(c0 + T.cells_per_block, I.G.ncell);
     update_block<R, DIM, true>(I.G, I.Ph, I.Sg, I.Sd, I.Pg, I.Pd, F, c0, c1, smem_raw);
 }
