@@ -296,7 +296,8 @@ tfsph_status tfsph_batch_init(tfsph_batch **out, const tfsph_batch_desc *desc, t
 
 /* Change the launch shape (results do not depend on it).  A new cells_per_block
  * rewrites the flattened form's block table on the stream of the batch's last
- * call (or of init) and drops the flattened form's captured graphs. */
+ * call (or of init), waits for that stream, and drops the flattened form's
+ * captured graphs. */
 tfsph_status tfsph_batch_set_tuning(tfsph_batch *b, const tfsph_batch_tuning *tuning);
 
 /* Advance every instance n_steps IDIC steps: one kernel launch (persistent
