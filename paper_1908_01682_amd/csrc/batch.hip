@@ -43,7 +43,10 @@ size_t batch_bytes(const std::vector<InstLayout> &L, int dim, Carver &cv, std::v
     // block tables of the flattened form: over the particles of both phases, and over the
     // cells at one cell per block (the most blocks any cells_per_block gives)
     size_t part = 0, cells = 0;
-    for (const InstLayout &l : L) part += size_t(blocks_for(l.ng)) + blocks_for(l.nd), cells += l.ncell;
+    for (const InstLayout &l : L) {
+        part += size_t(blocks_for(l.ng)) + size_t(blocks_for(l.nd));
+        cells += size_t(l.ncell);
+    }
     int2 *tab_part = cv.take<int2>(part);
     int2 *tab_cells = cv.take<int2>(cells);
     (void)dev_table, (void)order, (void)word, (void)one, (void)tab_part, (void)tab_cells;
@@ -236,7 +239,10 @@ static tfsph_status batch_setup(tfsph_batch *b, const tfsph_batch_desc *desc, st
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < blocks_for(L[i].nd); ++j) b->host_part.push_back(make_int2(i, j));
     b->flat_blocks_d = (int)b->host_part.size() - b->flat_blocks_g;
-    for (int i = 0; i < n; ++i) b->host_ncell[i] = L[i].ncell, ncell_total += size_t(L[i].ncell);
+    for (int i = 0; i < n; ++i) {
+        b->host_ncell[i] = L[i].ncell;
+        ncell_total += size_t(L[i].ncell);
+    }
     b->host_cells.assign(ncell_total, make_int2(0, 0));
     int2 *part = head.take<int2>(b->host_part.size());
     b->dev_cells = head.take<int2>(ncell_total);
