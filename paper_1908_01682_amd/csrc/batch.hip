@@ -95,6 +95,19 @@ size_t batch_bytes(const std::vector<InstLayout> &L, int dim, Carver &cv, std::v
     return cv.off + 256;
 }
 
+// Deal the entries e[s, s + m) of a block table out so that the blocks a launch
+// sends to one XCD (block b goes to XCD b % 8, round robin) take one contiguous
+// run of entries: neighbouring blocks of an instance, which read each other's
+// halos, then share that XCD's L2.
+void xcd_deal(int2 *e, int s, int m)
+{
+    const std::vector<int2> run(e + s, e + s + m);
+    int k = 0;
+    for (int x = 0; x < 8; ++x)
+        for (int b = s; b < s + m; ++b)
+            if (b % 8 == x) e[b] = run[k++];
+}
+
 tfsph_status check_desc(const tfsph_batch_desc *desc, std::vector<InstLayout> &L, int &dim, int &prec)
 {
     if (!desc || desc->n_inst < 1) return fail(TFSPH_E_INVALID_ARG, "batch needs at least one instance");
@@ -163,6 +176,7 @@ static tfsph_status upload_flat_cells(tfsph_batch *b, hipStream_t st)
         const int nb = (b->host_ncell[i] + b->flat_cpb - 1) / b->flat_cpb;
         for (int j = 0; j < nb; ++j) b->host_cells[k++] = make_int2(i, j);
     }
+    xcd_deal(b->host_cells.data(), 0, k);
     b->flat_blocks_c = k;
     b->flat.cells_per_block = b->flat_cpb;
     for (auto it = b->graphs.begin(); it != b->graphs.end();) {
@@ -239,6 +253,8 @@ static tfsph_status batch_setup(tfsph_batch *b, const tfsph_batch_desc *desc, st
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < blocks_for(L[i].nd); ++j) b->host_part.push_back(make_int2(i, j));
     b->flat_blocks_d = (int)b->host_part.size() - b->flat_blocks_g;
+    xcd_deal(b->host_part.data(), 0, b->flat_blocks_g);
+    xcd_deal(b->host_part.data(), b->flat_blocks_g, b->flat_blocks_d);
     for (int i = 0; i < n; ++i) {
         b->host_ncell[i] = L[i].ncell;
         ncell_total += size_t(L[i].ncell);
