@@ -142,6 +142,7 @@ tfsph_status check_desc(const tfsph_batch_desc *desc, std::vector<InstLayout> &L
 struct tfsph_batch {
     int n_inst = 0, dim = 1, prec = 0, block = kDefaultBatchBlock, form = TFSPH_BATCH_PERSISTENT;
     int flat_cpb = 0;              // cells per block of the flattened form's update launch
+    int flat_kind = -1;            // force-loop kind of every instance (kForce*), -1 if they differ
     FlatTable flat{};
     int flat_blocks_g = 0, flat_blocks_d = 0, flat_blocks_c = 0;
     std::vector<int> host_ncell;   // cells of each instance
@@ -276,6 +277,14 @@ static tfsph_status batch_setup(tfsph_batch *b, const tfsph_batch_desc *desc, st
     std::stable_sort(b->host_order.begin(), b->host_order.end(), [&L](int x, int y) {
         return (long long)L[x].ng + L[x].nd > (long long)L[y].ng + L[y].nd;
     });
+    // the force-loop kind each instance runs (the rule of force_kind()): one shared kind lets
+    // the flattened force launch be specialised on it
+    int kind = -2;
+    for (const Inst<R> &I : table) {
+        const int k = (I.Ph.av || I.Ph.eos != 0) ? kForceGeneral : (I.Sg.has_mass ? kForceIsoMass : kForceIsoUniform);
+        kind = (kind == -2 || kind == k) ? k : -1;
+    }
+    b->flat_kind = kind < 0 ? -1 : kind;
     b->host_table.resize(sizeof(Inst<R>) * table.size());
     std::copy(reinterpret_cast<const char *>(table.data()), reinterpret_cast<const char *>(table.data()) + b->host_table.size(),
               b->host_table.begin());
@@ -381,7 +390,14 @@ static tfsph_status launch_flat_t(tfsph_batch *b, int n_steps, hipStream_t st)
         }
         if (gg.x) {
             hipLaunchKernelGGL((k_flat_density<R, DIM>), gg, blk, 0, st, t, T);
-            hipLaunchKernelGGL((k_flat_predict<R, DIM>), gg, blk, 0, st, t, T);
+            switch (b->flat_kind) {
+            case kForceIsoUniform:
+                hipLaunchKernelGGL((k_flat_predict<R, DIM, kForceIsoUniform>), gg, blk, 0, st, t, T);
+                break;
+            case kForceIsoMass: hipLaunchKernelGGL((k_flat_predict<R, DIM, kForceIsoMass>), gg, blk, 0, st, t, T); break;
+            case kForceGeneral: hipLaunchKernelGGL((k_flat_predict<R, DIM, kForceGeneral>), gg, blk, 0, st, t, T); break;
+            default: hipLaunchKernelGGL((k_flat_predict<R, DIM, -1>), gg, blk, 0, st, t, T); break;
+            }
         }
         if (gc.x) hipLaunchKernelGGL((k_flat_update<R, DIM>), gc, blk, lds, st, t, T, b->F);
         LAUNCH_CHECK("flat_step");

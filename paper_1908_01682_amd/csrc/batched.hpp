@@ -309,13 +309,18 @@ __global__ void __launch_bounds__(kBlock) k_flat_density(const Inst<R> *__restri
     if (a < I.Sg.n) density_store<R, DIM>(I.G, I.Ph, I.Sg, a, 1);
 }
 
-template <typename R, int DIM>
+// KIND: the force-loop kind (kForce*) when every instance has the same one, so
+// the kernel holds the registers of that loop only (in 1D the isothermal loops
+// need 64 VGPRs against about 100 for the general one); -1 picks each
+// instance's kind at run time.  Either way an instance runs the loop that
+// tfsph_step runs for it.
+template <typename R, int DIM, int KIND>
 __global__ void __launch_bounds__(kBlock) k_flat_predict(const Inst<R> *__restrict__ insts, FlatTable T)
 {
     const int2 e = T.part[blockIdx.x];
     const Inst<R> &I = insts[e.x];
     const int a = e.y * kBlock + int(threadIdx.x);
-    if (a < I.Sg.n) gas_predict<R, DIM>(I.G, I.Ph, I.Sg, I.Pg, a);
+    if (a < I.Sg.n) gas_predict<R, DIM, KIND>(I.G, I.Ph, I.Sg, I.Pg, a);
 }
 
 // cell sums, implicit solve, particle update, move and carry of a run of

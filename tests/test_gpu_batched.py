@@ -84,6 +84,40 @@ def test_batched_equals_plain_bitwise(dim, precision, kmode, form):
     assert not (flags & T.TFSPH_FLAG_NONFINITE)
 
 
+def _batch_1d_viscous(all_viscous):
+    """Instances with artificial viscosity (the general force loop), on every instance or on
+    every other one next to the isothermal loop without viscosity."""
+    probs = I.batched_waves(n_inst=5, n_min=600, n_max=2500, seed=31, amp=1e-2)
+    for i, p in enumerate(probs):
+        if all_viscous or i % 2 == 0:
+            p.params = p.params.replace(av_alpha=1.0, av_beta=2.0)
+    return probs
+
+
+@pytest.mark.parametrize("form", ["persistent", "flat"])
+@pytest.mark.parametrize("all_viscous", [True, False], ids=["all_viscous", "mixed"])
+def test_batched_force_kinds_equal_plain_bitwise(all_viscous, form):
+    """The flattened force launch is specialised on a force loop that every instance shares
+    and picks each instance's loop at run time otherwise: either way every instance equals
+    tfsph_step on it alone, bitwise."""
+    probs = _batch_1d_viscous(all_viscous)
+    banner(f"batched force kinds all_viscous={all_viscous} form={form}")
+    bs = T.BatchedSimulation(probs, precision=0, form=FORMS[form])
+    bs.step(12)
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        sim = T.Simulation(p, precision=0)
+        sim.step(12)
+        torch.cuda.synchronize()
+        g, d = bs.instance(i)
+        _same(g, sim.gas.numpy())
+        _same(d, sim.dust.numpy())
+        sim.close()
+    flags, _ = bs.flags()
+    bs.close()
+    assert not (flags & T.TFSPH_FLAG_NONFINITE)
+
+
 def test_batched_matches_oracle(orc):
     probs = _batch_1d(seed=5, n_inst=3)
     bs = T.BatchedSimulation(probs, precision=0)
