@@ -149,8 +149,7 @@ __device__ __forceinline__ void batched_step(const Inst<R> &I, int *lds, unsigne
         const int a = base + tid;
         int key = -1;
         if (a < ng) {
-            bad |= !gas_finish<R, DIM>(G, I.Ph, I.Sg, I.Pg, a, I.cs[I.Sg.cell[a]], s2);
-            key = I.Pg.cell[a];
+            bad |= !gas_finish<R, DIM>(G, I.Ph, I.Sg, I.Pg, a, I.cs[I.Sg.cell[a]], s2, nullptr, &key);
         }
         const int sl = claim_slot(I.Sg.count, key);
         if (a < ng) I.Sg.slot[a] = sl;
@@ -159,8 +158,7 @@ __device__ __forceinline__ void batched_step(const Inst<R> &I, int *lds, unsigne
         const int j = base + tid;
         int key = -1;
         if (j < nd) {
-            bad |= !dust_finish<R, DIM>(G, I.Ph, I.Sd, I.Pd, j, I.cs[I.Sd.cell[j]], s2);
-            key = I.Pd.cell[j];
+            bad |= !dust_finish<R, DIM>(G, I.Ph, I.Sd, I.Pd, j, I.cs[I.Sd.cell[j]], s2, nullptr, &key);
         }
         const int sl = claim_slot(I.Sd.count, key);
         if (j < nd) I.Sd.slot[j] = sl;

@@ -737,11 +737,12 @@ __device__ __forceinline__ void gas_predict(const Geom<R> &G, const Phys<R> &Ph,
 }
 
 // Implicit update of eq. (19) for gas particle a of cell C, then
-// x^{n+1} = x^n + tau v^{n+1} and the carry; writes the caller's arrays at a.
+// x^{n+1} = x^n + tau v^{n+1} and the carry; writes the caller's arrays at a
+// (and the new cell to *new_cell when given).
 template <typename R, int DIM>
 __device__ __forceinline__ bool gas_finish(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg,
                                            const Phase<R> &Pg, int a, const CellSolve<R> &C, R &s2,
-                                           const R4<R> *staged = nullptr)
+                                           const R4<R> *staged = nullptr, int *new_cell = nullptr)
 {
     const int c = Sg.cell[a];
     const R inv = R(1) / (R(1) + C.alpha);
@@ -774,18 +775,21 @@ __device__ __forceinline__ bool gas_finish(const Geom<R> &G, const Phys<R> &Ph, 
     // signal speed of eq. (4): max(|v|, c), with the sound speed of the new energy
     s2 = fmax(s2, v2);
     if (Ph.eos != 0 && Sg.energy) s2 = fmax(s2, Ph.ggm1 * Pg.energy[a]);
-    Pg.cell[a] = join_cell(G, cc[0], cc[1], cc[2]);
+    const int cn = join_cell(G, cc[0], cc[1], cc[2]);
+    Pg.cell[a] = cn;
+    if (new_cell) *new_cell = cn;
     Pg.id[a] = Sg.id[a];
     if (Sg.has_mass && Pg.mass) const_cast<R *>(Pg.mass)[a] = me.w;
     Pg.rho[a] = Sg.rho[a];
     return ok;
 }
 
-// Implicit update of eq. (20) for dust particle j of cell C, then move + carry.
+// Implicit update of eq. (20) for dust particle j of cell C, then move + carry
+// (the new cell also to *new_cell when given).
 template <typename R, int DIM>
 __device__ __forceinline__ bool dust_finish(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sd,
                                             const Phase<R> &Pd, int j, const CellSolve<R> &C, R &s2,
-                                            const R4<R> *staged = nullptr)
+                                            const R4<R> *staged = nullptr, int *new_cell = nullptr)
 {
     const int c = Sd.cell[j];
     const R inv = R(1) / (R(1) + C.beta);
@@ -817,7 +821,9 @@ __device__ __forceinline__ bool dust_finish(const Geom<R> &G, const Phys<R> &Ph,
         u2 += u * u;
     }
     s2 = fmax(s2, u2);
-    Pd.cell[j] = join_cell(G, cc[0], cc[1], cc[2]);
+    const int cn = join_cell(G, cc[0], cc[1], cc[2]);
+    Pd.cell[j] = cn;
+    if (new_cell) *new_cell = cn;
     Pd.id[j] = Sd.id[j];
     if (Sd.has_mass && Pd.mass) const_cast<R *>(Pd.mass)[j] = me.w;
     return ok;
@@ -957,8 +963,8 @@ __device__ __forceinline__ void update_block(const Geom<R> &G, const Phys<R> &Ph
             const int a = base + threadIdx.x;
             int key = -1;
             if (a < gb) {
-                bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0], s2, staged ? &stg[a - ga] : nullptr);
-                key = Pg.cell[a];
+                bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0], s2, staged ? &stg[a - ga] : nullptr,
+                                           &key);
             }
             const int sl = claim_slot(Sg.count, key);
             if (a < gb) Sg.slot[a] = sl;
@@ -967,8 +973,8 @@ __device__ __forceinline__ void update_block(const Geom<R> &G, const Phys<R> &Ph
             const int j = base + threadIdx.x;
             int key = -1;
             if (j < db) {
-                bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[Sd.cell[j] - c0], s2, staged ? &std_[j - da] : nullptr);
-                key = Pd.cell[j];
+                bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[Sd.cell[j] - c0], s2, staged ? &std_[j - da] : nullptr,
+                                            &key);
             }
             const int sl = claim_slot(Sd.count, key);
             if (j < db) Sd.slot[j] = sl;
