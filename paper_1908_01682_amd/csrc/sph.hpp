@@ -958,26 +958,22 @@ __device__ __forceinline__ void update_block(const Geom<R> &G, const Phys<R> &Ph
     int bad = 0;
     R s2 = signal_floor(Ph);
     if constexpr (CLAIM) {
-        // every lane of a wave takes part in each claim (wave shuffles)
-        for (int base = ga; base < gb; base += kBlock) {
-            const int a = base + threadIdx.x;
-            int key = -1;
-            if (a < gb) {
-                bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0], s2, staged ? &stg[a - ga] : nullptr,
-                                           &key);
-            }
-            const int sl = claim_slot(Sg.count, key);
-            if (a < gb) Sg.slot[a] = sl;
-        }
-        for (int base = da; base < db; base += kBlock) {
-            const int j = base + threadIdx.x;
-            int key = -1;
-            if (j < db) {
-                bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[Sd.cell[j] - c0], s2, staged ? &std_[j - da] : nullptr,
-                                            &key);
-            }
-            const int sl = claim_slot(Sd.count, key);
-            if (j < db) Sd.slot[j] = sl;
+        // every lane of a wave takes part in each claim (wave shuffles); the gas and the dust
+        // particle of a thread claim together, so the two atomics are in flight at once
+        const int ng = gb - ga, nd = db - da;
+        for (int base = 0; base < max(ng, nd); base += kBlock) {
+            const int i = base + threadIdx.x;
+            int kg = -1, kd = -1;
+            if (i < ng)
+                bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, ga + i, cs[Sg.cell[ga + i] - c0], s2,
+                                           staged ? &stg[i] : nullptr, &kg);
+            if (i < nd)
+                bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, da + i, cs[Sd.cell[da + i] - c0], s2,
+                                            staged ? &std_[i] : nullptr, &kd);
+            const int sg = claim_slot(Sg.count, kg);
+            const int sd = claim_slot(Sd.count, kd);
+            if (i < ng) Sg.slot[ga + i] = sg;
+            if (i < nd) Sd.slot[da + i] = sd;
         }
     } else {
         for (int a = ga + threadIdx.x; a < gb; a += kBlock)
