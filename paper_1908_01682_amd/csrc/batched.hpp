@@ -55,15 +55,17 @@ __device__ __forceinline__ int block_scan_any(int v, int *lds_waves, int &total)
 // start[c] = sum of count[0..c), start[ncell] = total, for one instance: each
 // thread sums a contiguous run of cells, one block scan combines the runs.
 // The run's counts are loaded kRunLoad at a time with every load issued before
-// the sum uses it, so a run costs a few memory latencies, not one per cell.
+// the sum uses it, so a run costs a few memory latencies, not one per cell; a
+// run of at most kRunLoad cells keeps its counts in registers for the second
+// pass.
 constexpr int kRunLoad = 16;
 __device__ __forceinline__ void block_scan_cells(const int *count, int *start, int ncell, int *lds)
 {
     const int per = (ncell + blockDim.x - 1) / blockDim.x;
     const int c0 = min(int(threadIdx.x) * per, ncell), c1 = min(c0 + per, ncell);
+    int v[kRunLoad];
     int s = 0;
     for (int c = c0; c < c1; c += kRunLoad) {
-        int v[kRunLoad];
 #pragma unroll
         for (int u = 0; u < kRunLoad; ++u) v[u] = c + u < c1 ? count[c + u] : 0;
 #pragma unroll
@@ -71,10 +73,12 @@ __device__ __forceinline__ void block_scan_cells(const int *count, int *start, i
     }
     int total;
     int ex = block_scan_any(s, lds, total);
+    const bool held = per <= kRunLoad;     // v[] still holds the run's counts
     for (int c = c0; c < c1; c += kRunLoad) {
-        int v[kRunLoad];
+        if (!held) {
 #pragma unroll
-        for (int u = 0; u < kRunLoad; ++u) v[u] = c + u < c1 ? count[c + u] : 0;
+            for (int u = 0; u < kRunLoad; ++u) v[u] = c + u < c1 ? count[c + u] : 0;
+        }
 #pragma unroll
         for (int u = 0; u < kRunLoad; ++u) {
             if (c + u < c1) start[c + u] = ex;
