@@ -261,18 +261,55 @@ __global__ void __launch_bounds__(kBlock) k_flat_count(const Inst<R> *__restrict
     if (i < S.n) S.slot[i] = sl;
 }
 
-// exclusive scan of each instance's histograms, one block per instance and phase;
-// the counts are cleared once consumed
+// exclusive scan of each instance's histograms, one block per instance and phase,
+// in tiles of kFlatScanPer cells per thread staged in LDS: the counts are read (and
+// cleared) and the offsets written with coalesced accesses, each thread sums a run
+// of kFlatScanPer cells of the tile, and a running prefix carries over the tiles
+constexpr int kFlatScanPer = 8;
 template <typename R>
 __global__ void __launch_bounds__(kBatchMaxBlock) k_flat_scan(const Inst<R> *__restrict__ insts)
 {
     __shared__ int lds[kBatchMaxBlock / 64];
+    __shared__ int tile[kBatchMaxBlock * kFlatScanPer];
     const Inst<R> &I = insts[blockIdx.x >> 1];
     const Sorted<R> &S = (blockIdx.x & 1) ? I.Sd : I.Sg;
     const int ncell = I.G.ncell;
-    block_scan_cells(S.count, S.start, ncell, lds);
-    __syncthreads();
-    for (int c = threadIdx.x; c < ncell; c += blockDim.x) S.count[c] = 0;
+    const int t = int(threadIdx.x);
+    constexpr int kTile = kBatchMaxBlock * kFlatScanPer;
+    int prefix = 0;
+    for (int base = 0; base < ncell; base += kTile) {
+#pragma unroll
+        for (int k = 0; k < kFlatScanPer; ++k) {
+            const int c = base + k * kBatchMaxBlock + t;
+            int v = 0;
+            if (c < ncell) {
+                v = S.count[c];
+                S.count[c] = 0;     // consumed: zero for the next step's claims
+            }
+            tile[k * kBatchMaxBlock + t] = v;
+        }
+        __syncthreads();
+        int loc[kFlatScanPer];
+        int run = 0;
+#pragma unroll
+        for (int k = 0; k < kFlatScanPer; ++k) {
+            loc[k] = run;
+            run += tile[t * kFlatScanPer + k];
+        }
+        int total;
+        const int ex = block_scan_any(run, lds, total) + prefix;
+#pragma unroll
+        for (int k = 0; k < kFlatScanPer; ++k) tile[t * kFlatScanPer + k] = ex + loc[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kFlatScanPer; ++k) {
+            const int c = base + k * kBatchMaxBlock + t;
+            if (c < ncell) S.start[c] = tile[k * kBatchMaxBlock + t];
+        }
+        prefix += total;
+        __syncthreads();        // the next tile overwrites tile[]
+    }
+    if (t == 0) S.start[ncell] = prefix;
 }
 
 template <typename R>
