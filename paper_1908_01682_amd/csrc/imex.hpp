@@ -53,17 +53,22 @@ k_imex_gas1(Geom<R> G, Phys<R> Ph, Sorted<R> S, Stage<R> X, Phase<R> Q, ImexCoef
 {
     const int a = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (a >= S.n) return;
+    // the particle's own fields are loaded before the neighbour walk, which hides their latency
+    const int c0 = S.cell[a], id = S.id[a];
+    const R4<R> me = S.pos[a];
+    R v0[3];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) v0[d] = S.vel[d][a];
     R acc[3], dedt;
     gas_force_at<R, DIM, KIND>(G, Ph, S, a, acc, dedt);
     int cc[3];
-    split_cell(G, S.cell[a], cc[0], cc[1], cc[2]);
-    const R4<R> me = S.pos[a];
+    split_cell(G, c0, cc[0], cc[1], cc[2]);
     const R oo[3] = {me.x, me.y, me.z};
     bool ok = true;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         const R A = acc[d] + Ph.g[d];
-        const R v = S.vel[d][a];
+        const R v = v0[d];
         R o = oo[d] + C.gtau * v;
         ok &= finite_r(A);
         ok &= carry(o, cc[d], G.delta[d], G.nc[d]);
@@ -72,7 +77,7 @@ k_imex_gas1(Geom<R> G, Phys<R> Ph, Sorted<R> S, Stage<R> X, Phase<R> Q, ImexCoef
         Q.vel[d][a] = v + C.gtau * A;
     }
     Q.cell[a] = join_cell(G, cc[0], cc[1], cc[2]);
-    Q.id[a] = S.id[a];
+    Q.id[a] = id;
     if (Q.mass) const_cast<R *>(Q.mass)[a] = me.w;
     if (S.energy) {
         X.de1[a] = dedt;
@@ -115,9 +120,9 @@ k_imex_gas2(Geom<R> G, Phys<R> Ph, Sorted<R> S, Stage<R> X, Flags F)
 {
     const int a = xcd_block(gridDim.x) * kBlock + threadIdx.x;
     if (a >= S.n) return;
+    const int i = S.src[a];       // loaded before the neighbour walk, which hides its latency
     R acc[3], dedt;
     gas_force_at<R, DIM, KIND>(G, Ph, S, a, acc, dedt);
-    const int i = S.src[a];
     bool ok = true;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {

@@ -387,14 +387,17 @@ __device__ __forceinline__ R sound_of(const Phys<R> &Ph, R e)
 
 // --------------------------------------------------------------------------
 // Summation density of phase S at its own sorted particle a.  With `record`
-// (gas, masks allocated) the neighbour mask rows of a are stored as well.
+// (gas, masks allocated) the neighbour mask rows of a are stored as well; with
+// `own` a's record is returned there (it stays in registers for the caller).
 // --------------------------------------------------------------------------
 template <typename R, int DIM>
-__device__ __forceinline__ R density_at(const Geom<R> &G, const Sorted<R> &S, int a, bool record = false)
+__device__ __forceinline__ R density_at(const Geom<R> &G, const Sorted<R> &S, int a, bool record = false,
+                                        R4<R> *own = nullptr)
 {
     int cx, cy, cz;
     split_cell(G, S.cell[a], cx, cy, cz);
     const R4<R> me = S.pos[a];
+    if (own) *own = me;
     const R oa[3] = {me.x, me.y, me.z};
     R acc = R(0);
     auto term = [&](int, const R4<R> &q, R rx, R ry, R rz, bool ok) {
@@ -417,11 +420,11 @@ template <typename R, int DIM>
 __device__ __forceinline__ void density_store(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &S, int a,
                                               int want_frc)
 {
-    const R rho = density_at<R, DIM>(G, S, a, want_frc != 0);
+    R4<R> me;
+    const R rho = density_at<R, DIM>(G, S, a, want_frc != 0, &me);
     S.rho[a] = rho;
     if (want_frc) {
         const R e = S.energy ? S.energy[a] : R(0);
-        const R4<R> me = S.pos[a];
         S.frc[a] = mk4<R>(me.x, me.y, me.z, pressure_of(Ph, rho, e) / (rho * rho));
     }
 }
@@ -726,13 +729,17 @@ template <typename R, int DIM, int KIND = -1>
 __device__ __forceinline__ void gas_predict(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg,
                                             const Phase<R> &Pg, int a)
 {
+    // the particle's own velocity is loaded before the neighbour walk, which hides its latency
+    R v0[3];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) v0[d] = Sg.vel[d][a];
     R acc[3], dedt;
     if constexpr (KIND < 0)
         gas_force_any<R, DIM>(G, Ph, Sg, a, acc, dedt);
     else
         gas_force_at<R, DIM, KIND>(G, Ph, Sg, a, acc, dedt);
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) Sg.vt[d][a] = Sg.vel[d][a] + Ph.tau * (acc[d] + Ph.g[d]);
+    for (int d = 0; d < DIM; ++d) Sg.vt[d][a] = v0[d] + Ph.tau * (acc[d] + Ph.g[d]);
     if (Sg.energy) Pg.energy[a] = Sg.energy[a] + Ph.tau * dedt;
 }
 
