@@ -69,12 +69,12 @@ __device__ __forceinline__ R spline_df(R q)
 #define TFSPH_STAGE_OCCUPANCY(R, KIND) TFSPH_DENSITY_OCCUPANCY(R)
 #else
 // Waves per SIMD of the FP32 density pass on the 3D box, against the
-// compiler's choice: at 7 (72 VGPRs, a 20-byte spill) it takes 0.336 ms
+// compiler's choice: at 7 (72 VGPRs, 12 bytes spilled per lane) it takes 0.336 ms
 // against 0.345 at 6 (79 VGPRs).  FP64 would spill heavily, so it keeps the
 // compiler's choice.
 #define TFSPH_DENSITY_OCCUPANCY(R) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 7 : 1)))
-// The force passes sum FP64 terms (118 VGPRs, 4 waves per SIMD): the compiler's
-// choice.  On the 3D box the isothermal pass takes 0.285 ms; held to 5 waves, or
+// The force passes sum FP64 terms (120 VGPRs, 4 waves per SIMD): the compiler's
+// choice.  On the 3D box the isothermal pass takes 0.276 ms; held to 5 waves, or
 // walking 1 or 3 neighbours per step, it is slower.
 #ifndef TFSPH_FORCE_WAVES
 #define TFSPH_FORCE_WAVES 1
