@@ -228,6 +228,14 @@ __device__ __forceinline__ void rank_gather_one(const Geom<R> &G, const Phase<R>
     const int i = S.tmp_idx[j];
     const int myid = S.tmp_id[j];
     const int c = safe_cell(P.cell[i], G.ncell);
+    // the fields to gather depend on i alone: their loads go out before the rank loop
+    R o[3] = {R(0), R(0), R(0)}, v[3] = {R(0), R(0), R(0)};
+    for (int d = 0; d < G.dim; ++d) {
+        o[d] = P.off[d][i];
+        v[d] = P.vel[d][i];
+    }
+    const R m = P.mass ? P.mass[i] : P.m_uniform;
+    const R en = S.energy ? P.energy[i] : R(0);
     const int b = S.start[c];
     const int e = S.start[c + 1];
     int rank = 0;
@@ -247,13 +255,9 @@ __device__ __forceinline__ void rank_gather_one(const Geom<R> &G, const Phase<R>
     if (S.src) S.src[dst] = i;
     S.cell[dst] = c;
     S.id[dst] = myid;
-    R o[3] = {R(0), R(0), R(0)};
-    for (int d = 0; d < G.dim; ++d) {
-        o[d] = P.off[d][i];
-        S.vel[d][dst] = P.vel[d][i];
-    }
-    S.pos[dst] = mk4<R>(o[0], o[1], o[2], P.mass ? P.mass[i] : P.m_uniform);
-    if (S.energy) S.energy[dst] = P.energy[i];
+    for (int d = 0; d < G.dim; ++d) S.vel[d][dst] = v[d];
+    S.pos[dst] = mk4<R>(o[0], o[1], o[2], m);
+    if (S.energy) S.energy[dst] = en;
     if (j == 0) {
         // the pair loops read up to kPad records past the end: keep them finite
         for (int k = 0; k < kPad; ++k) {
