@@ -743,19 +743,36 @@ __device__ __forceinline__ void gas_predict(const Geom<R> &G, const Phys<R> &Ph,
     if (Sg.energy) Pg.energy[a] = Sg.energy[a] + Ph.tau * dedt;
 }
 
+// A sorted particle's own fields that the finish functions read, loaded ahead
+// of the cell sums by the update kernels so that their latency hides there.
+template <typename R>
+struct Own {
+    int cell, id;
+    R4<R> pos;
+    R rho;
+};
+
+template <typename R>
+__device__ __forceinline__ Own<R> own_of(const Sorted<R> &S, int a, bool with_rho)
+{
+    return Own<R>{S.cell[a], S.id[a], S.pos[a], with_rho ? S.rho[a] : R(0)};
+}
+
 // Implicit update of eq. (19) for gas particle a of cell C, then
 // x^{n+1} = x^n + tau v^{n+1} and the carry; writes the caller's arrays at a
-// (and the new cell to *new_cell when given).
+// (and the new cell to *new_cell when given).  With use_own, `own` holds a's
+// fields already loaded.
 template <typename R, int DIM>
 __device__ __forceinline__ bool gas_finish(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sg,
                                            const Phase<R> &Pg, int a, const CellSolve<R> &C, R &s2,
-                                           const R4<R> *staged = nullptr, int *new_cell = nullptr)
+                                           const R4<R> *staged = nullptr, int *new_cell = nullptr,
+                                           bool use_own = false, const Own<R> &own = Own<R>{})
 {
-    const int c = Sg.cell[a];
+    const int c = use_own ? own.cell : Sg.cell[a];
     const R inv = R(1) / (R(1) + C.alpha);
     int cc[3];
     split_cell(G, c, cc[0], cc[1], cc[2]);
-    const R4<R> me = Sg.pos[a];
+    const R4<R> me = use_own ? own.pos : Sg.pos[a];
     const R oo[3] = {me.x, me.y, me.z};
     bool ok = true;
     // v~ from the block's LDS copy when it has one: (m, v~x, v~y, v~z)
@@ -785,24 +802,25 @@ __device__ __forceinline__ bool gas_finish(const Geom<R> &G, const Phys<R> &Ph, 
     const int cn = join_cell(G, cc[0], cc[1], cc[2]);
     Pg.cell[a] = cn;
     if (new_cell) *new_cell = cn;
-    Pg.id[a] = Sg.id[a];
+    Pg.id[a] = use_own ? own.id : Sg.id[a];
     if (Sg.has_mass && Pg.mass) const_cast<R *>(Pg.mass)[a] = me.w;
-    Pg.rho[a] = Sg.rho[a];
+    Pg.rho[a] = use_own ? own.rho : Sg.rho[a];
     return ok;
 }
 
 // Implicit update of eq. (20) for dust particle j of cell C, then move + carry
-// (the new cell also to *new_cell when given).
+// (the new cell also to *new_cell when given; use_own and `own` as for gas_finish()).
 template <typename R, int DIM>
 __device__ __forceinline__ bool dust_finish(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &Sd,
                                             const Phase<R> &Pd, int j, const CellSolve<R> &C, R &s2,
-                                            const R4<R> *staged = nullptr, int *new_cell = nullptr)
+                                            const R4<R> *staged = nullptr, int *new_cell = nullptr,
+                                            bool use_own = false, const Own<R> &own = Own<R>{})
 {
-    const int c = Sd.cell[j];
+    const int c = use_own ? own.cell : Sd.cell[j];
     const R inv = R(1) / (R(1) + C.beta);
     int cc[3];
     split_cell(G, c, cc[0], cc[1], cc[2]);
-    const R4<R> me = Sd.pos[j];
+    const R4<R> me = use_own ? own.pos : Sd.pos[j];
     const R oo[3] = {me.x, me.y, me.z};
     bool ok = true;
     // u from the block's LDS copy when it has one: (m, ux, uy, uz)
@@ -831,7 +849,7 @@ __device__ __forceinline__ bool dust_finish(const Geom<R> &G, const Phys<R> &Ph,
     const int cn = join_cell(G, cc[0], cc[1], cc[2]);
     Pd.cell[j] = cn;
     if (new_cell) *new_cell = cn;
-    Pd.id[j] = Sd.id[j];
+    Pd.id[j] = use_own ? own.id : Sd.id[j];
     if (Sd.has_mass && Pd.mass) const_cast<R *>(Pd.mass)[j] = me.w;
     return ok;
 }
@@ -929,6 +947,12 @@ __device__ __forceinline__ void update_block(const Geom<R> &G, const Phys<R> &Ph
             std_[i] = mk4<R>(Sd.pos[j].w, Sd.vel[0][j], DIM > 1 ? Sd.vel[1][j] : R(0), DIM > 2 ? Sd.vel[2][j] : R(0));
         }
     }
+    // the first gas and dust particle of each thread in (2): their fields are loaded now, so
+    // that the cell sums hide the latency
+    const int a0 = ga + int(threadIdx.x), j0 = da + int(threadIdx.x);
+    Own<R> og{}, od{};
+    if (a0 < gb) og = own_of(Sg, a0, true);
+    if (j0 < db) od = own_of(Sd, j0, false);
     __syncthreads();
 
     // (1) per-cell sums in canonical order and the implicit solve
@@ -971,22 +995,35 @@ __device__ __forceinline__ void update_block(const Geom<R> &G, const Phys<R> &Ph
         for (int base = 0; base < max(ng, nd); base += kBlock) {
             const int i = base + threadIdx.x;
             int kg = -1, kd = -1;
-            if (i < ng)
-                bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, ga + i, cs[Sg.cell[ga + i] - c0], s2,
-                                           staged ? &stg[i] : nullptr, &kg);
-            if (i < nd)
-                bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, da + i, cs[Sd.cell[da + i] - c0], s2,
-                                            staged ? &std_[i] : nullptr, &kd);
+            const bool first = base == 0;
+            if (i < ng) {
+                const int cg = first ? og.cell : Sg.cell[ga + i];
+                bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, ga + i, cs[cg - c0], s2, staged ? &stg[i] : nullptr,
+                                           &kg, first, og);
+            }
+            if (i < nd) {
+                const int cd = first ? od.cell : Sd.cell[da + i];
+                bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, da + i, cs[cd - c0], s2, staged ? &std_[i] : nullptr,
+                                            &kd, first, od);
+            }
             const int sg = claim_slot(Sg.count, kg);
             const int sd = claim_slot(Sd.count, kd);
             if (i < ng) Sg.slot[ga + i] = sg;
             if (i < nd) Sd.slot[da + i] = sd;
         }
     } else {
-        for (int a = ga + threadIdx.x; a < gb; a += kBlock)
-            bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[Sg.cell[a] - c0], s2, staged ? &stg[a - ga] : nullptr);
-        for (int j = da + threadIdx.x; j < db; j += kBlock)
-            bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[Sd.cell[j] - c0], s2, staged ? &std_[j - da] : nullptr);
+        for (int a = a0; a < gb; a += kBlock) {
+            const bool first = a == a0;
+            const int cg = first ? og.cell : Sg.cell[a];
+            bad |= !gas_finish<R, DIM>(G, Ph, Sg, Pg, a, cs[cg - c0], s2, staged ? &stg[a - ga] : nullptr, nullptr,
+                                       first, og);
+        }
+        for (int j = j0; j < db; j += kBlock) {
+            const bool first = j == j0;
+            const int cd = first ? od.cell : Sd.cell[j];
+            bad |= !dust_finish<R, DIM>(G, Ph, Sd, Pd, j, cs[cd - c0], s2, staged ? &std_[j - da] : nullptr, nullptr,
+                                        first, od);
+        }
     }
     publish_speed(Ph, F, s2);
     if (bad) atomicOr(&s_bad, 1);
