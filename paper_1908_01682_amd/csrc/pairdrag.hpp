@@ -122,14 +122,16 @@ __device__ __forceinline__ R drag_over_rhos(const Phys<R> &Ph, R inv_rho_g, R in
     return Ph.inv_tstop * inv_rho_g;
 }
 
-// x^{n+1} = x^n + tau v^{n+1}, carry, and the caller's arrays at sorted index i
+// x^{n+1} = x^n + tau v^{n+1}, carry, and the caller's arrays at sorted index i,
+// from the particle's own cell, id, record and density that the kernel loaded
+// before its walk (a load here would hold the wave for a memory latency)
 template <typename R, int DIM>
-__device__ __forceinline__ bool store_moved(const Geom<R> &G, const Phys<R> &Ph, const Sorted<R> &S,
-                                            const Phase<R> &P, int i, const R v[3], R &s2)
+__device__ __forceinline__ bool store_moved(const Geom<R> &G, const Phys<R> &Ph, const Phase<R> &P, int i,
+                                            int cell, int id, const R4<R> &me, R rho, const R v[3], R &s2,
+                                            bool has_mass)
 {
     int cc[3];
-    split_cell(G, S.cell[i], cc[0], cc[1], cc[2]);
-    const R4<R> me = S.pos[i];
+    split_cell(G, cell, cc[0], cc[1], cc[2]);
     const R oo[3] = {me.x, me.y, me.z};
     bool ok = true;
     R v2 = R(0);
@@ -144,9 +146,9 @@ __device__ __forceinline__ bool store_moved(const Geom<R> &G, const Phys<R> &Ph,
     }
     s2 = fmax(s2, v2);
     P.cell[i] = join_cell(G, cc[0], cc[1], cc[2]);
-    P.id[i] = S.id[i];
-    if (S.has_mass && P.mass) const_cast<R *>(P.mass)[i] = me.w;
-    if (P.rho) P.rho[i] = S.rho[i];
+    P.id[i] = id;
+    if (has_mass && P.mass) const_cast<R *>(P.mass)[i] = me.w;
+    if (P.rho) P.rho[i] = rho;
     return ok;
 }
 
@@ -163,8 +165,9 @@ k_pair_gas(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, const R4<R> *__res
     int bad = 0, lonely = 0;
     if (a < Sg.n) {
         const R vt[3] = {Sg.vt[0][a], DIM > 1 ? Sg.vt[1][a] : R(0), DIM > 2 ? Sg.vt[2][a] : R(0)};
+        const int cell = Sg.cell[a], id = Sg.id[a];
         int cx, cy, cz;
-        split_cell(G, Sg.cell[a], cx, cy, cz);
+        split_cell(G, cell, cx, cy, cz);
         const R4<R> me = Sg.pos[a];
         const R oa[3] = {me.x, me.y, me.z};
         const R rho_a = Sg.rho[a];
@@ -223,7 +226,7 @@ k_pair_gas(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, const R4<R> *__res
             }
         }
         if (Sg.energy && Ph.eos != 0) s2 = fmax(s2, Ph.ggm1 * Pg.energy[a]);
-        bad = !store_moved<R, DIM>(G, Ph, Sg, Pg, a, vn, s2);
+        bad = !store_moved<R, DIM>(G, Ph, Pg, a, cell, id, me, rho_a, vn, s2, Sg.has_mass);
     }
     publish_speed(Ph, F, s2);
     if (bad) atomicOr(F.word, 1u);
@@ -245,8 +248,9 @@ k_pair_dust(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, const R4<R> *__re
     R s2 = signal_floor(Ph);
     int bad = 0, lonely = 0;
     if (j < Sd.n) {
+        const int cell = Sd.cell[j], id = Sd.id[j];
         int cx, cy, cz;
-        split_cell(G, Sd.cell[j], cx, cy, cz);
+        split_cell(G, cell, cx, cy, cz);
         const R4<R> me = Sd.pos[j];
         const R oj[3] = {me.x, me.y, me.z};
         const R uj[3] = {Sd.vel[0][j], DIM > 1 ? Sd.vel[1][j] : R(0), DIM > 2 ? Sd.vel[2][j] : R(0)};
@@ -321,7 +325,7 @@ k_pair_dust(Geom<R> G, Phys<R> Ph, Sorted<R> Sg, Sorted<R> Sd, const R4<R> *__re
                 un[d] = (beta * vt + (R(1) + alpha) * ut) / D;
             }
         }
-        bad = !store_moved<R, DIM>(G, Ph, Sd, Pd, j, un, s2);
+        bad = !store_moved<R, DIM>(G, Ph, Pd, j, cell, id, me, rho_j, un, s2, Sd.has_mass);
     }
     publish_speed(Ph, F, s2);
     if (bad) atomicOr(F.word, 1u);
